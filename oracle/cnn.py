@@ -1,0 +1,104 @@
+"""Residual CNN denoiser D_W(x) = x + N(x) of the MoDL subsection, in FP64.
+
+N is a stack of 3x3 convolution layers with bias; ReLU after every layer but
+the last.  The complex image enters as two real channels (channel 0 = real
+part, channel 1 = imaginary part) and leaves the same way.
+
+Readings of points the paper leaves open (its MoDL uses batch normalisation
+and F = 64 real filters; the configuration built here has no batch norm):
+
+* convolution = cross-correlation with zero "same" padding,
+  out[b,h,w,o] = bias[o] + sum_{dy,dx in {-1,0,1}} sum_i in[b,h+dy,w+dx,i] W[o,i,dy+1,dx+1];
+* weights W [C_out, C_in, 3, 3], biases [C_out]; activations [B, H, W, C];
+* the last layer is linear; the residual is added in the complex domain.
+
+Gradients follow the DF^H(1) convention of the paper's complex-numbers
+paragraph: for a complex quantity the returned gradient is dL/dRe + i dL/dIm.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def conv3x3(a, Wt, bias):
+    """Same-padded 3x3 cross-correlation. a [B,H,W,Ci], Wt [Co,Ci,3,3]."""
+    a = np.asarray(a, dtype=np.float64)
+    Wt = np.asarray(Wt, dtype=np.float64)
+    B, H, W, _ = a.shape
+    ap = np.pad(a, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    out = np.zeros((B, H, W, Wt.shape[0]))
+    for dy in range(3):
+        for dx in range(3):
+            out += ap[:, dy:dy + H, dx:dx + W, :] @ Wt[:, :, dy, dx].T
+    return out + np.asarray(bias, dtype=np.float64)
+
+
+def conv3x3_backward(a, Wt, g):
+    """Gradients of ``conv3x3`` w.r.t. its input, weights and bias given the
+    output gradient g [B,H,W,Co]."""
+    a = np.asarray(a, dtype=np.float64)
+    Wt = np.asarray(Wt, dtype=np.float64)
+    B, H, W, _ = a.shape
+    ap = np.pad(a, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    gp = np.pad(g, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    ga = np.zeros_like(a)
+    gW = np.zeros_like(Wt)
+    for dy in range(3):
+        for dx in range(3):
+            # out[p] uses in[p + d]  =>  g_in[q] += g[q - d] W_d
+            ga += gp[:, 2 - dy:2 - dy + H, 2 - dx:2 - dx + W, :] @ Wt[:, :, dy, dx]
+            gW[:, :, dy, dx] = np.einsum(
+                "bhwo,bhwi->oi", g, ap[:, dy:dy + H, dx:dx + W, :])
+    gb = g.sum(axis=(0, 1, 2))
+    return ga, gW, gb
+
+
+def to_channels(x):
+    x = np.asarray(x, dtype=np.complex128)
+    return np.stack([x.real, x.imag], axis=-1)
+
+
+def from_channels(a):
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def net_forward(x, weights, keep=False):
+    """N(x) for complex x [B,H,W]; weights = [(W, b), ...].
+    With keep=True also returns the per-layer inputs and pre-activations."""
+    a = to_channels(x)
+    acts, pres = [], []
+    L = len(weights)
+    for l, (Wt, b) in enumerate(weights):
+        acts.append(a)
+        pre = conv3x3(a, Wt, b)
+        pres.append(pre)
+        a = np.maximum(pre, 0.0) if l < L - 1 else pre
+    out = from_channels(a)
+    return (out, acts, pres) if keep else out
+
+
+def denoise(x, weights):
+    """D_W(x) = x + N(x)."""
+    return np.asarray(x, dtype=np.complex128) + net_forward(x, weights)
+
+
+def denoise_backward(x, weights, g):
+    """Reverse mode of D_W at x with upstream gradient g (complex [B,H,W]).
+    Returns (g_x complex, [(gW, gb), ...])."""
+    _, acts, pres = net_forward(x, weights, keep=True)
+    L = len(weights)
+    ga = to_channels(g)
+    grads = [None] * L
+    for l in range(L - 1, -1, -1):
+        if l < L - 1:
+            ga = ga * (pres[l] > 0)
+        gin, gW, gb = conv3x3_backward(acts[l], weights[l][0], ga)
+        grads[l] = (gW, gb)
+        ga = gin
+    return np.asarray(g, dtype=np.complex128) + from_channels(ga), grads
+
+
+def n_params(channels, k=3):
+    """Weights plus biases of a plain conv stack."""
+    return sum(channels[i] * channels[i + 1] * k * k + channels[i + 1]
+               for i in range(len(channels) - 1))

@@ -1,0 +1,188 @@
+"""Seeded generators for phantoms, coil maps, phase-encode masks, noise, weights.
+
+Recipe (stand-in for the knee and brain datasets of the paper's Results
+section, which are not available here):
+
+* Phantom: on normalised coordinates u (readout, along W) and v (phase
+  encode, along H), both in [-1, 1), a sum of K ~ U{8..14} filled ellipses with
+  centre ~ U(-0.6, 0.6)^2, semi-axes ~ U(0.05, 0.45), angle ~ U(0, pi) and
+  amplitude ~ U(0.1, 1); the magnitude is divided by its maximum so it lies in
+  [0, 1].  A smooth quadratic phase c0 + c1 u + c2 v + c3 u^2 + c4 v^2 + c5 u v
+  with c ~ U(-pi/4, pi/4) is applied.
+* Coils: C Gaussian profiles (width 0.7) centred on a circle of radius 1.3 at
+  angle 2 pi c / C + U(-0.1, 0.1), with a linear phase ramp, normalised so that
+  sum_c |S_c|^2 = 1 at every pixel.
+* Masks: phase-encode lines (rows).  floor(H / R) lines in total including a
+  fully sampled centre block; the rest drawn without replacement either
+  uniformly or with variable density p ~ (1 - |k - H/2| / (H/2))^2 + 1e-3; or
+  the regular pattern (every R-th line plus a centre block).
+* Noise: sigma * (N(0,1) + i N(0,1)) per k-space sample, sigma = 1e-3 (the
+  paper's training-data recipe, Results section).
+
+Everything is drawn in float64 with ``numpy.random.default_rng(seed)`` and
+rounded once to complex64 / float32.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Seed conventions: config k test inputs use 1000*k + slice index; training
+# phantoms, held-out evaluation phantoms and weights have their own ranges.
+SEEDS = {
+    "train_base": 100000,
+    "train_count": 2000,
+    "eval_base": 200000,
+    "eval_count": 64,
+    "weights": 7,
+}
+
+
+def _grid(H: int, W: int):
+    v = -1.0 + 2.0 * np.arange(H, dtype=np.float64) / H
+    u = -1.0 + 2.0 * np.arange(W, dtype=np.float64) / W
+    return np.meshgrid(v, u, indexing="ij")  # (V, U), each [H, W]
+
+
+def phantom(seed: int, H: int, W: int) -> np.ndarray:
+    """Random-ellipse complex phantom, magnitude in [0, 1]; complex64 [H, W]."""
+    rng = np.random.default_rng(seed)
+    V, U = _grid(H, W)
+    K = int(rng.integers(8, 15))
+    mag = np.zeros((H, W), dtype=np.float64)
+    for _ in range(K):
+        cu, cv = rng.uniform(-0.6, 0.6, size=2)
+        a, b = rng.uniform(0.05, 0.45, size=2)
+        th = rng.uniform(0.0, math.pi)
+        amp = rng.uniform(0.1, 1.0)
+        du, dv = U - cu, V - cv
+        ru = du * math.cos(th) + dv * math.sin(th)
+        rv = -du * math.sin(th) + dv * math.cos(th)
+        mag += amp * (((ru / a) ** 2 + (rv / b) ** 2) <= 1.0)
+    mx = mag.max()
+    if mx > 0:
+        mag /= mx
+    c = rng.uniform(-math.pi / 4, math.pi / 4, size=6)
+    phi = c[0] + c[1] * U + c[2] * V + c[3] * U * U + c[4] * V * V + c[5] * U * V
+    return (mag * np.exp(1j * phi)).astype(np.complex64)
+
+
+def coil_maps(seed: int, C: int, H: int, W: int) -> np.ndarray:
+    """C Gaussian coil profiles with sum_c |S_c|^2 = 1; complex64 [C, H, W]."""
+    rng = np.random.default_rng(seed)
+    V, U = _grid(H, W)
+    S = np.empty((C, H, W), dtype=np.complex128)
+    for c in range(C):
+        th = 2 * math.pi * c / C + rng.uniform(-0.1, 0.1)
+        cu, cv = 1.3 * math.cos(th), 1.3 * math.sin(th)
+        prof = np.exp(-((U - cu) ** 2 + (V - cv) ** 2) / (2 * 0.7 ** 2))
+        ph = 2 * math.pi * c / C + 0.3 * (U * math.cos(th) + V * math.sin(th))
+        S[c] = prof * np.exp(1j * ph)
+    S /= np.sqrt(np.sum(np.abs(S) ** 2, axis=0, keepdims=True))
+    return S.astype(np.complex64)
+
+
+def pe_mask(seed: int, H: int, R: int, n_center: int, kind: str = "vd") -> np.ndarray:
+    """Phase-encode line mask, float32 [H] with values in {0, 1}.
+
+    kind = "uniform": centre block plus uniform random lines;
+    kind = "vd": centre block plus variable-density random lines;
+    kind = "regular": every R-th line plus the centre block.
+    """
+    m = np.zeros(H, dtype=np.float32)
+    c0 = H // 2 - n_center // 2
+    m[c0:c0 + n_center] = 1.0
+    if kind == "regular":
+        m[::R] = 1.0
+        return m
+    rng = np.random.default_rng(seed)
+    n_tot = H // R
+    n_rest = max(0, n_tot - int(m.sum()))
+    cand = np.flatnonzero(m == 0)
+    if kind == "uniform":
+        p = np.ones(cand.size, dtype=np.float64)
+    elif kind == "vd":
+        p = (1.0 - np.abs(cand - H / 2) / (H / 2)) ** 2 + 1e-3
+    else:
+        raise ValueError(kind)
+    p = p / p.sum()
+    pick = rng.choice(cand, size=min(n_rest, cand.size), replace=False, p=p)
+    m[pick] = 1.0
+    return m
+
+
+def kspace_noise(seed: int, C: int, H: int, W: int, sigma: float = 1e-3) -> np.ndarray:
+    """Complex Gaussian noise, sigma per real component; complex64 [C, H, W]."""
+    rng = np.random.default_rng(seed)
+    n = rng.standard_normal((C, H, W, 2))
+    return (sigma * (n[..., 0] + 1j * n[..., 1])).astype(np.complex64)
+
+
+CNN_CHANNELS = (2, 64, 64, 64, 64, 2)
+
+
+def cnn_weights(seed: int = 7, channels=CNN_CHANNELS, last_scale: float = 1.0):
+    """He-normal 3x3 conv weights N(0, 2/(9 C_in)), zero biases.
+
+    Returns a list of (W [C_out, C_in, 3, 3] float32, b [C_out] float32).
+    ``last_scale`` multiplies the last layer (1.0 = plain He init).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    L = len(channels) - 1
+    for l in range(L):
+        ci, co = channels[l], channels[l + 1]
+        std = math.sqrt(2.0 / (9 * ci))
+        Wt = rng.standard_normal((co, ci, 3, 3)) * std
+        if l == L - 1:
+            Wt = Wt * last_scale
+        out.append((Wt.astype(np.float32), np.zeros(co, dtype=np.float32)))
+    return out
+
+
+def vn_params(seed: int, n_stages: int = 10, n_filters: int = 24, ksize: int = 11,
+              n_rbf: int = 31, lam0: float = 0.1):
+    """Initial variational-network parameters for ``n_stages`` stages.
+
+    Filters: complex, real and imaginary parts N(0, 0.01) (std 0.1) with the
+    per-filter mean removed.  RBF weights w_ij = 0.1 * mu_j / sqrt(2 pi), which
+    makes the activation close to 0.1 * s on [-1, 1] when the Gaussian width
+    equals the knot spacing.  Step sizes lambda_t = lam0.
+    Returns dict of float32 / complex64 arrays:
+      k [T, N_k, ks, ks] complex64, w [T, N_k, N_w] float32, lam [T] float32.
+    """
+    rng = np.random.default_rng(seed)
+    k = (rng.standard_normal((n_stages, n_filters, ksize, ksize))
+         + 1j * rng.standard_normal((n_stages, n_filters, ksize, ksize))) * 0.1
+    k -= k.mean(axis=(2, 3), keepdims=True)
+    mu = -1.0 + 2.0 * np.arange(n_rbf) / (n_rbf - 1)
+    w = np.broadcast_to(0.1 * mu / math.sqrt(2 * math.pi), (n_stages, n_filters, n_rbf))
+    return {
+        "k": k.astype(np.complex64),
+        "w": np.ascontiguousarray(w).astype(np.float32),
+        "lam": np.full(n_stages, lam0, dtype=np.float32),
+    }
+
+
+def slice_inputs(seed: int, H: int, W: int, C: int, R: int, n_center: int,
+                 mask_kind: str = "vd", sigma: float = 1e-3):
+    """One slice: phantom x [H,W], coils S [C,H,W], mask m [H], noise n [C,H,W].
+
+    The four draws use seeds derived from ``seed`` so that each is reproducible
+    on its own.
+    """
+    return {
+        "x": phantom(seed, H, W),
+        "S": coil_maps(seed + 7919, C, H, W),
+        "mask": pe_mask(seed + 15485863, H, R, n_center, mask_kind),
+        "noise": kspace_noise(seed + 32452843, C, H, W, sigma),
+    }
+
+
+def batch_inputs(seeds, H: int, W: int, C: int, R: int, n_center: int,
+                 mask_kind: str = "vd", sigma: float = 1e-3):
+    """Stack ``slice_inputs`` over ``seeds``: x [B,H,W], S [B,C,H,W], mask [B,H],
+    noise [B,C,H,W]."""
+    sl = [slice_inputs(s, H, W, C, R, n_center, mask_kind, sigma) for s in seeds]
+    return {k: np.stack([d[k] for d in sl]) for k in sl[0]}
