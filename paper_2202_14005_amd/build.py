@@ -1,0 +1,112 @@
+"""Build libmrx.so (HIP, gfx950) in-tree.
+
+    python -m paper_2202_14005_amd.build [-j JOBS]
+
+Every source under csrc/ is compiled with hipcc for gfx950 only; the transform
+schedule unit (sense_inst.hip) is compiled once per entry of SCHEDULES with
+the schedule's parameters as macros, so each length has its kernels
+instantiated in a separate object (parallel build, small objects).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libmrx.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# name, N1, N2, N3, threads per transform, column tile width, row tile height
+# (the first schedule listed for a length is its default)
+SCHEDULES = [
+    ("n16_4x4_t4", 4, 4, 1, 4, 16, 16),
+    ("n24_4x6_t2", 4, 6, 1, 2, 32, 32),
+    ("n32_4x8_t4", 4, 8, 1, 4, 16, 16),
+    ("n40_4x10_t2", 4, 10, 1, 2, 32, 32),
+    ("n48_4x12_t4", 4, 12, 1, 4, 16, 16),
+    ("n64_8x8_t8", 8, 8, 1, 8, 16, 16),
+    ("n80_4x4x5_t4", 4, 4, 5, 4, 16, 16),
+    ("n96_4x4x6_t8", 4, 4, 6, 8, 16, 16),
+    ("n128_4x4x8_t16", 4, 4, 8, 16, 16, 16),
+    ("n128_8x16_t8", 8, 16, 1, 8, 16, 16),
+    ("n160_4x4x10_t8", 4, 4, 10, 8, 16, 16),
+    ("n192_4x4x12_t16", 4, 4, 12, 16, 16, 16),
+    ("n192_8x24_t8", 8, 24, 1, 8, 16, 16),
+    ("n256_4x4x16_t16", 4, 4, 16, 16, 16, 16),
+    ("n256_16x16_t16", 16, 16, 1, 16, 16, 16),
+    ("n320_4x4x20_t16", 4, 4, 20, 16, 16, 16),
+    ("n320_8x40_t8", 8, 40, 1, 8, 16, 16),
+    ("n384_4x4x24_t16", 4, 4, 24, 16, 16, 16),
+    ("n384_16x24_t8", 16, 24, 1, 8, 16, 16),
+    ("n512_4x8x16_t32", 4, 8, 16, 32, 8, 8),
+]
+
+COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net_stub.hip"]
+
+HIP_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # no packed FP32 instructions in generated code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-result",
+]
+
+
+def _extra_sources():
+    return [s for s in sorted(os.listdir(CSRC))
+            if s.endswith(".hip") and s not in COMMON_SOURCES and s != "sense_inst.hip"]
+
+
+def _jobs():
+    srcs = COMMON_SOURCES + _extra_sources()
+    jobs = []
+    for s in srcs:
+        jobs.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".hip", ".o")), []))
+    for name, n1, n2, n3, t, wtc, wtr in SCHEDULES:
+        defs = [f"-DMRX_N1={n1}", f"-DMRX_N2={n2}", f"-DMRX_N3={n3}", f"-DMRX_T={t}",
+                f"-DMRX_WTC={wtc}", f"-DMRX_WTR={wtr}", f'-DMRX_NAME="{name}"']
+        jobs.append((os.path.join(CSRC, "sense_inst.hip"), os.path.join(BUILD, f"sched_{name}.o"), defs))
+    return jobs
+
+
+def _compile(job):
+    src, obj, defs = job
+    cmd = [HIPCC, *HIP_FLAGS, *defs, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    errs = "\n".join(l for l in (r.stderr or "").splitlines()
+                     if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{errs}")
+    return obj
+
+
+def build(jobs: int | None = None, verbose: bool = True) -> str:
+    """Compile every HIP source for gfx950 and link libmrx.so; returns its path."""
+    if not shutil.which(HIPCC) and not os.path.exists(HIPCC):
+        raise RuntimeError("hipcc not found; set HIPCC")
+    os.makedirs(BUILD, exist_ok=True)
+    js = _jobs()
+    n = jobs or min(16, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=n) as ex:
+        objs = list(ex.map(_compile, js))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB} from {len(objs)} objects", file=sys.stderr)
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-j", "--jobs", type=int, default=None)
+    a = ap.parse_args()
+    build(a.jobs)

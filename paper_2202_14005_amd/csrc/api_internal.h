@@ -1,0 +1,73 @@
+// Internal plan structure and host-side operator implementations.
+#pragma once
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mrx.h"
+#include "cg_kernels.h"
+#include "common.h"
+#include "sense_kernels.h"
+
+namespace mrx {
+
+struct Group {
+  int H = 0, W = 0, maxC = 0;
+  std::vector<int> slices;
+  int* d_slices = nullptr;
+  const ColVariant* col = nullptr;   // transform along H (column pass)
+  const RowVariant* rowW = nullptr;  // transform along W (row pass)
+  const RowVariant* rowH = nullptr;
+};
+
+}  // namespace mrx
+
+struct mrx_plan_s {
+  int B = 0;
+  int device = 0;
+  std::vector<mrx::SliceDesc> desc;
+  std::vector<mrx::Group> groups;
+  int maxH = 0, maxW = 0, maxC = 0;
+  int64_t maxHW = 0;
+  int64_t n_image = 0, n_coil = 0, n_mask = 0;
+  int npq = 0, nrr = 0;
+  // device tables (plan owned)
+  void* d_tables = nullptr;
+  mrx::SliceDesc* d_desc = nullptr;
+  int* d_all = nullptr;
+  std::map<int, float2*> tw;
+  // borrowed workspace and its layout (byte offsets)
+  char* ws = nullptr;
+  size_t ws_given = 0, ws_bytes = 0, ws_bytes_base = 0;
+  size_t ws_tmp = 0, ws_r = 0, ws_p = 0, ws_q = 0, ws_v = 0;
+  size_t ws_pq = 0, ws_rr0 = 0, ws_rr1 = 0, ws_part = 0, ws_stop = 0, ws_status = 0;
+  // network workspace (set by extra_workspace_bytes)
+  size_t ws_net = 0;
+};
+
+namespace mrx {
+
+mrx_status fail(mrx_status st, const std::string& msg);
+mrx_status hip_fail(hipError_t e, const char* what);
+const ColVariant* find_col(int N, const char* name);
+const RowVariant* find_row(int N);
+std::vector<const ColVariant*> col_variants(int N);
+
+extern std::mutex g_tune_mu;
+extern std::map<std::tuple<int, int, int>, std::string> g_tune_cache;
+
+size_t extra_workspace_bytes(mrx_plan_s* p);
+CgElemArgs elem_args(mrx_plan_s* p, const float* lam);
+hipError_t clear_status(mrx_plan_s* p, hipStream_t s);
+hipError_t fill_u32(uint32_t* dst, uint32_t value, int64_t n, hipStream_t s);
+
+mrx_status sense_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const float* mask, float2* x,
+                          hipStream_t s);
+mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
+                       float2* out, hipStream_t s);
+mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,
+                   const float* lam, int n_iter, float2* x, float* hist, hipStream_t s);
+
+}  // namespace mrx

@@ -1,0 +1,50 @@
+// Project-written schedule autotuner: times every registered column schedule
+// of each distinct (H, W, C) group of a plan on the normal operator and keeps
+// the fastest, in the plan and in an in-process cache.
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "api_internal.h"
+
+using namespace mrx;
+
+extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float* mask, float* a, float* b,
+                                        void* stream) {
+  if (!p) return fail(MRX_EINVAL, "autotune: null plan");
+  if (!S || !mask || !a || !b) return fail(MRX_EINVAL, "autotune: null data pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(MRX_EHIP, "autotune: event create");
+  for (auto& g : p->groups) {
+    const ColVariant* best = g.col;
+    float best_ms = 1e30f;
+    for (const ColVariant* v : col_variants(g.H)) {
+      NormalArgs na{};
+      na.desc = p->d_desc;
+      na.slices = g.d_slices;
+      na.nslices = (int)g.slices.size();
+      na.S = (const float2*)S;
+      na.mask = mask;
+      na.pin = (const float2*)a;
+      na.qout = (float2*)b;
+      na.tw = p->tw.at(g.H);
+      if (v->normal(na, g.W, s) != hipSuccess) continue;  // warm-up
+      hipEventRecord(e0, s);
+      for (int it = 0; it < 5; ++it) v->normal(na, g.W, s);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) { best_ms = ms; best = v; }
+    }
+    g.col = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[{g.H, g.W, g.maxC}] = best->name;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return hipGetLastError() == hipSuccess ? MRX_OK : fail(MRX_EHIP, "autotune: launch failed");
+}

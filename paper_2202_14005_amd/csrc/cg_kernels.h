@@ -1,0 +1,43 @@
+// Conjugate-gradient elementwise kernels (declarations).
+#pragma once
+#include "common.h"
+
+namespace mrx {
+
+constexpr int CG_THREADS = 256;
+constexpr int CG_EPB = 2048;  // elements per block and slice
+
+// per-slice status bits (same values as the public MRX_FLAG_* macros)
+constexpr uint32_t FLAG_NONFINITE = 1u;
+constexpr uint32_t FLAG_CG_BREAKDOWN = 2u;
+constexpr uint32_t FLAG_CNN_NONFINITE = 4u;
+constexpr uint32_t FLAG_DC_JUDGE = 8u;
+
+struct CgElemArgs {
+  const SliceDesc* desc;
+  const int* slices;
+  int nslices;
+  int nrr;               // blocks per slice (= partial count of rr buffers)
+  int npq;               // partial count of the <p, q> buffer
+  const float* lam;
+  const float2* aHy;     // init: right-hand side part; bwd tail: forward x
+  const float2* z;
+  float2* x;             // bwd tail: the adjoint solution v
+  float2* r;
+  float2* p;
+  const float2* q;
+  const float* pq;       // [B][npq]
+  const float* rr_cur;   // [B][nrr]
+  float* rr_next;        // [B][nrr]
+  int* stopped;          // [B]
+  uint32_t* status;      // [B]
+  float* hist;
+};
+
+hipError_t cg_init(const CgElemArgs& a, hipStream_t s);
+hipError_t cg_update(const CgElemArgs& a, hipStream_t s);
+hipError_t cg_hist(const CgElemArgs& a, int k, int stride, hipStream_t s);
+hipError_t cg_bwd_tail(const CgElemArgs& a, float2* gz, float* part, hipStream_t s);
+hipError_t slice_sum(const CgElemArgs& a, const float* part, float* out, int accumulate, hipStream_t s);
+
+}  // namespace mrx

@@ -1,0 +1,172 @@
+// Conjugate-gradient vector kernels with per-slice device scalars and
+// deterministic fixed-order reductions (CG as used for the MoDL inversion
+// S_lambda^{-1}, MoDL subsection).
+//
+// Each slice's vectors are split into blocks of EPB elements; a block writes
+// one partial sum per reduction and every consumer re-sums the partials of a
+// slice in the same fixed order, so results are bitwise reproducible and no
+// float atomics are used.
+#include "cg_kernels.h"
+
+namespace mrx {
+
+__device__ __forceinline__ float bsum(float v, float* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < CG_THREADS / 64; ++i) s += red[i];
+  return s;
+}
+
+__device__ __forceinline__ float psum(const float* a, int n) {
+  // fixed-order sum by every thread of the block (n is small)
+  __shared__ float tmp[CG_THREADS];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < n; i += CG_THREADS) s += a[i];
+  __syncthreads();
+  tmp[threadIdx.x] = s;
+  __syncthreads();
+  float t = 0.f;
+  const int m = n < CG_THREADS ? n : CG_THREADS;
+  for (int i = 0; i < m; ++i) t += tmp[i];
+  __syncthreads();
+  return t;
+}
+
+// r = aHy + lambda z, p = r, x = 0; partials of <r, r>.
+__global__ void __launch_bounds__(CG_THREADS) k_cg_init(CgElemArgs a) {
+  __shared__ float red[CG_THREADS / 64];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  const int64_t n = (int64_t)d.H * d.W;
+  const float lam = a.lam ? a.lam[b] : 0.f;
+  float rr = 0.f;
+  const int64_t base = (int64_t)blockIdx.x * CG_EPB;
+  for (int k = threadIdx.x; k < CG_EPB; k += CG_THREADS) {
+    const int64_t i = base + k;
+    if (i >= n) break;
+    const int64_t o = d.xoff + i;
+    float2 r = a.aHy[o];
+    if (a.z) { const float2 z = a.z[o]; r.x += lam * z.x; r.y += lam * z.y; }
+    a.r[o] = r;
+    a.p[o] = r;
+    a.x[o] = make_float2(0.f, 0.f);
+    rr += r.x * r.x + r.y * r.y;
+  }
+  const float s = bsum(rr, red);
+  if (threadIdx.x == 0) {
+    a.rr_next[(int64_t)b * a.nrr + blockIdx.x] = s;
+    if (blockIdx.x == 0) { a.stopped[b] = 0; }
+  }
+}
+
+// alpha = rho / Re<p, q>; x += alpha p; r -= alpha q; partials of <r, r>.
+__global__ void __launch_bounds__(CG_THREADS) k_cg_update(CgElemArgs a) {
+  __shared__ float red[CG_THREADS / 64];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  const int64_t n = (int64_t)d.H * d.W;
+  const float rho = psum(a.rr_cur + (int64_t)b * a.nrr, a.nrr);
+  const float pq = psum(a.pq + (int64_t)b * a.npq, a.npq);
+  bool stop = a.stopped[b] != 0;
+  const bool bad = !(pq > 0.f) || !(rho > 0.f) || !isfinite(rho / pq);
+  if (!stop && bad) {
+    stop = true;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.stopped[b] = 1;
+      uint32_t f = 0;
+      if (!isfinite(pq) || !isfinite(rho)) f |= FLAG_NONFINITE;
+      else if (rho > 0.f) f |= FLAG_CG_BREAKDOWN;
+      if (f) a.status[b] |= f;
+    }
+  }
+  const float alpha = stop ? 0.f : rho / pq;
+  float rr = 0.f;
+  const int64_t base = (int64_t)blockIdx.x * CG_EPB;
+  for (int k = threadIdx.x; k < CG_EPB; k += CG_THREADS) {
+    const int64_t i = base + k;
+    if (i >= n) break;
+    const int64_t o = d.xoff + i;
+    float2 r = a.r[o];
+    if (!stop) {
+      const float2 p = a.p[o], q = a.q[o];
+      float2 x = a.x[o];
+      x.x += alpha * p.x; x.y += alpha * p.y;
+      r.x -= alpha * q.x; r.y -= alpha * q.y;
+      a.x[o] = x;
+      a.r[o] = r;
+    }
+    rr += r.x * r.x + r.y * r.y;
+  }
+  const float s = bsum(rr, red);
+  if (threadIdx.x == 0) a.rr_next[(int64_t)b * a.nrr + blockIdx.x] = s;
+}
+
+// hist[b][k] = rho_k (sum of the current partials).
+__global__ void __launch_bounds__(CG_THREADS) k_cg_hist(CgElemArgs a, int k, int stride) {
+  const int b = a.slices[blockIdx.y];
+  const float rho = psum(a.rr_cur + (int64_t)b * a.nrr, a.nrr);
+  if (threadIdx.x == 0) a.hist[(int64_t)b * stride + k] = rho;
+}
+
+// Backward helpers: g_z = lambda v; partials of Re<v, z - x>.
+__global__ void __launch_bounds__(CG_THREADS) k_cg_bwd_tail(CgElemArgs a, float2* gz, float* part) {
+  __shared__ float red[CG_THREADS / 64];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  const int64_t n = (int64_t)d.H * d.W;
+  const float lam = a.lam ? a.lam[b] : 0.f;
+  float acc = 0.f;
+  const int64_t base = (int64_t)blockIdx.x * CG_EPB;
+  for (int k = threadIdx.x; k < CG_EPB; k += CG_THREADS) {
+    const int64_t i = base + k;
+    if (i >= n) break;
+    const int64_t o = d.xoff + i;
+    const float2 v = a.x[o];
+    if (gz) gz[o] = make_float2(lam * v.x, lam * v.y);
+    if (part) {
+      float2 zx = a.z ? a.z[o] : make_float2(0.f, 0.f);
+      const float2 xf = a.aHy[o];  // forward solution
+      zx.x -= xf.x; zx.y -= xf.y;
+      acc += v.x * zx.x + v.y * zx.y;
+    }
+  }
+  if (part) {
+    const float s = bsum(acc, red);
+    if (threadIdx.x == 0) part[(int64_t)b * a.nrr + blockIdx.x] = s;
+  }
+}
+
+__global__ void __launch_bounds__(CG_THREADS) k_slice_sum(CgElemArgs a, const float* part, float* out, int accumulate) {
+  const int b = a.slices[blockIdx.y];
+  const float s = psum(part + (int64_t)b * a.nrr, a.nrr);
+  if (threadIdx.x == 0) out[b] = accumulate ? out[b] + s : s;
+}
+
+hipError_t cg_init(const CgElemArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, dim3(a.nrr, a.nslices), dim3(CG_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t cg_update(const CgElemArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, dim3(a.nrr, a.nslices), dim3(CG_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t cg_hist(const CgElemArgs& a, int k, int stride, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_hist, dim3(1, a.nslices), dim3(CG_THREADS), 0, s, a, k, stride);
+  return hipGetLastError();
+}
+hipError_t cg_bwd_tail(const CgElemArgs& a, float2* gz, float* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_bwd_tail, dim3(a.nrr, a.nslices), dim3(CG_THREADS), 0, s, a, gz, part);
+  return hipGetLastError();
+}
+hipError_t slice_sum(const CgElemArgs& a, const float* part, float* out, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_slice_sum, dim3(1, a.nslices), dim3(CG_THREADS), 0, s, a, part, out, accumulate);
+  return hipGetLastError();
+}
+
+}  // namespace mrx

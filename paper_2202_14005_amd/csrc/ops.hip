@@ -1,0 +1,140 @@
+// Host-side sequencing of the SENSE and CG operators on the device.
+#include <chrono>
+#include <mutex>
+
+#include "api_internal.h"
+
+namespace mrx {
+
+__global__ void k_fill_u32(uint32_t* d, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = v;
+}
+
+hipError_t fill_u32(uint32_t* dst, uint32_t value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, dst, value, n);
+  return hipGetLastError();
+}
+
+hipError_t clear_status(mrx_plan_s* p, hipStream_t s) {
+  return fill_u32((uint32_t*)(p->ws + p->ws_status), 0u, p->B, s);
+}
+
+CgElemArgs elem_args(mrx_plan_s* p, const float* lam) {
+  CgElemArgs a{};
+  a.desc = p->d_desc;
+  a.slices = p->d_all;
+  a.nslices = p->B;
+  a.nrr = p->nrr;
+  a.npq = p->npq;
+  a.lam = lam;
+  a.stopped = (int*)(p->ws + p->ws_stop);
+  a.status = (uint32_t*)(p->ws + p->ws_status);
+  return a;
+}
+
+mrx_status sense_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const float* mask, float2* x,
+                          hipStream_t s) {
+  float2* tmp = (float2*)(p->ws + p->ws_tmp);
+  for (auto& g : p->groups) {
+    SenseRowArgs ra{p->d_desc, g.d_slices, (int)g.slices.size(), mask, y, tmp, nullptr, p->tw.at(g.W)};
+    hipError_t e = g.rowW->adj_row(ra, g.H, g.maxC, s);
+    if (e != hipSuccess) return hip_fail(e, "sense_adj: row pass");
+    SenseColArgs ca{p->d_desc, g.d_slices, (int)g.slices.size(), S, mask, tmp, x, p->tw.at(g.H)};
+    e = g.col->adj_col(ca, g.W, s);
+    if (e != hipSuccess) return hip_fail(e, "sense_adj: column pass");
+  }
+  return MRX_OK;
+}
+
+mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
+                       float2* out, hipStream_t s) {
+  for (auto& g : p->groups) {
+    NormalArgs na{};
+    na.desc = p->d_desc;
+    na.slices = g.d_slices;
+    na.nslices = (int)g.slices.size();
+    na.S = S;
+    na.mask = mask;
+    na.lam = lam;
+    na.pin = x;
+    na.qout = out;
+    na.tw = p->tw.at(g.H);
+    na.mode = 0;
+    hipError_t e = g.col->normal(na, g.W, s);
+    if (e != hipSuccess) return hip_fail(e, "sense_normal");
+  }
+  return MRX_OK;
+}
+
+// x = CG_n(A^H A + lam I, aHy + lam z) from x0 = 0.
+mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,
+                   const float* lam, int n_iter, float2* x, float* hist, hipStream_t s) {
+  float2* r = (float2*)(p->ws + p->ws_r);
+  float2* pv = (float2*)(p->ws + p->ws_p);
+  float2* q = (float2*)(p->ws + p->ws_q);
+  float* pq = (float*)(p->ws + p->ws_pq);
+  float* rr[2] = {(float*)(p->ws + p->ws_rr0), (float*)(p->ws + p->ws_rr1)};
+  CgElemArgs a = elem_args(p, lam);
+  a.aHy = aHy;
+  a.z = z;
+  a.x = x;
+  a.r = r;
+  a.p = pv;
+  a.q = q;
+  a.pq = pq;
+  a.hist = hist;
+  a.rr_next = rr[0];
+  // tiles that a schedule never writes must read as zero partials
+  hipError_t e = fill_u32((uint32_t*)pq, 0u, (int64_t)p->B * p->npq, s);
+  if (e != hipSuccess) return hip_fail(e, "cg: clear partials");
+  e = cg_init(a, s);
+  if (e != hipSuccess) return hip_fail(e, "cg: init");
+  for (int k = 0; k < n_iter; ++k) {
+    float* rr_cur = rr[k & 1];
+    float* rr_prev = rr[(k + 1) & 1];
+    if (hist) {
+      a.rr_cur = rr_cur;
+      e = cg_hist(a, k, n_iter + 1, s);
+      if (e != hipSuccess) return hip_fail(e, "cg: history");
+    }
+    for (auto& g : p->groups) {
+      NormalArgs na{};
+      na.desc = p->d_desc;
+      na.slices = g.d_slices;
+      na.nslices = (int)g.slices.size();
+      na.S = S;
+      na.mask = mask;
+      na.lam = lam;
+      na.pin = pv;
+      na.qout = q;
+      na.tw = p->tw.at(g.H);
+      na.mode = 1;
+      na.iter = k;
+      na.r = r;
+      na.pout = pv;
+      na.rr_cur = rr_cur;
+      na.rr_prev = rr_prev;
+      na.nrr = p->nrr;
+      na.pq_part = pq;
+      na.npq = p->npq;
+      na.stopped = a.stopped;
+      e = g.col->normal(na, g.W, s);
+      if (e != hipSuccess) return hip_fail(e, "cg: normal operator");
+    }
+    a.rr_cur = rr_cur;
+    a.rr_next = rr_prev;  // rho_{k+1} overwrites rho_{k-1}
+    e = cg_update(a, s);
+    if (e != hipSuccess) return hip_fail(e, "cg: update");
+  }
+  if (hist) {
+    a.rr_cur = rr[n_iter & 1];
+    e = cg_hist(a, n_iter, n_iter + 1, s);
+    if (e != hipSuccess) return hip_fail(e, "cg: history");
+  }
+  return MRX_OK;
+}
+
+}  // namespace mrx

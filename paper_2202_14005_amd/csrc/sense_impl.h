@@ -1,0 +1,398 @@
+// Kernel templates for the SENSE column and row passes.  Included by the
+// per-length instantiation units only.
+#pragma once
+#include "fft.h"
+#include "sense_kernels.h"
+
+namespace mrx {
+
+// Deterministic fixed-order sum of n floats by one wavefront: lane l adds
+// elements l, l+64, ... in order, then a fixed butterfly over lanes.
+__device__ __forceinline__ float wave_sum_fixed(const float* a, int n, int lane) {
+  float s = 0.f;
+  for (int i = lane; i < n; i += 64) s += a[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+// Block-wide fixed-order reduction of one float per thread (blockDim <= 1024).
+// Returns the sum to every thread.  red must hold blockDim/64 floats.
+__device__ __forceinline__ float block_sum_fixed(float v, float* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  float s = 0.f;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// --------------------------------------------------------- normal operator
+// One workgroup = WT adjacent columns of one slice, T threads per column.
+// q = sum_c conj(S_c) F_H^H diag(m') F_H (S_c p) + lambda p, one HBM read of
+// every coil map per application.
+template <class Sd, int WT>
+__global__ void __launch_bounds__(Sd::T * WT)
+k_normal(NormalArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  using L = LdsInterleaved<N, WT>;
+  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 tw[N];
+  __shared__ float mk[N];
+  __shared__ float red[(T * WT + 63) / 64];
+  __shared__ float sc[2];
+
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  if (d.H != N) return;
+  const int W = d.W;
+  const int tile = blockIdx.x;
+  if (tile * WT >= W) return;
+  const int lid = threadIdx.x;
+  const int c = lid % WT, tc = lid / WT;
+  const int col = tile * WT + c;
+  const bool valid = col < W;
+  const bool cg = a.mode == 1;
+  if (cg && a.stopped[b]) return;
+
+  for (int i = lid; i < N; i += T * WT) {
+    tw[i] = a.tw[i];
+    mk[i] = a.mask[d.moff + (i + N / 2) % N] * (1.0f / N);
+  }
+  if (cg && lid < 64) {
+    float beta = 0.f;
+    if (a.iter > 0) {
+      const float rc = wave_sum_fixed(a.rr_cur + (int64_t)b * a.nrr, a.nrr, lid);
+      const float rp = wave_sum_fixed(a.rr_prev + (int64_t)b * a.nrr, a.nrr, lid);
+      beta = rp > 0.f ? rc / rp : 0.f;
+    }
+    if (lid == 0) sc[0] = beta;
+  }
+  __syncthreads();
+
+  const float2* pbase = a.pin + d.xoff;
+  float2 p[P];
+  if (cg && a.iter > 0) {
+    const float beta = sc[0];
+    const float2* rbase = a.r + d.xoff;
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+        float2 pv = valid ? pbase[o] : make_float2(0.f, 0.f);
+        float2 rv = valid ? rbase[o] : make_float2(0.f, 0.f);
+        pv = make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
+        p[i * Sd::N1 + r] = pv;
+        if (valid) a.pout[d.xoff + o] = pv;
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+        p[i * Sd::N1 + r] = valid ? pbase[o] : make_float2(0.f, 0.f);
+      }
+  }
+
+  float2 acc[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) acc[k] = make_float2(0.f, 0.f);
+
+  const int64_t plane = (int64_t)N * W;
+  const float2* Sb = a.S + d.soff;
+  for (int coil = 0; coil < d.C; ++coil) {
+    const float2* Sc = Sb + coil * plane;
+    float2 s[P], v[P];
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+        s[i * Sd::N1 + r] = valid ? Sc[o] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = cmul(s[k], p[k]);
+    fft_forward<Sd, L>(v, lds, tw, tc, c);
+#pragma unroll
+    for (int i = 0; i < Sd::GFIN; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::NFIN; ++r) {
+        const float m = mk[Sd::freq(tc, i, r)];
+        v[i * Sd::NFIN + r] = cscale(v[i * Sd::NFIN + r], m);
+      }
+    fft_inverse<Sd, L>(v, lds, tw, tc, c);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const float2 t = cmulc(s[k], v[k]);
+      acc[k] = cadd(acc[k], t);
+    }
+  }
+
+  const float lam = a.lam ? a.lam[b] : 0.f;
+  float dot = 0.f;
+  float2* qbase = a.qout + d.xoff;
+#pragma unroll
+  for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::N1; ++r) {
+      const int k = i * Sd::N1 + r;
+      const float2 q = make_float2(acc[k].x + lam * p[k].x, acc[k].y + lam * p[k].y);
+      dot += p[k].x * q.x + p[k].y * q.y;
+      if (valid) qbase[(int64_t)Sd::a1(tc, i, r) * W + col] = q;
+    }
+  if (cg) {
+    const float s = block_sum_fixed(dot, red);
+    if (lid == 0) a.pq_part[(int64_t)b * a.npq + tile] = s;
+  }
+}
+
+// ----------------------------------------------- forward column pass (A, H)
+// v = S_c x, transform along H, keep sampled rows: out[c, k, :] for m[k] = 1
+// gets (-1)^j (F v)[j] / sqrt(H) with k = (j + H/2) mod H.
+template <class Sd, int WT>
+__global__ void __launch_bounds__(Sd::T * WT)
+k_fwd_col(SenseColArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  using L = LdsInterleaved<N, WT>;
+  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 tw[N];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  if (d.H != N) return;
+  const int W = d.W, tile = blockIdx.x;
+  if (tile * WT >= W) return;
+  const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
+  const bool valid = col < W;
+  for (int i = lid; i < N; i += T * WT) tw[i] = a.tw[i];
+  __syncthreads();
+  const float scale = rsqrtf((float)N);
+  float2 x[P];
+#pragma unroll
+  for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::N1; ++r)
+      x[i * Sd::N1 + r] = valid ? a.in[d.xoff + (int64_t)Sd::a1(tc, i, r) * W + col] : make_float2(0.f, 0.f);
+  const int64_t plane = (int64_t)N * W;
+  const float* mrow = a.mask + d.moff;
+  for (int coil = 0; coil < d.C; ++coil) {
+    const float2* Sc = a.S + d.soff + coil * plane;
+    float2 v[P];
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const float2 s = valid ? Sc[(int64_t)Sd::a1(tc, i, r) * W + col] : make_float2(0.f, 0.f);
+        v[i * Sd::N1 + r] = cmul(s, x[i * Sd::N1 + r]);
+      }
+    fft_forward<Sd, L>(v, lds, tw, tc, c);
+    float2* oc = a.out + d.soff + coil * plane;
+#pragma unroll
+    for (int i = 0; i < Sd::GFIN; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::NFIN; ++r) {
+        const int j = Sd::freq(tc, i, r);
+        const int k = (j + N / 2) % N;
+        const float sg = (j & 1) ? -scale : scale;
+        if (valid && mrow[k] != 0.f) oc[(int64_t)k * W + col] = cscale(v[i * Sd::NFIN + r], sg);
+      }
+  }
+}
+
+// ------------------------------------------- adjoint column pass (A^H, H)
+// For each coil: gather sampled rows of the row-pass output into frequency
+// order with the centering sign, inverse transform along H, multiply by
+// conj(S_c) and accumulate over coils.
+template <class Sd, int WT>
+__global__ void __launch_bounds__(Sd::T * WT)
+k_adj_col(SenseColArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  using L = LdsInterleaved<N, WT>;
+  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 tw[N];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  if (d.H != N) return;
+  const int W = d.W, tile = blockIdx.x;
+  if (tile * WT >= W) return;
+  const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
+  const bool valid = col < W;
+  for (int i = lid; i < N; i += T * WT) tw[i] = a.tw[i];
+  __syncthreads();
+  const float scale = rsqrtf((float)N);
+  const int64_t plane = (int64_t)N * W;
+  const float* mrow = a.mask + d.moff;
+  float2 acc[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) acc[k] = make_float2(0.f, 0.f);
+  for (int coil = 0; coil < d.C; ++coil) {
+    const float2* ic = a.in + d.soff + coil * plane;
+    float2 v[P];
+#pragma unroll
+    for (int i = 0; i < Sd::GFIN; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::NFIN; ++r) {
+        const int j = Sd::freq(tc, i, r);
+        const int k = (j + N / 2) % N;
+        const float sg = (j & 1) ? -scale : scale;
+        float2 u = make_float2(0.f, 0.f);
+        if (valid && mrow[k] != 0.f) u = cscale(ic[(int64_t)k * W + col], sg);
+        v[i * Sd::NFIN + r] = u;
+      }
+    fft_inverse<Sd, L>(v, lds, tw, tc, c);
+    const float2* Sc = a.S + d.soff + coil * plane;
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const float2 s = valid ? Sc[(int64_t)Sd::a1(tc, i, r) * W + col] : make_float2(0.f, 0.f);
+        acc[i * Sd::N1 + r] = cadd(acc[i * Sd::N1 + r], cmulc(s, v[i * Sd::N1 + r]));
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::N1; ++r)
+      if (valid) a.out[d.xoff + (int64_t)Sd::a1(tc, i, r) * W + col] = acc[i * Sd::N1 + r];
+}
+
+// ----------------------------------------------------- row passes (along W)
+// One workgroup = WT rows (of any slices' coil planes), T threads per row;
+// grid.x enumerates (slice, coil, row-block) via blockIdx.x over
+// ceil(H/WT) * C row blocks of slice blockIdx.y.
+template <class Sd, int WT>
+__global__ void __launch_bounds__(Sd::T * WT)
+k_fwd_row(SenseRowArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  using L = LdsContig<N, WT>;
+  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 tw[N];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  if (d.W != N) return;
+  const int H = d.H;
+  const int rblocks = (H + WT - 1) / WT;
+  if ((int)blockIdx.x >= rblocks * d.C) return;
+  const int coil = blockIdx.x / rblocks, rb = blockIdx.x % rblocks;
+  const int lid = threadIdx.x, tc = lid % T, c = lid / T;
+  const int row = rb * WT + c;
+  for (int i = lid; i < N; i += T * WT) tw[i] = a.tw[i];
+  __syncthreads();
+  const bool valid = row < H;
+  const bool sampled = valid && a.mask[d.moff + row] != 0.f;
+  const int64_t base = d.soff + ((int64_t)coil * H + row) * N;
+  float2 v[P];
+#pragma unroll
+  for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::N1; ++r)
+      v[i * Sd::N1 + r] = sampled ? a.in[base + Sd::a1(tc, i, r)] : make_float2(0.f, 0.f);
+  fft_forward<Sd, L>(v, lds, tw, tc, c);
+  if (!valid) return;
+  const float scale = rsqrtf((float)N);
+#pragma unroll
+  for (int i = 0; i < Sd::GFIN; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::NFIN; ++r) {
+      const int j = Sd::freq(tc, i, r);
+      const int l = (j + N / 2) % N;
+      const float sg = (j & 1) ? -scale : scale;
+      float2 y = make_float2(0.f, 0.f);
+      if (sampled) {
+        y = cscale(v[i * Sd::NFIN + r], sg);
+        if (a.noise) y = cadd(y, a.noise[base + l]);
+      }
+      a.out[base + l] = y;
+    }
+}
+
+template <class Sd, int WT>
+__global__ void __launch_bounds__(Sd::T * WT)
+k_adj_row(SenseRowArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  using L = LdsContig<N, WT>;
+  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 tw[N];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  if (d.W != N) return;
+  const int H = d.H;
+  const int rblocks = (H + WT - 1) / WT;
+  if ((int)blockIdx.x >= rblocks * d.C) return;
+  const int coil = blockIdx.x / rblocks, rb = blockIdx.x % rblocks;
+  const int lid = threadIdx.x, tc = lid % T, c = lid / T;
+  const int row = rb * WT + c;
+  for (int i = lid; i < N; i += T * WT) tw[i] = a.tw[i];
+  __syncthreads();
+  const bool valid = row < H;
+  const bool sampled = valid && a.mask[d.moff + row] != 0.f;
+  const int64_t base = d.soff + ((int64_t)coil * H + row) * N;
+  const float scale = rsqrtf((float)N);
+  float2 v[P];
+#pragma unroll
+  for (int i = 0; i < Sd::GFIN; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::NFIN; ++r) {
+      const int j = Sd::freq(tc, i, r);
+      const int l = (j + N / 2) % N;
+      const float sg = (j & 1) ? -scale : scale;
+      v[i * Sd::NFIN + r] = sampled ? cscale(a.in[base + l], sg) : make_float2(0.f, 0.f);
+    }
+  fft_inverse<Sd, L>(v, lds, tw, tc, c);
+  if (!sampled) return;
+#pragma unroll
+  for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::N1; ++r) a.out[base + Sd::a1(tc, i, r)] = v[i * Sd::N1 + r];
+}
+
+// ------------------------------------------------------------- launchers
+template <class Sd, int WT>
+hipError_t launch_normal(const NormalArgs& a, int maxW, hipStream_t s) {
+  dim3 grid((maxW + WT - 1) / WT, a.nslices);
+  hipLaunchKernelGGL((k_normal<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
+  return hipGetLastError();
+}
+template <class Sd, int WT>
+hipError_t launch_fwd_col(const SenseColArgs& a, int maxW, hipStream_t s) {
+  dim3 grid((maxW + WT - 1) / WT, a.nslices);
+  hipLaunchKernelGGL((k_fwd_col<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
+  return hipGetLastError();
+}
+template <class Sd, int WT>
+hipError_t launch_adj_col(const SenseColArgs& a, int maxW, hipStream_t s) {
+  dim3 grid((maxW + WT - 1) / WT, a.nslices);
+  hipLaunchKernelGGL((k_adj_col<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
+  return hipGetLastError();
+}
+template <class Sd, int WT>
+hipError_t launch_fwd_row(const SenseRowArgs& a, int maxH, int maxC, hipStream_t s) {
+  dim3 grid(((maxH + WT - 1) / WT) * maxC, a.nslices);
+  hipLaunchKernelGGL((k_fwd_row<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
+  return hipGetLastError();
+}
+template <class Sd, int WT>
+hipError_t launch_adj_row(const SenseRowArgs& a, int maxH, int maxC, hipStream_t s) {
+  dim3 grid(((maxH + WT - 1) / WT) * maxC, a.nslices);
+  hipLaunchKernelGGL((k_adj_row<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
+  return hipGetLastError();
+}
+
+// Registers one column schedule and one row schedule for a length.
+template <class Sd, int WTC, int WTR>
+struct Registrar {
+  Registrar(const char* name) {
+    ColVariant cv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTC,
+                  &launch_normal<Sd, WTC>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name};
+    register_col_variant(cv);
+    RowVariant rv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTR,
+                  &launch_fwd_row<Sd, WTR>, &launch_adj_row<Sd, WTR>, name};
+    register_row_variant(rv);
+  }
+};
+
+}  // namespace mrx

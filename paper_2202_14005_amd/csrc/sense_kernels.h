@@ -1,0 +1,84 @@
+// SENSE operator kernels for one FFT schedule (template), plus the argument
+// structs and the registry through which the host picks a schedule.
+//
+// The SENSE model A = P F C (coil multiply, centered unitary 2-D DFT, row
+// sampling) and its adjoint are computed in two passes (a column pass doing
+// the transform along H and a row pass doing the transform along W).  The
+// normal operator A^H A needs only the column pass: with a row mask m[h]
+// constant along W, F^H P^H P F = F_H^H diag(m) F_H because the unitary
+// W-transforms cancel, and the centering shifts reduce to evaluating the mask
+// at (j + H/2) mod H for the uncentered frequency j.
+#pragma once
+#include "common.h"
+
+namespace mrx {
+
+struct NormalArgs {
+  const SliceDesc* desc;   // all slices of the plan
+  const int* slices;       // slices handled by this launch (nslices of them)
+  int nslices;
+  const float2* S;         // packed coil maps
+  const float* mask;       // packed row masks
+  const float* lam;        // per-slice lambda (device), may be null (= 0)
+  const float2* pin;       // operand (image sized)
+  float2* qout;            // result (image sized)
+  const float2* tw;        // exp(-2 pi i j / H), j < H
+  // Fused CG step (mode 1): before the operator, p = r + beta p with
+  // beta = rho_k / rho_{k-1} summed from the rr partial buffers; p is written
+  // back to pout and the partial sums of Re<p, q> go to pq_part.
+  int mode;
+  int iter;
+  const float2* r;
+  float2* pout;
+  const float* rr_cur;     // [B][nrr] partials of rho_k
+  const float* rr_prev;    // [B][nrr] partials of rho_{k-1}
+  int nrr;
+  float* pq_part;          // [B][npq]
+  int npq;
+  const int* stopped;      // [B] per-slice stop flag (CG breakdown)
+};
+
+struct SenseColArgs {
+  const SliceDesc* desc;
+  const int* slices;
+  int nslices;
+  const float2* S;
+  const float* mask;
+  const float2* in;        // fwd: image x; adj: row-pass output (coil sized)
+  float2* out;             // fwd: coil-sized k-space rows; adj: image
+  const float2* tw;
+};
+
+struct SenseRowArgs {
+  const SliceDesc* desc;
+  const int* slices;
+  int nslices;
+  const float* mask;
+  const float2* in;        // coil sized
+  float2* out;             // coil sized (may alias in for the forward pass)
+  const float2* noise;     // optional additive noise on sampled rows (forward)
+  const float2* tw;        // exp(-2 pi i j / W), j < W
+};
+
+using NormalFn = hipError_t (*)(const NormalArgs&, int maxW, hipStream_t);
+using ColFn = hipError_t (*)(const SenseColArgs&, int maxW, hipStream_t);
+using RowFn = hipError_t (*)(const SenseRowArgs&, int maxH, int maxC, hipStream_t);
+
+struct ColVariant {
+  int N, N1, N2, N3, T, WT;
+  NormalFn normal;
+  ColFn fwd_col;
+  ColFn adj_col;
+  const char* name;
+};
+struct RowVariant {
+  int N, N1, N2, N3, T, WT;
+  RowFn fwd_row;
+  RowFn adj_row;
+  const char* name;
+};
+
+void register_col_variant(const ColVariant& v);
+void register_row_variant(const RowVariant& v);
+
+}  // namespace mrx

@@ -1,0 +1,187 @@
+"""Thin Python binding of the mrx C-ABI (argument marshalling only).
+
+Every computation runs in the HIP kernels of libmrx.so; torch supplies device
+memory, the current stream and, in ``autograd``, the tape.  Complex tensors
+are complex64 (interleaved float pairs), contiguous, on one CUDA/HIP device.
+
+Shapes for an even batch: images [B, H, W], coil data [B, C, H, W],
+masks [B, H] float32.  For uneven batches (different H, W, C per slice) pass
+flat packed 1-D tensors in the layout described in include/mrx.h.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from ._lib import check, lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """Shapes of a batch of slices plus the library's plan and workspace.
+
+    ``H``, ``W``, ``C`` are ints (even batch of ``B`` slices) or per-slice
+    sequences (uneven batch)."""
+
+    def __init__(self, H, W, C, B: int | None = None, device=None):
+        L = lib()
+        if isinstance(H, int):
+            if B is None:
+                raise ValueError("B is required for an even batch")
+            Hs, Ws, Cs = [H] * B, [W] * B, [C] * B
+        else:
+            Hs, Ws, Cs = list(H), list(W), list(C)
+        self.B = len(Hs)
+        self.H, self.W, self.C = Hs, Ws, Cs
+        self.even = len(set(zip(Hs, Ws, Cs))) == 1
+        self.device = (torch.device(device) if device is not None
+                       else torch.device("cuda", torch.cuda.current_device()))
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        arr = lambda v: (ctypes.c_int32 * len(v))(*v)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.mrx_plan_create(ctypes.byref(h), self.B, arr(Hs), arr(Ws), arr(Cs), 0), "plan_create")
+        self._h = h
+        ni, nc, nm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(L.mrx_plan_sizes(h, ctypes.byref(ni), ctypes.byref(nc), ctypes.byref(nm)), "plan_sizes")
+        self.n_image, self.n_coil, self.n_mask = ni.value, nc.value, nm.value
+        nbytes = int(L.mrx_plan_workspace_bytes(h))
+        self.workspace = torch.empty(max(nbytes, 256) + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        with torch.cuda.device(self.device):
+            check(L.mrx_plan_set_workspace(h, ctypes.c_void_p(self.workspace.data_ptr() + off), nbytes),
+                  "plan_set_workspace")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().mrx_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ------------------------------------------------------------ checking
+    def _img(self, t, name):
+        return self._chk(t, name, self.n_image, torch.complex64, (self.B, self.H[0], self.W[0]))
+
+    def _coil(self, t, name):
+        return self._chk(t, name, self.n_coil, torch.complex64, (self.B, self.C[0], self.H[0], self.W[0]))
+
+    def _mask(self, t, name):
+        return self._chk(t, name, self.n_mask, torch.float32, (self.B, self.H[0]))
+
+    def _chk(self, t, name, numel, dtype, even_shape):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if t.device != self.device and not (t.device.type == "cuda" and self.device.type == "cuda"
+                                             and t.device.index == self.device.index):
+            raise ValueError(f"{name} must be on {self.device}, got {t.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, plan needs {numel}")
+        if self.even and t.dim() > 1 and tuple(t.shape) != even_shape:
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {even_shape}")
+        return t
+
+    def lam(self, lam):
+        """Per-slice lambda as a device float32 tensor [B]."""
+        if isinstance(lam, torch.Tensor):
+            t = lam.to(device=self.device, dtype=torch.float32).reshape(-1)
+            if t.numel() == 1:
+                t = t.expand(self.B)
+            return t.contiguous()
+        if isinstance(lam, (int, float)):
+            return torch.full((self.B,), float(lam), dtype=torch.float32, device=self.device)
+        return torch.tensor(list(lam), dtype=torch.float32, device=self.device)
+
+    def _empty_img(self):
+        shape = (self.B, self.H[0], self.W[0]) if self.even else (self.n_image,)
+        return torch.empty(shape, dtype=torch.complex64, device=self.device)
+
+    def _empty_coil(self):
+        shape = (self.B, self.C[0], self.H[0], self.W[0]) if self.even else (self.n_coil,)
+        return torch.empty(shape, dtype=torch.complex64, device=self.device)
+
+    # ----------------------------------------------------------- operators
+    def sense_fwd(self, x, S, mask, noise=None, out=None):
+        """y = mask * (F(S x) + noise)."""
+        self._img(x, "x"); self._coil(S, "S"); self._mask(mask, "mask"); self._coil(noise, "noise")
+        y = self._coil(out, "out") if out is not None else self._empty_coil()
+        check(lib().mrx_sense_fwd(self._h, _ptr(x), _ptr(S), _ptr(mask), _ptr(noise), _ptr(y),
+                                  _stream(self.device)), "sense_fwd")
+        return y
+
+    def sense_adj(self, y, S, mask, out=None):
+        """x = sum_c conj(S_c) F^H(mask * y_c)."""
+        self._coil(y, "y"); self._coil(S, "S"); self._mask(mask, "mask")
+        x = self._img(out, "out") if out is not None else self._empty_img()
+        check(lib().mrx_sense_adj(self._h, _ptr(y), _ptr(S), _ptr(mask), _ptr(x), _stream(self.device)),
+              "sense_adj")
+        return x
+
+    def sense_normal(self, x, S, mask, lam=None, out=None):
+        """(A^H A + lambda I) x."""
+        self._img(x, "x"); self._coil(S, "S"); self._mask(mask, "mask")
+        lt = self.lam(lam) if lam is not None else None
+        q = self._img(out, "out") if out is not None else self._empty_img()
+        check(lib().mrx_sense_normal(self._h, _ptr(x), _ptr(S), _ptr(mask), _ptr(lt), _ptr(q),
+                                     _stream(self.device)), "sense_normal")
+        return q
+
+    def cg_dc(self, aHy, S, mask, lam, n_iter, z=None, out=None, hist=False):
+        """x = (A^H A + lambda I)^{-1}(aHy + lambda z) by n_iter CG steps from 0.
+        With hist=True also returns ||r_k||^2, float32 [B, n_iter + 1]."""
+        self._img(aHy, "aHy"); self._img(z, "z"); self._coil(S, "S"); self._mask(mask, "mask")
+        lt = self.lam(lam)
+        x = self._img(out, "out") if out is not None else self._empty_img()
+        h = torch.empty((self.B, n_iter + 1), dtype=torch.float32, device=self.device) if hist else None
+        check(lib().mrx_cg_dc(self._h, _ptr(aHy), _ptr(z), _ptr(S), _ptr(mask), _ptr(lt), int(n_iter),
+                              _ptr(x), _ptr(h), _stream(self.device)), "cg_dc")
+        return (x, h) if hist else x
+
+    def cg_dc_backward(self, gx, x, S, mask, lam, n_iter, z=None, need_z=True, need_lam=True):
+        """Returns (g_aHy, g_z or None, g_lambda [B] or None)."""
+        self._img(gx, "gx"); self._img(x, "x"); self._img(z, "z"); self._coil(S, "S"); self._mask(mask, "mask")
+        lt = self.lam(lam)
+        ga = self._empty_img()
+        gz = self._empty_img() if need_z else None
+        gl = torch.zeros(self.B, dtype=torch.float32, device=self.device) if need_lam else None
+        check(lib().mrx_cg_dc_backward(self._h, _ptr(gx), _ptr(x), _ptr(z), _ptr(S), _ptr(mask), _ptr(lt),
+                                       int(n_iter), _ptr(ga), _ptr(gz), _ptr(gl), 0,
+                                       _stream(self.device)), "cg_dc_backward")
+        return ga, gz, gl
+
+    def status(self, clear=False):
+        """Per-slice status bits (uint32 as int64 tensor on the device)."""
+        f = torch.zeros(self.B, dtype=torch.int32, device=self.device)
+        check(lib().mrx_status_word(self._h, _ptr(f), int(bool(clear)), _stream(self.device)), "status_word")
+        return f
+
+    def autotune(self, S, mask):
+        a = self._empty_img().normal_()
+        b = self._empty_img()
+        check(lib().mrx_plan_autotune(self._h, _ptr(S), _ptr(mask), _ptr(a), _ptr(b), _stream(self.device)),
+              "autotune")
+
+    def schedule(self, b=0):
+        return lib().mrx_plan_schedule(self._h, int(b)).decode()
+
+
+def supported_length(n: int) -> bool:
+    return bool(lib().mrx_supported_length(int(n)))
