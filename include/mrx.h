@@ -57,6 +57,25 @@ typedef enum {
 
 typedef struct mrx_plan_s* mrx_plan;
 
+/* mrx_plan_create flags */
+#define MRX_PLAN_NETWORK 1u /* also reserve workspace for the CNN / MoDL calls */
+
+/*
+ * Denoiser parameters: fp32 master weights of the five 3x3 convolution
+ * layers, w[l] laid out [C_out][C_in][3][3] (channels 2-64-64-64-64-2) and
+ * biases b[l] [C_out], all device pointers owned by the caller.
+ */
+typedef struct {
+  const float* w[5];
+  const float* b[5];
+} mrx_cnn_params;
+
+/* Gradient buffers with the same shapes as mrx_cnn_params (fp32, device). */
+typedef struct {
+  float* w[5];
+  float* b[5];
+} mrx_cnn_grads;
+
 /* Library version string and the last error of the calling thread. */
 const char* mrx_version(void);
 const char* mrx_last_error(void);
@@ -69,7 +88,7 @@ const char* mrx_last_error(void);
  * 1 <= C <= 64.  Creates device tables (shape table, twiddles) with hipMalloc
  * on the current device; this is the only allocating call.  Returns
  * MRX_EUNSUPPORTED for sizes without a schedule, MRX_EINVAL for bad counts.
- * flags: reserved, pass 0.
+ * flags: 0, or MRX_PLAN_NETWORK to size the workspace for the network calls.
  */
 mrx_status mrx_plan_create(mrx_plan* plan, int32_t B, const int32_t* H, const int32_t* W,
                            const int32_t* C, uint32_t flags);
@@ -148,6 +167,80 @@ mrx_status mrx_cg_dc_backward(mrx_plan plan, const float* gx, const float* x, co
 /* Copy the per-slice status words (uint32[B]) to dev_flags (device) and, if
  * clear != 0, reset them.  Enqueued on stream. */
 mrx_status mrx_status_word(mrx_plan plan, uint32_t* dev_flags, int32_t clear, void* stream);
+
+/*
+ * MoDL residual denoiser D(x) = x + N(x) (MoDL subsection: a residual network
+ * of L = 5 convolution layers with F = 64 channels and ReLU; batch
+ * normalisation is not used).  N: 3x3 convolutions with zero "same" padding
+ * and bias, ReLU after layers 1-4; the complex image enters as channels
+ * (real, imag).  Convolutions run on bf16 MFMA with fp32 accumulation; the
+ * layer activations are stored as bf16.  Needs a plan created with
+ * MRX_PLAN_NETWORK.
+ *
+ * mrx_cnn_set_weights packs bf16 copies of the weights into the workspace;
+ * call it again after every weight update.  It keeps the bias pointers.
+ */
+mrx_status mrx_cnn_set_weights(mrx_plan plan, const mrx_cnn_params* w, void* stream);
+/* z = x + N(x) (image-sized complex, must not alias). */
+mrx_status mrx_cnn_forward(mrx_plan plan, const float* x, float* z, void* stream);
+/*
+ * Reverse mode of D at x: recomputes the activations at x, then
+ * gx = gz + J_N(x)^T gz and the weight/bias gradients (written to g, or added
+ * to it if accumulate != 0).  gz in the DF^H(1) convention.
+ */
+mrx_status mrx_cnn_backward(mrx_plan plan, const float* x, const float* gz, float* gx,
+                            const mrx_cnn_grads* g, int32_t accumulate, void* stream);
+
+/*
+ * One 64 -> 64 channel layer of the denoiser (layer = 1, 2 or 3): out =
+ * ReLU(conv3x3(in, W[layer]) + b[layer]) on bf16 NHWC activations
+ * (n_image x 64 bf16 values each, device).  For composing or timing single
+ * layers; mrx_cnn_forward runs all five.
+ */
+mrx_status mrx_cnn_layer_forward(mrx_plan plan, int32_t layer, const void* in, void* out, void* stream);
+
+/*
+ * MoDL unrolled network, eq. update_modl with shared weights:
+ *   x^0 = aHy,  x^{t+1} = (A^H A + lambda I)^{-1} (aHy + lambda D(x^t)),  t < T,
+ * each inverse by n_cg CG steps (as mrx_cg_dc).  x_out receives x^T.
+ * states: NULL or device buffer of (T + 1) image-sized arrays receiving
+ * x^0 .. x^T (what mrx_modl_backward needs).
+ */
+mrx_status mrx_modl_forward(mrx_plan plan, const float* aHy, const float* S, const float* mask,
+                            const float* lambda, int32_t T, int32_t n_cg, float* x_out,
+                            float* states, void* stream);
+
+/*
+ * Reverse mode of mrx_modl_forward from the stored states x^0..x^T: for
+ * t = T-1 .. 0 the denoiser activations at x^t are recomputed, the data
+ * consistency block is differentiated by a second CG solve
+ * (v = (A^H A + lambda I)^{-1} g, g_z = lambda v, g_lambda += Re<v, z^t - x^{t+1}>)
+ * and the denoiser by its reverse pass.  g_out: gradient w.r.t. x^T.
+ * Weight gradients go to g (summed over the unrolls; added to g if
+ * accumulate != 0).  g_lambda (device float[B]) and g_aHy (image-sized) may
+ * be NULL.
+ */
+mrx_status mrx_modl_backward(mrx_plan plan, const float* g_out, const float* states, const float* aHy,
+                             const float* S, const float* mask, const float* lambda, int32_t T,
+                             int32_t n_cg, const mrx_cnn_grads* g, float* g_lambda, float* g_aHy,
+                             int32_t accumulate, void* stream);
+
+/*
+ * MSE loss of eq. network_optimize over all packed pixels:
+ *   loss = mean |x - ref|^2,  g = 2 (x - ref) / n_image  (DF^H(1) form).
+ * g (image-sized) and loss (device float[1]) may be NULL.
+ */
+mrx_status mrx_mse_grad(mrx_plan plan, const float* x, const float* ref, float* g, float* loss,
+                        void* stream);
+
+/*
+ * One Adam step (the training algorithm named in the Methods section) on n
+ * fp32 parameters: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * w -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  step >= 1.
+ * All arrays are device arrays of n floats.
+ */
+mrx_status mrx_adam_step(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                         float b2, float eps, int32_t step, void* stream);
 
 /* Choose the fastest registered schedule per distinct length of the plan by
  * timing each on the given stream (synchronises the host).  The choice is

@@ -14,10 +14,34 @@ and F = 64 real filters; the configuration built here has no batch norm):
 
 Gradients follow the DF^H(1) convention of the paper's complex-numbers
 paragraph: for a complex quantity the returned gradient is dL/dRe + i dL/dIm.
+
+Operand precision.  With ``bf16=True`` the convolution operands are rounded
+to bfloat16 (round to nearest even) where a bf16-operand / wide-accumulator
+implementation rounds them: the layer inputs (the complex image, the stored
+activations), the weights, and the gradients entering each convolution of the
+reverse pass; sums stay in float64.  This mode exists because the ReLU
+derivative is a decision taken on a floating-point value: comparing a bf16
+implementation's reverse pass with an fp64 one mixes in sign flips of
+pre-activations that lie within rounding of zero, so the decision has to be
+taken in the same precision on both sides.  ``bf16=False`` (the default) is
+the plain FP64 definition.
 """
 from __future__ import annotations
 
 import numpy as np
+
+
+def bf16_round(a):
+    """Round to the nearest bfloat16 value (ties to even), via float32.
+    Returns float64."""
+    a32 = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _q(a, on):
+    return bf16_round(a) if on else np.asarray(a, dtype=np.float64)
 
 
 def conv3x3(a, Wt, bias):
@@ -62,37 +86,43 @@ def from_channels(a):
     return a[..., 0] + 1j * a[..., 1]
 
 
-def net_forward(x, weights, keep=False):
+def net_forward(x, weights, keep=False, bf16=False):
     """N(x) for complex x [B,H,W]; weights = [(W, b), ...].
-    With keep=True also returns the per-layer inputs and pre-activations."""
-    a = to_channels(x)
+    With keep=True also returns the per-layer inputs and pre-activations.
+    bf16: round the layer inputs and the weights to bfloat16 (see module)."""
+    a = _q(to_channels(x), bf16)
     acts, pres = [], []
     L = len(weights)
     for l, (Wt, b) in enumerate(weights):
         acts.append(a)
-        pre = conv3x3(a, Wt, b)
+        pre = conv3x3(a, _q(Wt, bf16), b)
         pres.append(pre)
-        a = np.maximum(pre, 0.0) if l < L - 1 else pre
+        a = _q(np.maximum(pre, 0.0), bf16) if l < L - 1 else pre
     out = from_channels(a)
     return (out, acts, pres) if keep else out
 
 
-def denoise(x, weights):
+def denoise(x, weights, bf16=False):
     """D_W(x) = x + N(x)."""
-    return np.asarray(x, dtype=np.complex128) + net_forward(x, weights)
+    return np.asarray(x, dtype=np.complex128) + net_forward(x, weights, bf16=bf16)
 
 
-def denoise_backward(x, weights, g):
+def denoise_backward(x, weights, g, bf16=False):
     """Reverse mode of D_W at x with upstream gradient g (complex [B,H,W]).
-    Returns (g_x complex, [(gW, gb), ...])."""
-    _, acts, pres = net_forward(x, weights, keep=True)
+    Returns (g_x complex, [(gW, gb), ...]).  With bf16=True the gradient
+    entering each convolution is rounded to bfloat16 as well (the bias
+    gradient of the last layer uses the unrounded upstream gradient)."""
+    _, acts, pres = net_forward(x, weights, keep=True, bf16=bf16)
     L = len(weights)
     ga = to_channels(g)
     grads = [None] * L
     for l in range(L - 1, -1, -1):
         if l < L - 1:
-            ga = ga * (pres[l] > 0)
-        gin, gW, gb = conv3x3_backward(acts[l], weights[l][0], ga)
+            ga = _q(ga * (pres[l] > 0), bf16)
+        gq = _q(ga, bf16)
+        gin, gW, gb = conv3x3_backward(acts[l], _q(weights[l][0], bf16), gq)
+        if l == L - 1:
+            gb = ga.sum(axis=(0, 1, 2))
         grads[l] = (gW, gb)
         ga = gin
     return np.asarray(g, dtype=np.complex128) + from_channels(ga), grads

@@ -22,19 +22,20 @@ import numpy as np
 from . import cg, cnn
 
 
-def forward(aHy, S, m, weights, lam, T, n_cg):
-    """Returns (x^T, states [x^0..x^T], zs [z^0..z^{T-1}])."""
+def forward(aHy, S, m, weights, lam, T, n_cg, bf16=False):
+    """Returns (x^T, states [x^0..x^T], zs [z^0..z^{T-1}]).
+    bf16: denoiser operands rounded to bfloat16 (see oracle.cnn)."""
     x = np.asarray(aHy, dtype=np.complex128)
     states, zs = [x], []
     for _ in range(T):
-        z = cnn.denoise(x, weights)
+        z = cnn.denoise(x, weights, bf16=bf16)
         x, _ = cg.cg_dc(aHy, z, S, m, lam, n_cg)
         zs.append(z)
         states.append(x)
     return x, states, zs
 
 
-def backward(g_out, states, zs, aHy, S, m, weights, lam, T, n_cg):
+def backward(g_out, states, zs, aHy, S, m, weights, lam, T, n_cg, bf16=False):
     """Reverse mode.  Returns (grads [(gW, gb)], g_lambda [B], g_aHy)."""
     lam = np.asarray(lam, dtype=np.float64).reshape(-1)
     g = np.asarray(g_out, dtype=np.complex128)
@@ -46,7 +47,7 @@ def backward(g_out, states, zs, aHy, S, m, weights, lam, T, n_cg):
         v, g_z, gl = cg.cg_dc_backward(g, states[t + 1], zs[t], S, m, lam, n_cg)
         g_lam += gl
         g_a += v
-        g, lg = cnn.denoise_backward(states[t], weights, g_z)
+        g, lg = cnn.denoise_backward(states[t], weights, g_z, bf16=bf16)
         gW = [(a[0] + b[0], a[1] + b[1]) for a, b in zip(gW, lg)]
     g_a += g  # x^0 = A^H y
     return gW, g_lam, g_a

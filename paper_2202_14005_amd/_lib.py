@@ -40,11 +40,27 @@ SIGNATURES = {
     "mrx_cg_dc_backward": (c_int32, [P, P, P, P, P, P, P, c_int32, P, P, P, c_int32, P]),
     "mrx_status_word": (c_int32, [P, P, c_int32, P]),
     "mrx_plan_autotune": (c_int32, [P, P, P, P, P, P]),
+    "mrx_cnn_set_weights": (c_int32, [P, P, P]),
+    "mrx_cnn_forward": (c_int32, [P, P, P, P]),
+    "mrx_cnn_layer_forward": (c_int32, [P, c_int32, P, P, P]),
+    "mrx_cnn_backward": (c_int32, [P, P, P, P, P, c_int32, P]),
+    "mrx_modl_forward": (c_int32, [P, P, P, P, P, c_int32, c_int32, P, P, P]),
+    "mrx_modl_backward": (c_int32, [P, P, P, P, P, P, P, c_int32, c_int32, P, P, P, c_int32, P]),
+    "mrx_mse_grad": (c_int32, [P, P, P, P, P, P]),
+    "mrx_adam_step": (c_int32, [P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "mrx_plan_schedule": (c_char_p, [P, c_int32]),
 }
 
 STATUS = {0: "MRX_OK", -1: "MRX_EINVAL", -2: "MRX_EUNSUPPORTED", -3: "MRX_ENOMEM",
           -4: "MRX_EHIP", -5: "MRX_ENOWORKSPACE"}
+
+
+class CnnParams(ctypes.Structure):
+    _fields_ = [("w", c_void_p * 5), ("b", c_void_p * 5)]
+
+
+class CnnGrads(ctypes.Structure):
+    _fields_ = [("w", c_void_p * 5), ("b", c_void_p * 5)]
 
 
 class MrxError(RuntimeError):

@@ -47,7 +47,8 @@ SCHEDULES = [
     ("n512_4x8x16_t32", 4, 8, 16, 32, 8, 8),
 ]
 
-COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net_stub.hip"]
+COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net.hip", "conv.hip",
+                  "conv_wgrad.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -83,9 +83,10 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   *out = nullptr;
   if (B <= 0 || B > (1 << 20)) return fail(MRX_EINVAL, "plan_create: batch size must be in [1, 2^20]");
   if (!H || !W || !C) return fail(MRX_EINVAL, "plan_create: null shape array");
-  (void)flags;
+  if (flags & ~MRX_PLAN_NETWORK) return fail(MRX_EINVAL, "plan_create: unknown flags");
   auto* p = new mrx_plan_s();
   p->B = B;
+  p->flags = flags;
   int64_t xo = 0, so = 0, mo = 0;
   for (int b = 0; b < B; ++b) {
     const int h = H[b], w = W[b], c = C[b];
@@ -225,6 +226,7 @@ mrx_status mrx_plan_set_workspace(mrx_plan p, void* ptr, size_t bytes) {
   if (((uintptr_t)ptr) & 255) return fail(MRX_EINVAL, "set_workspace: pointer not 256-byte aligned");
   p->ws = (char*)ptr;
   p->ws_given = bytes;
+  p->net_ready = false;  // packed weights live in the workspace
   // status words and stop flags start at zero
   hipError_t e = hipMemset(p->ws + p->ws_stop, 0, align256(sizeof(int) * p->B) + align256(sizeof(uint32_t) * p->B));
   if (e != hipSuccess) return hip_fail(e, "set_workspace: clear status");

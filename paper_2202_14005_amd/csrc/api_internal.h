@@ -43,8 +43,13 @@ struct mrx_plan_s {
   size_t ws_given = 0, ws_bytes = 0, ws_bytes_base = 0;
   size_t ws_tmp = 0, ws_r = 0, ws_p = 0, ws_q = 0, ws_v = 0;
   size_t ws_pq = 0, ws_rr0 = 0, ws_rr1 = 0, ws_part = 0, ws_stop = 0, ws_status = 0;
+  uint32_t flags = 0;
   // network workspace (set by extra_workspace_bytes)
-  size_t ws_net = 0;
+  size_t ws_act[4] = {0, 0, 0, 0}, ws_gact[2] = {0, 0};
+  size_t ws_z = 0, ws_ximg[2] = {0, 0}, ws_gimg[2] = {0, 0}, ws_vimg = 0;
+  size_t ws_pk = 0, ws_wpart = 0, ws_loss = 0;
+  const float* net_b[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool net_ready = false;
 };
 
 namespace mrx {

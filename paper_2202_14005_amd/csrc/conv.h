@@ -1,0 +1,50 @@
+// MFMA (bf16 in, fp32 accumulate) 3x3 convolution kernels for the MoDL
+// residual denoiser D_W(x) = x + N(x) (MoDL subsection): N = conv(2->64) ReLU
+// conv(64->64) ReLU x3, conv(64->2), zero "same" padding, bias.
+#pragma once
+#include "common.h"
+
+namespace mrx {
+
+constexpr int CNN_F = 64;      // feature channels
+constexpr int CNN_L = 5;       // layers
+constexpr int CONV_TW = 32;    // output tile width (pixels)
+constexpr int CONV_TH = 16;    // output tile height (rows); 4 waves x 4 rows
+
+// Packed bf16 weights of one network (layout chosen for the MFMA operand
+// fragments, filled by k_pack_*):
+//   first:  [2 ksteps][2 mblk][64 lanes][8]  (K = 9 taps x 2 ch padded to 32)
+//   mid:    [9 taps][4 kc][2 mblk][64 lanes][8]
+//   last:   [9 taps][2 cc][64 lanes][8]       (16x16x32, co padded to 16)
+struct PackedNet {
+  const uint16_t* first;
+  const uint16_t* mid[3];
+  const uint16_t* last;
+  const float* bias[5];
+};
+
+// Epilogue / input variants
+enum ConvMode : int {
+  CONV_FWD = 0,     // bias + ReLU (first, mid); bias + residual (last)
+  CONV_DGRAD = 1,   // no bias; output multiplied by ReLU'(act) ; last: add residual grad
+};
+
+struct ConvArgs {
+  const SliceDesc* desc;
+  const int* slices;
+  int nslices;
+  int tiles_x;               // max over slices of ceil(W / 32)
+  int tiles_y;               // max over slices of ceil(H / 16)
+  const uint16_t* in_bf16;   // NHWC bf16, pixel offset xoff * 64
+  const float2* in_c;        // complex image (first layer input / last layer residual)
+  uint16_t* out_bf16;        // NHWC bf16
+  float2* out_c;             // complex output (last layer)
+  const uint16_t* wpk;       // packed weights
+  const float* bias;         // fp32 bias or null
+  const uint16_t* relu_ref;  // dgrad: activation whose ReLU derivative masks the output
+  const float2* resid;       // last layer: residual term added to the output
+  int mode;
+  uint32_t* status;          // per-slice status (non-finite output flag), may be null
+};
+
+}  // namespace mrx

@@ -1,0 +1,321 @@
+// MFMA 3x3 convolutions for the MoDL denoiser (bf16 operands, fp32
+// accumulation, NHWC activations).  One workgroup (4 waves) computes a tile
+// of 16 rows x 32 columns of one slice; the input tile with its one-pixel
+// halo is staged in LDS, weights stream from L1/L2 as MFMA fragments.
+//   first layer:  2 -> 64 channels, v_mfma_f32_32x32x16_bf16, K = 18 -> 32
+//   middle layer: 64 -> 64, v_mfma_f32_32x32x16_bf16, K = 9 x 64
+//   last layer:   64 -> 2 (+ residual), v_mfma_f32_16x16x32_bf16, co padded to 16
+// The same kernels run the input-gradient (dgrad) pass with transposed,
+// flipped weights and a ReLU-derivative mask in the epilogue.
+#include "conv.h"
+#include "cg_kernels.h"
+
+namespace mrx {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);                      // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ uint4 ldg16(const uint16_t* p) { return *(const uint4*)p; }
+
+// LDS input tile: (16 + 2) x (32 + 2) pixels x 64 channels bf16, as 8 chunks
+// of 16 bytes per pixel; chunk c of pixel p sits at slot c ^ (p & 7) so the
+// 32 lanes reading one chunk of 32 consecutive pixels hit distinct banks.
+constexpr int TILE_PX = (CONV_TH + 2) * (CONV_TW + 2);
+
+__device__ __forceinline__ void load_tile64(uint4* tile, const uint16_t* in, int H, int W, int ty0, int tx0) {
+  for (int q = threadIdx.x; q < TILE_PX * 8; q += 256) {
+    const int px = q >> 3, ch = q & 7;
+    const int ly = px / (CONV_TW + 2), lx = px % (CONV_TW + 2);
+    const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = ldg16(in + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
+    tile[px * 8 + (ch ^ (px & 7))] = v;
+  }
+}
+
+__device__ __forceinline__ bool bf_pos(uint16_t h) { return (h & 0x8000u) == 0 && h != 0; }
+
+// ------------------------------------------------------------- 64 -> 64
+__global__ void __launch_bounds__(256) k_conv_mid(ConvArgs a) {
+  __shared__ uint4 tile[TILE_PX * 8];
+  const int b = a.slices[blockIdx.z];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
+  if (tx0 >= W || ty0 >= H) return;
+  load_tile64(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[m][n][v] = 0.f;
+  const uint16_t* wp = a.wpk + lane * 8;
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const bf16x8 w0 = as_bf16x8(ldg16(wp + ((tap * 4 + kc) * 2 + 0) * 512));
+      const bf16x8 w1 = as_bf16x8(ldg16(wp + ((tap * 4 + kc) * 2 + 1) * 512));
+      const int ch = kc * 2 + (lane >> 5);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int px = (wv * 4 + nb + dy) * (CONV_TW + 2) + (lane & 31) + dx;
+        const bf16x8 bv = as_bf16x8(tile[px * 8 + (ch ^ (px & 7))]);
+        acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, bv, acc[0][nb], 0, 0, 0);
+        acc[1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bv, acc[1][nb], 0, 0, 0);
+      }
+    }
+  }
+  uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
+  const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int gy = ty0 + wv * 4 + nb, gx = tx0 + (lane & 31);
+    if (gy >= H || gx >= W) continue;
+    const int64_t po = ((int64_t)gy * W + gx) * CNN_F;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int co0 = m * 32 + 8 * g + (lane >> 5) * 4;
+        uint16_t h[4];
+        uint2 mref = make_uint2(0, 0);
+        if (a.mode == CONV_DGRAD) mref = *(const uint2*)(rref + po + co0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v = acc[m][nb][4 * g + j];
+          if (a.mode == CONV_FWD) {
+            v += a.bias[co0 + j];
+            v = v > 0.f ? v : 0.f;
+          } else {
+            const uint32_t word = (j < 2) ? mref.x : mref.y;
+            const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
+            if (!bf_pos(r)) v = 0.f;
+          }
+          h[j] = f2bf(v);
+        }
+        uint2 pk;
+        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        *(uint2*)(out + po + co0) = pk;
+      }
+  }
+}
+
+// ---------------------------------------------------------------- 2 -> 64
+// Input: complex image (fp32 pairs), rounded to bf16.  K = 9 taps x 2 channels
+// = 18, padded to 32 (two 16-deep MFMA steps).
+__global__ void __launch_bounds__(256) k_conv_first(ConvArgs a) {
+  __shared__ uint32_t tile[TILE_PX];
+  const int b = a.slices[blockIdx.z];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
+  if (tx0 >= W || ty0 >= H) return;
+  const float2* in = a.in_c + d.xoff;
+  for (int px = threadIdx.x; px < TILE_PX; px += 256) {
+    const int ly = px / (CONV_TW + 2), lx = px % (CONV_TW + 2);
+    const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+    float2 v = make_float2(0.f, 0.f);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = in[(int64_t)gy * W + gx];
+    tile[px] = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[m][n][v] = 0.f;
+  const uint16_t* wp = a.wpk + lane * 8;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const bf16x8 w0 = as_bf16x8(ldg16(wp + (s * 2 + 0) * 512));
+    const bf16x8 w1 = as_bf16x8(ldg16(wp + (s * 2 + 1) * 512));
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      uint4 raw;
+      uint32_t* rw = (uint32_t*)&raw;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int t = s * 8 + (lane >> 5) * 4 + e;  // tap
+        uint32_t v = 0;
+        if (t < 9) {
+          const int dy = t / 3, dx = t % 3;
+          v = tile[(wv * 4 + nb + dy) * (CONV_TW + 2) + (lane & 31) + dx];
+        }
+        rw[e] = v;
+      }
+      const bf16x8 bv = as_bf16x8(raw);
+      acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, bv, acc[0][nb], 0, 0, 0);
+      acc[1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bv, acc[1][nb], 0, 0, 0);
+    }
+  }
+  uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
+  const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int gy = ty0 + wv * 4 + nb, gx = tx0 + (lane & 31);
+    if (gy >= H || gx >= W) continue;
+    const int64_t po = ((int64_t)gy * W + gx) * CNN_F;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int co0 = m * 32 + 8 * g + (lane >> 5) * 4;
+        uint16_t h[4];
+        uint2 mref = make_uint2(0, 0);
+        if (a.mode == CONV_DGRAD) mref = *(const uint2*)(rref + po + co0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v = acc[m][nb][4 * g + j];
+          if (a.mode == CONV_FWD) {
+            v += a.bias[co0 + j];
+            v = v > 0.f ? v : 0.f;
+          } else {
+            const uint32_t word = (j < 2) ? mref.x : mref.y;
+            const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
+            if (!bf_pos(r)) v = 0.f;
+          }
+          h[j] = f2bf(v);
+        }
+        uint2 pk;
+        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        *(uint2*)(out + po + co0) = pk;
+      }
+  }
+}
+
+// ---------------------------------------------------------------- 64 -> 2
+// v_mfma_f32_16x16x32_bf16 with the two output channels padded to 16 rows;
+// each wave covers 4 rows x 32 columns = 8 blocks of 16 pixels.
+// Output: out_c = resid + (acc + bias)  (fwd: z = x + N(x); dgrad: g_x).
+__global__ void __launch_bounds__(256) k_conv_last(ConvArgs a) {
+  __shared__ uint4 tile[TILE_PX * 8];
+  const int b = a.slices[blockIdx.z];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
+  if (tx0 >= W || ty0 >= H) return;
+  load_tile64(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  f32x4 acc[8];
+#pragma unroll
+  for (int n = 0; n < 8; ++n)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[n][v] = 0.f;
+  const uint16_t* wp = a.wpk + lane * 8;
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const bf16x8 w = as_bf16x8(ldg16(wp + (tap * 2 + cc) * 512));
+      const int ch = cc * 4 + (lane >> 4);
+#pragma unroll
+      for (int n = 0; n < 8; ++n) {
+        const int px = (wv * 4 + (n >> 1) + dy) * (CONV_TW + 2) + (n & 1) * 16 + (lane & 15) + dx;
+        const bf16x8 bv = as_bf16x8(tile[px * 8 + (ch ^ (px & 7))]);
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, bv, acc[n], 0, 0, 0);
+      }
+    }
+  }
+  if (lane >= 16) return;
+  const float b0 = a.bias ? a.bias[0] : 0.f, b1 = a.bias ? a.bias[1] : 0.f;
+  float2* out = a.out_c + d.xoff;
+  const float2* res = a.resid ? a.resid + d.xoff : nullptr;
+  bool bad = false;
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    const int gy = ty0 + wv * 4 + (n >> 1), gx = tx0 + (n & 1) * 16 + lane;
+    if (gy >= H || gx >= W) continue;
+    const int64_t o = (int64_t)gy * W + gx;
+    float2 r = res ? res[o] : make_float2(0.f, 0.f);
+    float2 v = make_float2(r.x + acc[n][0] + b0, r.y + acc[n][1] + b1);
+    bad |= !isfinite(v.x) || !isfinite(v.y);
+    out[o] = v;
+  }
+  if (bad && a.status) a.status[b] |= FLAG_CNN_NONFINITE;
+}
+
+// ------------------------------------------------------------- weight packing
+// fp32 master weights W[co][ci][3][3] -> MFMA fragment layouts (see conv.h).
+// transpose = 1 packs the dgrad operator (swap co/ci, flip taps).
+// W[orig_co][orig_ci][tap] with orig_ci_count input channels.  Plain:
+// (co, ci) = (orig_co, orig_ci).  Transposed (dgrad operator): the new
+// out-channel is the original in-channel and the taps are mirrored.
+__device__ __forceinline__ float wget(const float* Wm, int co, int ci, int tap, int orig_ci_count, int transpose) {
+  if (!transpose) return Wm[(co * orig_ci_count + ci) * 9 + tap];
+  return Wm[(ci * orig_ci_count + co) * 9 + (8 - tap)];
+}
+
+// mid: [9][4][2][64][8]; CO = CI = 64 (after the transpose, too)
+__global__ void k_pack_mid(const float* Wm, uint16_t* out, int transpose) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 9 * 4 * 2 * 64 * 8) return;
+  const int e = idx & 7, lane = (idx >> 3) & 63, mb = (idx >> 9) & 1, kc = (idx >> 10) & 3, tap = idx >> 12;
+  const int co = mb * 32 + (lane & 31), ci = kc * 16 + (lane >> 5) * 8 + e;
+  out[idx] = f2bf(wget(Wm, co, ci, tap, 64, transpose));
+}
+
+// first: [2 s][2 mb][64][8]; out-channels 64, in-channels 2.
+// Forward: original W1 [64][2][3][3].  Transposed: original W5 [2][64][3][3]
+// used as the dgrad of the last layer (out = 64 = original ci, in = 2).
+__global__ void k_pack_first(const float* Wm, uint16_t* out, int transpose) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * 2 * 64 * 8) return;
+  const int e = idx & 7, lane = (idx >> 3) & 63, mb = (idx >> 9) & 1, s = idx >> 10;
+  const int co = mb * 32 + (lane & 31);
+  const int k = s * 16 + (lane >> 5) * 8 + e;
+  const int tap = k >> 1, ci = k & 1;
+  float v = 0.f;
+  if (tap < 9) v = transpose ? wget(Wm, co, ci, tap, 64, 1) : wget(Wm, co, ci, tap, 2, 0);
+  out[idx] = f2bf(v);
+}
+
+// last: [9][2 cc][64][8]; out-channels 2 padded to 16, in-channels 64.
+// Forward: original W5 [2][64][3][3].  Transposed: original W1 [64][2][3][3]
+// used as the dgrad of the first layer (out = 2 = original ci, in = 64).
+__global__ void k_pack_last(const float* Wm, uint16_t* out, int transpose) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 9 * 2 * 64 * 8) return;
+  const int e = idx & 7, lane = (idx >> 3) & 63, cc = (idx >> 9) & 1, tap = idx >> 10;
+  const int co = lane & 15, ci = cc * 32 + (lane >> 4) * 8 + e;
+  float v = 0.f;
+  if (co < 2) v = transpose ? wget(Wm, co, ci, tap, 2, 1) : wget(Wm, co, ci, tap, 64, 0);
+  out[idx] = f2bf(v);
+}
+
+hipError_t conv_launch(int kind, const ConvArgs& a, hipStream_t s) {
+  dim3 grid(a.tiles_x, a.tiles_y, a.nslices);
+  if (kind == 0) hipLaunchKernelGGL(k_conv_first, grid, dim3(256), 0, s, a);
+  else if (kind == 1) hipLaunchKernelGGL(k_conv_mid, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_conv_last, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t pack_weights(int kind, const float* Wm, uint16_t* out, int transpose, hipStream_t s) {
+  if (kind == 0) hipLaunchKernelGGL(k_pack_first, dim3(8), dim3(256), 0, s, Wm, out, transpose);
+  else if (kind == 1) hipLaunchKernelGGL(k_pack_mid, dim3(144), dim3(256), 0, s, Wm, out, transpose);
+  else hipLaunchKernelGGL(k_pack_last, dim3(36), dim3(256), 0, s, Wm, out, transpose);
+  return hipGetLastError();
+}
+
+}  // namespace mrx

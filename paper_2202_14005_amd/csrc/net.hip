@@ -1,0 +1,423 @@
+// Network entry points: the MoDL residual denoiser (forward, reverse mode),
+// the MoDL unrolled network (eq. update_modl) with its reverse pass by adjoint
+// CG and recomputed unroll activations, the MSE loss gradient and Adam.
+#include "../../include/mrx.h"
+#include "api_internal.h"
+#include "conv.h"
+#include "wgrad.h"
+
+namespace mrx {
+
+static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int PK_FIRST = 2 * 2 * 64 * 8;
+constexpr int PK_MID = 9 * 4 * 2 * 64 * 8;
+constexpr int PK_LAST = 9 * 2 * 64 * 8;
+constexpr int NOUT_MID = 64 * 64 * 9 + 64;
+constexpr int NOUT_FIRST = 64 * 2 * 9 + 64;
+constexpr int NOUT_LAST = 2 * 64 * 9 + 2;
+
+static int bands_of(mrx_plan_s* p) { return (p->maxH + WG_BAND - 1) / WG_BAND; }
+
+// Network workspace layout, appended after the SENSE/CG part (flags bit 0).
+size_t extra_workspace_bytes(mrx_plan_s* p) {
+  if (!(p->flags & MRX_PLAN_NETWORK)) return 0;
+  const size_t ni = (size_t)p->n_image;
+  size_t w = 0;
+  auto take = [&](size_t bytes) { size_t o = p->ws_bytes_base + w; w += al(bytes); return o; };
+  for (int i = 0; i < 4; ++i) p->ws_act[i] = take(ni * CNN_F * 2);
+  for (int i = 0; i < 2; ++i) p->ws_gact[i] = take(ni * CNN_F * 2);
+  p->ws_z = take(ni * 8);
+  for (int i = 0; i < 2; ++i) p->ws_ximg[i] = take(ni * 8);
+  for (int i = 0; i < 2; ++i) p->ws_gimg[i] = take(ni * 8);
+  p->ws_vimg = take(ni * 8);
+  p->ws_pk = take((size_t)2 * (PK_FIRST + 3 * PK_MID + PK_LAST) * 2);
+  const size_t slots = (size_t)bands_of(p) * p->B;
+  p->ws_wpart = take(std::max<size_t>(slots * NOUT_MID, 2 * slots * NOUT_FIRST) * 4);
+  p->ws_loss = take((size_t)p->B * p->nrr * 4);
+  return w;
+}
+
+// Packed weights: the forward set [first | mid x3 | last] followed by the
+// dgrad set, whose first-layer operator is last-shaped and whose last-layer
+// operator is first-shaped: [last-shaped | mid x3 | first-shaped].
+static uint16_t* pk_ptr(mrx_plan_s* p, int transpose, int layer) {
+  uint16_t* base = (uint16_t*)(p->ws + p->ws_pk);
+  if (!transpose) {
+    if (layer == 0) return base;
+    if (layer <= 3) return base + PK_FIRST + (layer - 1) * PK_MID;
+    return base + PK_FIRST + 3 * PK_MID;
+  }
+  base += PK_FIRST + 3 * PK_MID + PK_LAST;
+  if (layer == 0) return base;
+  if (layer <= 3) return base + PK_LAST + (layer - 1) * PK_MID;
+  return base + PK_LAST + 3 * PK_MID;
+}
+
+static ConvArgs conv_args(mrx_plan_s* p) {
+  ConvArgs a{};
+  a.desc = p->d_desc;
+  a.slices = p->d_all;
+  a.nslices = p->B;
+  a.tiles_x = (p->maxW + CONV_TW - 1) / CONV_TW;
+  a.tiles_y = (p->maxH + CONV_TH - 1) / CONV_TH;
+  a.status = (uint32_t*)(p->ws + p->ws_status);
+  return a;
+}
+
+static mrx_status net_ready(mrx_plan_s* p, const char* who) {
+  if (!p->ws) return fail(MRX_ENOWORKSPACE, std::string(who) + ": workspace not set");
+  if (!(p->flags & MRX_PLAN_NETWORK))
+    return fail(MRX_ENOWORKSPACE, std::string(who) + ": plan was created without MRX_PLAN_NETWORK");
+  if (!p->net_ready) return fail(MRX_EINVAL, std::string(who) + ": call mrx_cnn_set_weights first");
+  return MRX_OK;
+}
+
+// z = x + N(x); activations of layers 1-4 stay in the workspace.
+static mrx_status cnn_fwd(mrx_plan_s* p, const float2* x, float2* z, hipStream_t s) {
+  uint16_t* act[4];
+  for (int i = 0; i < 4; ++i) act[i] = (uint16_t*)(p->ws + p->ws_act[i]);
+  ConvArgs a = conv_args(p);
+  a.mode = CONV_FWD;
+  a.in_c = x;
+  a.out_bf16 = act[0];
+  a.wpk = pk_ptr(p, 0, 0);
+  a.bias = p->net_b[0];
+  hipError_t e = conv_launch(0, a, s);
+  for (int l = 1; l <= 3 && e == hipSuccess; ++l) {
+    ConvArgs m = conv_args(p);
+    m.mode = CONV_FWD;
+    m.in_bf16 = act[l - 1];
+    m.out_bf16 = act[l];
+    m.wpk = pk_ptr(p, 0, l);
+    m.bias = p->net_b[l];
+    e = conv_launch(1, m, s);
+  }
+  if (e == hipSuccess) {
+    ConvArgs f = conv_args(p);
+    f.mode = CONV_FWD;
+    f.in_bf16 = act[3];
+    f.out_c = z;
+    f.resid = x;
+    f.wpk = pk_ptr(p, 0, 4);
+    f.bias = p->net_b[4];
+    e = conv_launch(2, f, s);
+  }
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "cnn_forward");
+}
+
+// Reverse mode of D at x (activations of cnn_fwd(x) must be in the workspace):
+// gx = gz + J_N(x)^T gz; weight/bias gradients into g (accumulate or set).
+static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, float2* gx, const mrx_cnn_grads* g,
+                          int accumulate, hipStream_t s) {
+  uint16_t* act[4];
+  for (int i = 0; i < 4; ++i) act[i] = (uint16_t*)(p->ws + p->ws_act[i]);
+  uint16_t* gb[2] = {(uint16_t*)(p->ws + p->ws_gact[0]), (uint16_t*)(p->ws + p->ws_gact[1])};
+  float* part = (float*)(p->ws + p->ws_wpart);
+  const int bands = bands_of(p);
+  const int slots = bands * p->B;
+  hipError_t e;
+  auto wg = [&](int kind, const uint16_t* gin, const uint16_t* ain, const float2* xin, int layer) {
+    WgradArgs w{};
+    w.desc = p->d_desc;
+    w.slices = p->d_all;
+    w.nslices = p->B;
+    w.g = gin;
+    w.act = ain;
+    w.x = xin;
+    w.partial = part;
+    w.nout = kind == 1 ? NOUT_MID : kind == 0 ? NOUT_FIRST : NOUT_LAST;
+    hipError_t r = wgrad_launch(kind, w, bands, s);
+    if (r != hipSuccess) return r;
+    const int nslots = kind == 1 ? slots : 2 * slots;
+    const int nw = w.nout - (kind == 2 ? 2 : 64);
+    return wgrad_reduce(part, nslots, w.nout, g->w[layer], g->b[layer], nw, accumulate, s);
+  };
+  // layer 5 (64 -> 2)
+  e = wg(2, nullptr, act[3], gz, 4);
+  if (e == hipSuccess) {
+    ConvArgs a = conv_args(p);
+    a.mode = CONV_DGRAD;
+    a.in_c = gz;
+    a.out_bf16 = gb[0];
+    a.wpk = pk_ptr(p, 1, 4);
+    a.relu_ref = act[3];
+    e = conv_launch(0, a, s);
+  }
+  // layers 4, 3, 2 (64 -> 64)
+  int cur = 0;
+  for (int l = 3; l >= 1 && e == hipSuccess; --l) {
+    e = wg(1, gb[cur], act[l - 1], nullptr, l);
+    if (e != hipSuccess) break;
+    ConvArgs m = conv_args(p);
+    m.mode = CONV_DGRAD;
+    m.in_bf16 = gb[cur];
+    m.out_bf16 = gb[1 - cur];
+    m.wpk = pk_ptr(p, 1, l);
+    m.relu_ref = act[l - 1];
+    e = conv_launch(1, m, s);
+    cur = 1 - cur;
+  }
+  // layer 1 (2 -> 64) and the residual
+  if (e == hipSuccess) e = wg(0, gb[cur], nullptr, x, 0);
+  if (e == hipSuccess) {
+    ConvArgs f = conv_args(p);
+    f.mode = CONV_DGRAD;
+    f.in_bf16 = gb[cur];
+    f.out_c = gx;
+    f.resid = gz;
+    f.wpk = pk_ptr(p, 1, 0);
+    e = conv_launch(2, f, s);
+  }
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "cnn_backward");
+}
+
+// ------------------------------------------------------ elementwise helpers
+__global__ void k_copy_c(const float2* src, float2* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+__global__ void k_axpy_c(const float2* src, float2* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) { float2 a = dst[i], b = src[i]; dst[i] = make_float2(a.x + b.x, a.y + b.y); }
+}
+static hipError_t copy_c(const float2* src, float2* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_c, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+static hipError_t axpy_c(const float2* src, float2* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_c, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// g = 2 (x - ref) / n_total; per-slice-block partial sums of |x - ref|^2.
+__global__ void __launch_bounds__(256) k_mse(const SliceDesc* desc, const int* slices, const float2* x,
+                                             const float2* ref, float2* g, float* part, int nrr, float scale) {
+  __shared__ float red[4];
+  const int b = slices[blockIdx.y];
+  const SliceDesc d = desc[b];
+  const int64_t n = (int64_t)d.H * d.W;
+  float acc = 0.f;
+  const int64_t base = (int64_t)blockIdx.x * CG_EPB;
+  for (int k = threadIdx.x; k < CG_EPB; k += 256) {
+    const int64_t i = base + k;
+    if (i >= n) break;
+    const float2 a = x[d.xoff + i], r = ref[d.xoff + i];
+    const float dx = a.x - r.x, dy = a.y - r.y;
+    acc += dx * dx + dy * dy;
+    if (g) g[d.xoff + i] = make_float2(2.f * scale * dx, 2.f * scale * dy);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)b * nrr + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+__global__ void k_mse_total(const float* part, int total, float scale, float* loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.f;
+    for (int i = 0; i < total; ++i) s += part[i];
+    *loss = s * scale;
+  }
+}
+
+__global__ void k_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace mrx
+
+using namespace mrx;
+
+extern "C" {
+
+mrx_status mrx_cnn_set_weights(mrx_plan p, const mrx_cnn_params* w, void* stream) {
+  if (!p || !w) return fail(MRX_EINVAL, "cnn_set_weights: null argument");
+  if (!p->ws) return fail(MRX_ENOWORKSPACE, "cnn_set_weights: workspace not set");
+  if (!(p->flags & MRX_PLAN_NETWORK))
+    return fail(MRX_ENOWORKSPACE, "cnn_set_weights: plan was created without MRX_PLAN_NETWORK");
+  for (int l = 0; l < 5; ++l)
+    if (!w->w[l] || !w->b[l]) return fail(MRX_EINVAL, "cnn_set_weights: null weight or bias");
+  hipStream_t s = (hipStream_t)stream;
+  for (int l = 0; l < 5; ++l) p->net_b[l] = w->b[l];
+  const int kinds[5] = {0, 1, 1, 1, 2};
+  const int tkinds[5] = {2, 1, 1, 1, 0};  // dgrad of first is last-shaped and vice versa
+  for (int l = 0; l < 5; ++l) {
+    hipError_t e = pack_weights(kinds[l], w->w[l], pk_ptr(p, 0, l), 0, s);
+    if (e == hipSuccess) e = pack_weights(tkinds[l], w->w[l], pk_ptr(p, 1, l), 1, s);
+    if (e != hipSuccess) return hip_fail(e, "cnn_set_weights: pack");
+  }
+  p->net_ready = true;
+  return MRX_OK;
+}
+
+mrx_status mrx_cnn_forward(mrx_plan p, const float* x, float* z, void* stream) {
+  if (!p) return fail(MRX_EINVAL, "cnn_forward: null plan");
+  if (!x || !z) return fail(MRX_EINVAL, "cnn_forward: null data pointer");
+  if (x == z) return fail(MRX_EINVAL, "cnn_forward: input and output must not alias");
+  mrx_status st = net_ready(p, "cnn_forward");
+  if (st != MRX_OK) return st;
+  return cnn_fwd(p, (const float2*)x, (float2*)z, (hipStream_t)stream);
+}
+
+mrx_status mrx_cnn_backward(mrx_plan p, const float* x, const float* gz, float* gx, const mrx_cnn_grads* g,
+                            int32_t accumulate, void* stream) {
+  if (!p) return fail(MRX_EINVAL, "cnn_backward: null plan");
+  if (!x || !gz || !gx || !g) return fail(MRX_EINVAL, "cnn_backward: null data pointer");
+  for (int l = 0; l < 5; ++l)
+    if (!g->w[l] || !g->b[l]) return fail(MRX_EINVAL, "cnn_backward: null gradient buffer");
+  if (gx == gz) return fail(MRX_EINVAL, "cnn_backward: gx and gz must not alias");
+  mrx_status st = net_ready(p, "cnn_backward");
+  if (st != MRX_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  float2* z = (float2*)(p->ws + p->ws_z);
+  st = cnn_fwd(p, (const float2*)x, z, s);  // recompute the activations at x
+  if (st != MRX_OK) return st;
+  return cnn_bwd(p, (const float2*)x, (const float2*)gz, (float2*)gx, g, accumulate, s);
+}
+
+mrx_status mrx_cnn_layer_forward(mrx_plan p, int32_t layer, const void* in, void* out, void* stream) {
+  if (!p) return fail(MRX_EINVAL, "cnn_layer_forward: null plan");
+  if (!in || !out || in == out) return fail(MRX_EINVAL, "cnn_layer_forward: bad data pointers");
+  if (layer < 1 || layer > 3) return fail(MRX_EINVAL, "cnn_layer_forward: layer must be 1, 2 or 3");
+  mrx_status st = net_ready(p, "cnn_layer_forward");
+  if (st != MRX_OK) return st;
+  ConvArgs m = conv_args(p);
+  m.mode = CONV_FWD;
+  m.in_bf16 = (const uint16_t*)in;
+  m.out_bf16 = (uint16_t*)out;
+  m.wpk = pk_ptr(p, 0, layer);
+  m.bias = p->net_b[layer];
+  hipError_t e = conv_launch(1, m, (hipStream_t)stream);
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "cnn_layer_forward");
+}
+
+mrx_status mrx_modl_forward(mrx_plan p, const float* aHy, const float* S, const float* mask, const float* lambda,
+                            int32_t T, int32_t n_cg, float* x_out, float* states, void* stream) {
+  if (!p) return fail(MRX_EINVAL, "modl_forward: null plan");
+  if (!aHy || !S || !mask || !lambda || !x_out) return fail(MRX_EINVAL, "modl_forward: null data pointer");
+  if (T < 0 || T > 1000 || n_cg < 0 || n_cg > 100000) return fail(MRX_EINVAL, "modl_forward: T or n_cg out of range");
+  mrx_status st = net_ready(p, "modl_forward");
+  if (st != MRX_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ni = p->n_image;
+  float2* z = (float2*)(p->ws + p->ws_z);
+  float2* st2 = (float2*)states;
+  const float2* prev = (const float2*)aHy;
+  if (st2) {
+    hipError_t e = copy_c((const float2*)aHy, st2, ni, s);
+    if (e != hipSuccess) return hip_fail(e, "modl_forward: copy");
+  }
+  if (T == 0) {
+    hipError_t e = copy_c((const float2*)aHy, (float2*)x_out, ni, s);
+    return e == hipSuccess ? MRX_OK : hip_fail(e, "modl_forward: copy");
+  }
+  for (int t = 0; t < T; ++t) {
+    st = cnn_fwd(p, prev, z, s);
+    if (st != MRX_OK) return st;
+    float2* next;
+    if (t == T - 1) next = (float2*)x_out;
+    else if (st2) next = st2 + (int64_t)(t + 1) * ni;
+    else next = (float2*)(p->ws + p->ws_ximg[t & 1]);
+    st = cg_impl(p, (const float2*)aHy, z, (const float2*)S, mask, lambda, n_cg, next, nullptr, s);
+    if (st != MRX_OK) return st;
+    prev = next;
+  }
+  if (st2) {
+    hipError_t e = copy_c((const float2*)x_out, st2 + (int64_t)T * ni, ni, s);
+    if (e != hipSuccess) return hip_fail(e, "modl_forward: copy");
+  }
+  return MRX_OK;
+}
+
+mrx_status mrx_modl_backward(mrx_plan p, const float* g_out, const float* states, const float* aHy, const float* S,
+                             const float* mask, const float* lambda, int32_t T, int32_t n_cg,
+                             const mrx_cnn_grads* g, float* g_lambda, float* g_aHy, int32_t accumulate,
+                             void* stream) {
+  if (!p) return fail(MRX_EINVAL, "modl_backward: null plan");
+  if (!g_out || !states || !aHy || !S || !mask || !lambda || !g)
+    return fail(MRX_EINVAL, "modl_backward: null data pointer");
+  for (int l = 0; l < 5; ++l)
+    if (!g->w[l] || !g->b[l]) return fail(MRX_EINVAL, "modl_backward: null gradient buffer");
+  if (T < 1 || T > 1000 || n_cg < 0 || n_cg > 100000) return fail(MRX_EINVAL, "modl_backward: T or n_cg out of range");
+  mrx_status st = net_ready(p, "modl_backward");
+  if (st != MRX_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ni = p->n_image;
+  const float2* X = (const float2*)states;
+  float2* z = (float2*)(p->ws + p->ws_z);
+  float2* gcur = (float2*)(p->ws + p->ws_gimg[0]);
+  float2* gz = (float2*)(p->ws + p->ws_gimg[1]);
+  float2* v = (float2*)(p->ws + p->ws_vimg);
+  float* part = (float*)(p->ws + p->ws_part);
+  hipError_t e = copy_c((const float2*)g_out, gcur, ni, s);
+  if (e != hipSuccess) return hip_fail(e, "modl_backward: copy");
+  if (g_aHy && !accumulate) {
+    e = fill_u32((uint32_t*)g_aHy, 0u, 2 * ni, s);
+    if (e != hipSuccess) return hip_fail(e, "modl_backward: clear");
+  }
+  for (int t = T - 1; t >= 0; --t) {
+    const float2* xt = X + (int64_t)t * ni;
+    const float2* xn = X + (int64_t)(t + 1) * ni;
+    st = cnn_fwd(p, xt, z, s);  // recompute z_t and the activations at x_t
+    if (st != MRX_OK) return st;
+    st = cg_impl(p, gcur, nullptr, (const float2*)S, mask, lambda, n_cg, v, nullptr, s);
+    if (st != MRX_OK) return st;
+    CgElemArgs a = elem_args(p, lambda);
+    a.aHy = xn;
+    a.z = z;
+    a.x = v;
+    e = cg_bwd_tail(a, gz, g_lambda ? part : nullptr, s);
+    if (e == hipSuccess && g_lambda) e = slice_sum(a, part, g_lambda, (accumulate || t < T - 1) ? 1 : 0, s);
+    if (e == hipSuccess && g_aHy) e = axpy_c(v, (float2*)g_aHy, ni, s);
+    if (e != hipSuccess) return hip_fail(e, "modl_backward: dc tail");
+    st = cnn_bwd(p, xt, gz, gcur, g, (accumulate || t < T - 1) ? 1 : 0, s);
+    if (st != MRX_OK) return st;
+  }
+  if (g_aHy) {
+    e = axpy_c(gcur, (float2*)g_aHy, ni, s);
+    if (e != hipSuccess) return hip_fail(e, "modl_backward: tail");
+  }
+  return MRX_OK;
+}
+
+mrx_status mrx_mse_grad(mrx_plan p, const float* x, const float* ref, float* g, float* loss, void* stream) {
+  if (!p) return fail(MRX_EINVAL, "mse_grad: null plan");
+  if (!x || !ref) return fail(MRX_EINVAL, "mse_grad: null data pointer");
+  if (!p->ws) return fail(MRX_ENOWORKSPACE, "mse_grad: workspace not set");
+  if (!(p->flags & MRX_PLAN_NETWORK)) return fail(MRX_ENOWORKSPACE, "mse_grad: plan needs MRX_PLAN_NETWORK");
+  hipStream_t s = (hipStream_t)stream;
+  float* part = (float*)(p->ws + p->ws_loss);
+  const float scale = 1.0f / (float)p->n_image;
+  hipLaunchKernelGGL(k_mse, dim3(p->nrr, p->B), dim3(256), 0, s, p->d_desc, p->d_all, (const float2*)x,
+                     (const float2*)ref, (float2*)g, part, p->nrr, scale);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && loss) {
+    hipLaunchKernelGGL(k_mse_total, dim3(1), dim3(64), 0, s, part, p->B * p->nrr, scale, loss);
+    e = hipGetLastError();
+  }
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "mse_grad");
+}
+
+mrx_status mrx_adam_step(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                         float eps, int32_t step, void* stream) {
+  if (!w || !g || !m || !v) return fail(MRX_EINVAL, "adam_step: null pointer");
+  if (n < 0) return fail(MRX_EINVAL, "adam_step: negative size");
+  if (step < 1) return fail(MRX_EINVAL, "adam_step: step counts from 1");
+  if (n == 0) return MRX_OK;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w, g, m, v, n,
+                     lr, b1, b2, eps, c1, c2);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "adam_step");
+}
+
+}  // extern "C"

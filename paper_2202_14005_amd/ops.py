@@ -32,7 +32,7 @@ class Plan:
     ``H``, ``W``, ``C`` are ints (even batch of ``B`` slices) or per-slice
     sequences (uneven batch)."""
 
-    def __init__(self, H, W, C, B: int | None = None, device=None):
+    def __init__(self, H, W, C, B: int | None = None, device=None, network: bool = False):
         L = lib()
         if isinstance(H, int):
             if B is None:
@@ -50,7 +50,10 @@ class Plan:
         arr = lambda v: (ctypes.c_int32 * len(v))(*v)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            check(L.mrx_plan_create(ctypes.byref(h), self.B, arr(Hs), arr(Ws), arr(Cs), 0), "plan_create")
+            check(L.mrx_plan_create(ctypes.byref(h), self.B, arr(Hs), arr(Ws), arr(Cs), 1 if network else 0),
+                  "plan_create")
+        self.network = network
+        self._weights_key = None
         self._h = h
         ni, nc, nm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         check(L.mrx_plan_sizes(h, ctypes.byref(ni), ctypes.byref(nc), ctypes.byref(nm)), "plan_sizes")
@@ -181,6 +184,195 @@ class Plan:
 
     def schedule(self, b=0):
         return lib().mrx_plan_schedule(self._h, int(b)).decode()
+
+
+    # ------------------------------------------------------------- network
+    def set_weights(self, cnn: "CNN", force=False):
+        """Pack the denoiser weights (bf16 MFMA fragments) into the workspace;
+        skipped when the same weights (same tensors and version) are packed."""
+        key = cnn.key()
+        if force or key != self._weights_key:
+            check(lib().mrx_cnn_set_weights(self._h, ctypes.byref(cnn.c_params()), _stream(self.device)),
+                  "cnn_set_weights")
+            self._weights_key = key
+
+    def cnn_forward(self, x, cnn: "CNN", out=None):
+        """z = x + N(x)."""
+        self._img(x, "x")
+        self.set_weights(cnn)
+        z = self._img(out, "out") if out is not None else self._empty_img()
+        check(lib().mrx_cnn_forward(self._h, _ptr(x), _ptr(z), _stream(self.device)), "cnn_forward")
+        return z
+
+    def cnn_layer_forward(self, layer, a_in, cnn: "CNN", out=None):
+        """One 64-channel layer on bf16 NHWC activations (torch.bfloat16
+        tensors of n_image * 64 elements)."""
+        self.set_weights(cnn)
+        if a_in.dtype != torch.bfloat16 or a_in.numel() != self.n_image * 64 or not a_in.is_contiguous():
+            raise ValueError("a_in must be a contiguous bfloat16 tensor of n_image * 64 elements")
+        out = torch.empty_like(a_in) if out is None else out
+        check(lib().mrx_cnn_layer_forward(self._h, int(layer), _ptr(a_in), _ptr(out), _stream(self.device)),
+              "cnn_layer_forward")
+        return out
+
+    def cnn_backward(self, x, gz, cnn: "CNN", grads: "CNNGrads", accumulate=False):
+        """Returns gx = gz + J_N(x)^T gz; weight gradients into grads."""
+        self._img(x, "x"); self._img(gz, "gz")
+        self.set_weights(cnn)
+        gx = self._empty_img()
+        check(lib().mrx_cnn_backward(self._h, _ptr(x), _ptr(gz), _ptr(gx), ctypes.byref(grads.c_grads()),
+                                     int(bool(accumulate)), _stream(self.device)), "cnn_backward")
+        return gx
+
+    def modl_forward(self, aHy, S, mask, cnn: "CNN", lam, T, n_cg, states=False):
+        self._img(aHy, "aHy"); self._coil(S, "S"); self._mask(mask, "mask")
+        self.set_weights(cnn)
+        lt = self.lam(lam)
+        x = self._empty_img()
+        st = (torch.empty((T + 1,) + tuple(x.shape), dtype=torch.complex64, device=self.device)
+              if states else None)
+        check(lib().mrx_modl_forward(self._h, _ptr(aHy), _ptr(S), _ptr(mask), _ptr(lt), int(T), int(n_cg),
+                                     _ptr(x), _ptr(st), _stream(self.device)), "modl_forward")
+        return (x, st) if states else x
+
+    def modl_backward(self, g_out, states, aHy, S, mask, cnn: "CNN", lam, T, n_cg, grads: "CNNGrads",
+                      accumulate=False, need_aHy=False):
+        """Returns (g_lambda [B], g_aHy or None); weight gradients into grads."""
+        self._img(g_out, "g_out"); self._img(aHy, "aHy"); self._coil(S, "S"); self._mask(mask, "mask")
+        self.set_weights(cnn)
+        lt = self.lam(lam)
+        gl = torch.zeros(self.B, dtype=torch.float32, device=self.device)
+        ga = self._empty_img() if need_aHy else None
+        check(lib().mrx_modl_backward(self._h, _ptr(g_out), _ptr(states), _ptr(aHy), _ptr(S), _ptr(mask),
+                                      _ptr(lt), int(T), int(n_cg), ctypes.byref(grads.c_grads()), _ptr(gl),
+                                      _ptr(ga), int(bool(accumulate)), _stream(self.device)), "modl_backward")
+        return gl, ga
+
+    def mse_grad(self, x, ref):
+        """Returns (loss as a device float tensor [1], gradient)."""
+        self._img(x, "x"); self._img(ref, "ref")
+        g = self._empty_img()
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        check(lib().mrx_mse_grad(self._h, _ptr(x), _ptr(ref), _ptr(g), _ptr(loss), _stream(self.device)),
+              "mse_grad")
+        return loss, g
+
+
+def _cuda(device):
+    return torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+
+
+class CNN:
+    """fp32 master weights of the 5-layer 3x3 denoiser (channels 2-64-64-64-64-2),
+    W[l] [C_out, C_in, 3, 3] and b[l] [C_out], on the device."""
+
+    CHANNELS = (2, 64, 64, 64, 64, 2)
+
+    def __init__(self, weights, biases):
+        self.w = [w.contiguous() for w in weights]
+        self.b = [b.contiguous() for b in biases]
+        self.version = 0
+        for l, (w, b) in enumerate(zip(self.w, self.b)):
+            co, ci = self.CHANNELS[l + 1], self.CHANNELS[l]
+            if tuple(w.shape) != (co, ci, 3, 3) or tuple(b.shape) != (co,):
+                raise ValueError(f"layer {l}: expected W {(co, ci, 3, 3)} and b {(co,)}")
+            if w.dtype != torch.float32 or b.dtype != torch.float32:
+                raise TypeError("weights must be float32")
+
+    @classmethod
+    def from_numpy(cls, wb, device=None):
+        dev = _cuda(device)
+        return cls([torch.from_numpy(w).to(dev) for w, _ in wb], [torch.from_numpy(b).to(dev) for _, b in wb])
+
+    @classmethod
+    def init(cls, seed=7, device=None, last_scale=1.0):
+        from synthetic import cnn_weights
+        return cls.from_numpy(cnn_weights(seed, last_scale=last_scale), device)
+
+    def params(self):
+        out = []
+        for w, b in zip(self.w, self.b):
+            out += [w, b]
+        return out
+
+    def key(self):
+        return (self.version,) + tuple((t.data_ptr(), t._version) for t in self.params())
+
+    def c_params(self):
+        from ._lib import CnnParams
+        p = CnnParams()
+        for l in range(5):
+            p.w[l] = self.w[l].data_ptr()
+            p.b[l] = self.b[l].data_ptr()
+        return p
+
+    def numpy(self):
+        return [(w.detach().cpu().numpy(), b.detach().cpu().numpy()) for w, b in zip(self.w, self.b)]
+
+
+class CNNGrads:
+    """Gradient buffers shaped like a CNN's parameters."""
+
+    def __init__(self, cnn: CNN):
+        self.w = [torch.zeros_like(w) for w in cnn.w]
+        self.b = [torch.zeros_like(b) for b in cnn.b]
+
+    def c_grads(self):
+        from ._lib import CnnGrads
+        g = CnnGrads()
+        for l in range(5):
+            g.w[l] = self.w[l].data_ptr()
+            g.b[l] = self.b[l].data_ptr()
+        return g
+
+    def params(self):
+        out = []
+        for w, b in zip(self.w, self.b):
+            out += [w, b]
+        return out
+
+
+class Adam:
+    """Adam state over a CNN's parameters, stepped by the library kernel."""
+
+    def __init__(self, cnn: CNN, lr=1e-4, b1=0.9, b2=0.999, eps=1e-8):
+        self.cnn, self.lr, self.b1, self.b2, self.eps = cnn, lr, b1, b2, eps
+        self.m = [torch.zeros_like(p) for p in cnn.params()]
+        self.v = [torch.zeros_like(p) for p in cnn.params()]
+        self.t = 0
+
+    def step(self, grads: CNNGrads):
+        self.t += 1
+        stream = _stream(self.cnn.w[0].device)
+        for p, g, m, v in zip(self.cnn.params(), grads.params(), self.m, self.v):
+            check(lib().mrx_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), self.lr, self.b1, self.b2,
+                                      self.eps, self.t, stream), "adam_step")
+        self.cnn.version += 1  # the packed bf16 copies are now stale
+
+
+class MoDL:
+    """MoDL network: x^0 = A^H y, T unrolls of [denoiser, CG data consistency]."""
+
+    def __init__(self, plan: Plan, cnn: CNN, lam=0.05, T=5, n_cg=10):
+        if not plan.network:
+            raise ValueError("MoDL needs a plan created with network=True")
+        self.plan, self.cnn, self.lam, self.T, self.n_cg = plan, cnn, lam, T, n_cg
+
+    def forward(self, y, S, mask, states=False):
+        aHy = self.plan.sense_adj(y, S, mask)
+        return self.plan.modl_forward(aHy, S, mask, self.cnn, self.lam, self.T, self.n_cg, states=states)
+
+    def train_step(self, y, S, mask, x_ref, grads: CNNGrads, opt: Adam):
+        """One training step: forward with stored states, MSE loss, reverse
+        pass (adjoint CG + recomputed denoiser activations), Adam.
+        Returns the loss as a device tensor."""
+        p = self.plan
+        aHy = p.sense_adj(y, S, mask)
+        xT, states = p.modl_forward(aHy, S, mask, self.cnn, self.lam, self.T, self.n_cg, states=True)
+        loss, g = p.mse_grad(xT, x_ref)
+        p.modl_backward(g, states, aHy, S, mask, self.cnn, self.lam, self.T, self.n_cg, grads)
+        opt.step(grads)
+        return loss
 
 
 def supported_length(n: int) -> bool:

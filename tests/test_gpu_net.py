@@ -1,0 +1,180 @@
+"""Parity of the HIP denoiser (bf16 MFMA convolutions), the MoDL unrolled
+network and its reverse pass, the MSE gradient and Adam against the FP64
+oracle, through the C-ABI.
+
+Tolerances: network outputs NRMSE <= 1e-2 against the plain FP64 oracle
+(bf16 operands, fp32 accumulation).  Reverse-mode results are compared with
+the oracle run with bf16-rounded convolution operands (oracle.cnn, bf16=True),
+because the ReLU derivative is a decision on a rounded value and has to be
+taken in the same precision on both sides; what remains is fp32-vs-fp64
+accumulation and rare differences of one bf16 rounding step, bound 5e-3.
+Against the plain FP64 oracle the reverse pass differs by the ReLU decisions
+that flip under bf16 rounding of the pre-activations (a fraction ~2^-9 of
+positions per layer, contributing about sqrt of that fraction in relative L2
+per layer), bound 0.2.  Elementwise fp32 kernels (MSE, Adam): 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adam as oadam
+from oracle import cnn as ocnn
+from oracle import modl as omodl
+from oracle import sense as osense
+from paper_2202_14005_amd import ops
+from synthetic import cnn_weights
+from tests.gpu_util import dev, host, inputs, rel, uneven
+
+pytestmark = pytest.mark.gpu
+
+NET_TOL = 1e-2
+GRAD_TOL = 5e-3       # against the bf16-operand oracle
+GRAD_TOL_FP64 = 0.2   # against the plain FP64 oracle
+# MoDL reverse pass: the unroll states x^t (t > 0) entering the denoiser
+# already differ by the fp32 CG error (~1e-5), so a fraction of their bf16
+# roundings and ReLU decisions cannot be matched by any oracle; over T
+# unrolls this leaves ~1e-2 relative on the weight gradients.
+MODL_GRAD_TOL = 2e-2
+
+
+def weights(seed=7, last_scale=1.0):
+    return cnn_weights(seed, last_scale=last_scale)
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 48, 40), (1, 320, 320), (2, 24, 16), (1, 96, 128)])
+def test_cnn_forward_parity(B, H, W):
+    d = inputs([300 + i for i in range(B)], H, W, 2)
+    w = weights()
+    plan = ops.Plan(H, W, 2, B=B, network=True)
+    cnn = ops.CNN.from_numpy(w)
+    z = host(plan.cnn_forward(dev(d["x"]), cnn))
+    zref = ocnn.denoise(d["x"], w)
+    nref = zref - d["x"]
+    e_z, e_n = rel(z, zref), rel(z - d["x"], nref)
+    print(f"cnn fwd {B}x{H}x{W}: NRMSE z {e_z:.2e}, N(x) {e_n:.2e}")
+    assert e_z < NET_TOL
+    assert e_n < NET_TOL
+
+
+def test_cnn_backward_parity():
+    B, H, W = 2, 48, 40
+    d = inputs([310, 311], H, W, 2)
+    w = weights()
+    rng = np.random.default_rng(5)
+    gz = (rng.standard_normal((B, H, W)) + 1j * rng.standard_normal((B, H, W))).astype(np.complex64)
+    plan = ops.Plan(H, W, 2, B=B, network=True)
+    cnn = ops.CNN.from_numpy(w)
+    grads = ops.CNNGrads(cnn)
+    gx = host(plan.cnn_backward(dev(d["x"]), dev(gz), cnn, grads))
+    gx_ref, gw_ref = ocnn.denoise_backward(d["x"], w, gz, bf16=True)
+    gx64, gw64 = ocnn.denoise_backward(d["x"], w, gz)
+    e, e64 = rel(gx - gz, gx_ref - gz), rel(gx - gz, gx64 - gz)
+    print(f"cnn bwd J^T gz: vs bf16-operand oracle {e:.2e}, vs fp64 oracle {e64:.2e}")
+    assert e < GRAD_TOL
+    assert e64 < GRAD_TOL_FP64
+    for l in range(5):
+        ew = rel(host(grads.w[l]), gw_ref[l][0])
+        eb = rel(host(grads.b[l]), gw_ref[l][1])
+        ew64 = rel(host(grads.w[l]), gw64[l][0])
+        print(f"layer {l}: dW {ew:.2e} db {eb:.2e} (dW vs fp64 {ew64:.2e})")
+        assert ew < GRAD_TOL and eb < GRAD_TOL
+        assert ew64 < GRAD_TOL_FP64
+    # accumulate flag adds
+    plan.cnn_backward(dev(d["x"]), dev(gz), cnn, grads, accumulate=True)
+    assert rel(host(grads.w[2]), 2 * gw_ref[2][0]) < GRAD_TOL
+
+
+def test_cnn_uneven_batch():
+    shapes = [(48, 40, 2), (32, 64, 2), (96, 48, 2)]
+    sl, pk = uneven(shapes, seed0=700)
+    w = weights()
+    plan = ops.Plan([s[0] for s in shapes], [s[1] for s in shapes], [s[2] for s in shapes], network=True)
+    cnn = ops.CNN.from_numpy(w)
+    z = host(plan.cnn_forward(dev(pk["x"]), cnn))
+    o = 0
+    for (H, W, _), s in zip(shapes, sl):
+        zref = ocnn.denoise(s["x"][None], w)
+        assert rel(z[o:o + H * W], zref) < NET_TOL
+        o += H * W
+
+
+def modl_case(B, H, W, C, seed=400):
+    d = inputs([seed + i for i in range(B)], H, W, C)
+    y = osense.measure(d["x"], d["S"], d["mask"], d["noise"])
+    aHy = osense.sense_adj(y, d["S"], d["mask"]).astype(np.complex64)
+    return d, aHy
+
+
+@pytest.mark.parametrize("B,H,W,C,T", [(2, 48, 40, 4, 2), (1, 320, 320, 15, 5)])
+def test_modl_forward_parity(B, H, W, C, T):
+    d, aHy = modl_case(B, H, W, C)
+    w = weights(last_scale=0.1)
+    lam = np.full(B, 0.05, dtype=np.float32)
+    plan = ops.Plan(H, W, C, B=B, network=True)
+    cnn = ops.CNN.from_numpy(w)
+    x, st = plan.modl_forward(dev(aHy), dev(d["S"]), dev(d["mask"]), cnn, torch.tensor(lam), T, 10, states=True)
+    xref, sref, _ = omodl.forward(aHy, d["S"], d["mask"], w, lam, T, 10)
+    e = rel(host(x), xref)
+    print(f"modl fwd {B}x{H}x{W} T={T}: NRMSE {e:.2e}")
+    assert e < NET_TOL
+    assert np.array_equal(host(st)[T], host(x))
+    assert np.array_equal(host(st)[0], aHy)
+
+
+def test_modl_backward_parity():
+    B, H, W, C, T = 2, 48, 40, 4, 2
+    d, aHy = modl_case(B, H, W, C, seed=420)
+    w = weights(last_scale=0.1)
+    lam = np.full(B, 0.05, dtype=np.float32)
+    plan = ops.Plan(H, W, C, B=B, network=True)
+    cnn = ops.CNN.from_numpy(w)
+    S, m = dev(d["S"]), dev(d["mask"])
+    xT, st = plan.modl_forward(dev(aHy), S, m, cnn, torch.tensor(lam), T, 10, states=True)
+    loss, g = plan.mse_grad(xT, dev(d["x"]))
+    grads = ops.CNNGrads(cnn)
+    gl, ga = plan.modl_backward(g, st, dev(aHy), S, m, cnn, torch.tensor(lam), T, 10, grads, need_aHy=True)
+    xr, sr, zr = omodl.forward(aHy, d["S"], d["mask"], w, lam, T, 10, bf16=True)
+    gref = omodl.mse_grad(xr, d["x"])
+    gw_ref, gl_ref, ga_ref = omodl.backward(gref, sr, zr, aHy, d["S"], d["mask"], w, lam, T, 10, bf16=True)
+    assert abs(float(host(loss)[0]) - omodl.mse(xr, d["x"])) < NET_TOL * omodl.mse(xr, d["x"])
+    for l in range(5):
+        ew = rel(host(grads.w[l]), gw_ref[l][0])
+        eb = rel(host(grads.b[l]), gw_ref[l][1])
+        print(f"modl layer {l}: dW {ew:.2e} db {eb:.2e}")
+        assert ew < MODL_GRAD_TOL and eb < MODL_GRAD_TOL
+    el = np.max(np.abs(host(gl) - gl_ref) / np.abs(gl_ref))
+    ea = rel(host(ga), ga_ref)
+    print(f"modl g_lambda {el:.2e} g_aHy {ea:.2e}")
+    assert el < MODL_GRAD_TOL and ea < MODL_GRAD_TOL
+
+
+def test_mse_grad_parity():
+    B, H, W = 2, 64, 48
+    d = inputs([500, 501], H, W, 2)
+    rng = np.random.default_rng(9)
+    x = (d["x"] + 0.1 * rng.standard_normal(d["x"].shape)).astype(np.complex64)
+    plan = ops.Plan(H, W, 2, B=B, network=True)
+    loss, g = plan.mse_grad(dev(x), dev(d["x"]))
+    assert abs(float(host(loss)[0]) - omodl.mse(x, d["x"])) < 1e-5 * omodl.mse(x, d["x"])
+    assert rel(host(g), omodl.mse_grad(x, d["x"])) < 1e-6
+
+
+def test_adam_parity():
+    w = cnn_weights(3)
+    cnn = ops.CNN.from_numpy(w)
+    opt = ops.Adam(cnn, lr=1e-3)
+    rng = np.random.default_rng(2)
+    grads = ops.CNNGrads(cnn)
+    ref = [p.copy().astype(np.float64) for pair in w for p in pair]
+    m = [np.zeros_like(r) for r in ref]
+    v = [np.zeros_like(r) for r in ref]
+    for t in range(1, 4):
+        gs = [rng.standard_normal(r.shape).astype(np.float32) for r in ref]
+        for gt, g in zip(grads.params(), gs):
+            gt.copy_(torch.from_numpy(g))
+        opt.step(grads)
+        for i in range(len(ref)):
+            ref[i], m[i], v[i] = oadam.step(ref[i], gs[i], m[i], v[i], t, lr=1e-3)
+    for p, r in zip(cnn.params(), ref):
+        assert np.max(np.abs(host(p) - r)) < 1e-6
+    assert cnn.version == 3

@@ -172,3 +172,22 @@ def test_adam_constant_gradient_moves_lr_per_step(rng):
     for t in range(1, 6):
         w, m, v = adam.step(w, g, m, v, t, lr=1e-2, eps=0.0)
     assert np.max(np.abs(w - (w0 - 5 * 1e-2 * np.sign(g)))) < 1e-12
+
+
+def test_bf16_rounding_matches_torch_and_ties_to_even(rng):
+    import torch
+    a = rng.standard_normal(1000).astype(np.float32) * 10.0 ** rng.integers(-5, 5, 1000)
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(cnn.bf16_round(a), ref)
+    one_plus_half_ulp = np.float32(1.0 + 2.0 ** -8)   # halfway between 1 and 1 + 2^-7
+    three_halves = np.float32(1.0 + 3 * 2.0 ** -8)     # halfway between 1 + 2^-7 and 1 + 2^-6
+    assert cnn.bf16_round(one_plus_half_ulp) == 1.0
+    assert cnn.bf16_round(three_halves) == 1.0 + 2.0 ** -6
+
+
+def test_bf16_mode_is_close_to_fp64(rng):
+    x = rand_c(rng, 1, 12, 10)
+    w = small_weights(rng)
+    a = cnn.denoise(x, w)
+    b = cnn.denoise(x, w, bf16=True)
+    assert 0 < np.linalg.norm(a - b) / np.linalg.norm(a) < 2e-2
