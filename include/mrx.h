@@ -59,6 +59,18 @@ typedef struct mrx_plan_s* mrx_plan;
 
 /* mrx_plan_create flags */
 #define MRX_PLAN_NETWORK 1u /* also reserve workspace for the CNN / MoDL calls */
+#define MRX_PLAN_VN 2u      /* also reserve workspace for the VarNet stage calls */
+
+/*
+ * Parameters of one variational-network stage (device pointers): k = 24
+ * complex 11 x 11 filters, interleaved [24][11][11][re, im]; w = RBF weights
+ * [24][31]; lam = the stage's step size (1 float).
+ */
+typedef struct {
+  const float* k;
+  const float* w;
+  const float* lam;
+} mrx_vn_params;
 
 /*
  * Denoiser parameters: fp32 master weights of the five 3x3 convolution
@@ -88,7 +100,8 @@ const char* mrx_last_error(void);
  * 1 <= C <= 64.  Creates device tables (shape table, twiddles) with hipMalloc
  * on the current device; this is the only allocating call.  Returns
  * MRX_EUNSUPPORTED for sizes without a schedule, MRX_EINVAL for bad counts.
- * flags: 0, or MRX_PLAN_NETWORK to size the workspace for the network calls.
+ * flags: 0, or MRX_PLAN_NETWORK and/or MRX_PLAN_VN to size the workspace
+ * for the MoDL network calls and the VarNet stage calls.
  */
 mrx_status mrx_plan_create(mrx_plan* plan, int32_t B, const int32_t* H, const int32_t* W,
                            const int32_t* C, uint32_t flags);
@@ -242,6 +255,29 @@ mrx_status mrx_mse_grad(mrx_plan plan, const float* x, const float* ref, float* 
 mrx_status mrx_adam_step(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                          float b2, float eps, int32_t step, void* stream);
 
+/*
+ * One variational-network stage (Variational Network subsection, eq.
+ * update_vn):
+ *   x_next = x - sum_i K_i^T Phi'_i(Re(k_i * x)) - lambda (A^H A x - aHy)
+ * with 24 complex 11 x 11 filters (cross-correlation, zero "same" padding),
+ * Phi'_i(s) = sum_j w_ij exp(-(s - mu_j)^2 / (2 sigma^2)), 31 knots mu_j on
+ * [-1, 1], sigma = the knot spacing.  fp32 throughout.  Needs a plan created
+ * with MRX_PLAN_VN.  x, aHy, x_next image-sized complex; x_next must not
+ * alias x.
+ */
+mrx_status mrx_vn_stage(mrx_plan plan, const float* x, const float* aHy, const float* S,
+                        const float* mask, const mrx_vn_params* p, float* x_next, void* stream);
+/*
+ * Reverse mode of mrx_vn_stage at x with upstream gradient g:
+ *   g_x = g - K^T(Phi''(Kx) * Kg) - lambda A^H A g,
+ *   g_k (complex [24][11][11]), g_w ([24][31]) and g_lam (1 float) written,
+ *   or added to if accumulate != 0.  Gradients in the DF^H(1) convention.
+ */
+mrx_status mrx_vn_stage_backward(mrx_plan plan, const float* g, const float* x, const float* aHy,
+                                 const float* S, const float* mask, const mrx_vn_params* p,
+                                 float* g_x, float* g_k, float* g_w, float* g_lam,
+                                 int32_t accumulate, void* stream);
+
 /* Choose the fastest registered schedule per distinct length of the plan by
  * timing each on the given stream (synchronises the host).  The choice is
  * kept in the plan and in an in-process cache keyed by (H, W, C). */
@@ -249,6 +285,10 @@ mrx_status mrx_plan_autotune(mrx_plan plan, const float* S, const float* mask, f
                              float* scratch_b, void* stream);
 /* Name of the schedule the plan uses for slice b's column transform. */
 const char* mrx_plan_schedule(mrx_plan plan, int32_t b);
+/* Name of the idx-th registered column schedule for length n, or NULL. */
+const char* mrx_schedule_name(int32_t n, int32_t idx);
+/* Force the column schedule `name` for the slices of the plan with H = n. */
+mrx_status mrx_plan_set_schedule(mrx_plan plan, int32_t n, const char* name);
 
 #ifdef __cplusplus
 }

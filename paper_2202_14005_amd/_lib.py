@@ -49,6 +49,10 @@ SIGNATURES = {
     "mrx_mse_grad": (c_int32, [P, P, P, P, P, P]),
     "mrx_adam_step": (c_int32, [P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "mrx_plan_schedule": (c_char_p, [P, c_int32]),
+    "mrx_schedule_name": (c_char_p, [c_int32, c_int32]),
+    "mrx_vn_stage": (c_int32, [P, P, P, P, P, P, P, P]),
+    "mrx_vn_stage_backward": (c_int32, [P, P, P, P, P, P, P, P, P, P, P, c_int32, P]),
+    "mrx_plan_set_schedule": (c_int32, [P, c_int32, c_char_p]),
 }
 
 STATUS = {0: "MRX_OK", -1: "MRX_EINVAL", -2: "MRX_EUNSUPPORTED", -3: "MRX_ENOMEM",
@@ -57,6 +61,10 @@ STATUS = {0: "MRX_OK", -1: "MRX_EINVAL", -2: "MRX_EUNSUPPORTED", -3: "MRX_ENOMEM
 
 class CnnParams(ctypes.Structure):
     _fields_ = [("w", c_void_p * 5), ("b", c_void_p * 5)]
+
+
+class VnParams(ctypes.Structure):
+    _fields_ = [("k", c_void_p), ("w", c_void_p), ("lam", c_void_p)]
 
 
 class CnnGrads(ctypes.Structure):

@@ -22,33 +22,44 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmrx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# name, N1, N2, N3, threads per transform, column tile width, row tile height
-# (the first schedule listed for a length is its default)
+# name, N1, N2, N3, threads per transform T, column tile width, row tile
+# height, coil groups per normal-operator workgroup, keep coil values in
+# registers (1) or re-read them from L2 (0).
+# The first schedule listed for a length is its default; the autotuner
+# times all schedules of a length on the normal operator.
 SCHEDULES = [
-    ("n16_4x4_t4", 4, 4, 1, 4, 16, 16),
-    ("n24_4x6_t2", 4, 6, 1, 2, 32, 32),
-    ("n32_4x8_t4", 4, 8, 1, 4, 16, 16),
-    ("n40_4x10_t2", 4, 10, 1, 2, 32, 32),
-    ("n48_4x12_t4", 4, 12, 1, 4, 16, 16),
-    ("n64_8x8_t8", 8, 8, 1, 8, 16, 16),
-    ("n80_4x4x5_t4", 4, 4, 5, 4, 16, 16),
-    ("n96_4x4x6_t8", 4, 4, 6, 8, 16, 16),
-    ("n128_4x4x8_t16", 4, 4, 8, 16, 16, 16),
-    ("n128_8x16_t8", 8, 16, 1, 8, 16, 16),
-    ("n160_4x4x10_t8", 4, 4, 10, 8, 16, 16),
-    ("n192_4x4x12_t16", 4, 4, 12, 16, 16, 16),
-    ("n192_8x24_t8", 8, 24, 1, 8, 16, 16),
-    ("n256_4x4x16_t16", 4, 4, 16, 16, 16, 16),
-    ("n256_16x16_t16", 16, 16, 1, 16, 16, 16),
-    ("n320_4x4x20_t16", 4, 4, 20, 16, 16, 16),
-    ("n320_8x40_t8", 8, 40, 1, 8, 16, 16),
-    ("n384_4x4x24_t16", 4, 4, 24, 16, 16, 16),
-    ("n384_16x24_t8", 16, 24, 1, 8, 16, 16),
-    ("n512_4x8x16_t32", 4, 8, 16, 32, 8, 8),
+    ("n16_4x4_t4", 4, 4, 1, 4, 16, 16, 1, 1),
+    ("n24_4x6_t2", 4, 6, 1, 2, 32, 32, 1, 1),
+    ("n32_4x8_t4", 4, 8, 1, 4, 16, 16, 1, 1),
+    ("n40_4x10_t2", 4, 10, 1, 2, 32, 32, 1, 1),
+    ("n48_4x12_t4", 4, 12, 1, 4, 16, 16, 1, 1),
+    ("n64_8x8_t8", 8, 8, 1, 8, 16, 16, 1, 1),
+    ("n80_4x4x5_t4", 4, 4, 5, 4, 16, 16, 1, 1),
+    ("n96_4x4x6_t8", 4, 4, 6, 8, 16, 16, 1, 1),
+    ("n128_4x4x8_t16_w16_g2_rl", 4, 4, 8, 16, 16, 16, 2, 0),
+    ("n128_4x4x8_t16_w8_g3_rl", 4, 4, 8, 16, 8, 16, 3, 0),
+    ("n128_4x4x8_t16_w16", 4, 4, 8, 16, 16, 16, 1, 1),
+    ("n160_4x4x10_t8_w16_g2_rl", 4, 4, 10, 8, 16, 16, 2, 0),
+    ("n192_4x4x12_t16_w16_g2_rl", 4, 4, 12, 16, 16, 16, 2, 0),
+    ("n192_4x4x12_t16_w8_g3_rl", 4, 4, 12, 16, 8, 16, 3, 0),
+    ("n192_4x4x12_t16_w16", 4, 4, 12, 16, 16, 16, 1, 1),
+    ("n256_4x4x16_t16_w16_g2_rl", 4, 4, 16, 16, 16, 16, 2, 0),
+    ("n256_4x4x16_t16_w8_g3_rl", 4, 4, 16, 16, 8, 16, 3, 0),
+    ("n256_4x4x16_t16_w16", 4, 4, 16, 16, 16, 16, 1, 1),
+    ("n320_4x4x20_t16_w16_g2_rl", 4, 4, 20, 16, 16, 16, 2, 0),
+    ("n320_4x4x20_t16_w16_g3_rl", 4, 4, 20, 16, 16, 16, 3, 0),
+    ("n320_4x4x20_t16_w8_g3_rl", 4, 4, 20, 16, 8, 16, 3, 0),
+    ("n320_4x4x20_t16_w8_g4_rl", 4, 4, 20, 16, 8, 16, 4, 0),
+    ("n320_8x40_t8_w16_g2_rl", 8, 40, 1, 8, 16, 16, 2, 0),
+    ("n320_4x4x20_t16_w16", 4, 4, 20, 16, 16, 16, 1, 1),
+    ("n384_4x4x24_t16_w16_g2_rl", 4, 4, 24, 16, 16, 16, 2, 0),
+    ("n384_4x4x24_t16_w8_g3_rl", 4, 4, 24, 16, 8, 16, 3, 0),
+    ("n384_4x4x24_t16_w16", 4, 4, 24, 16, 16, 16, 1, 1),
+    ("n512_4x8x16_t32_w8", 4, 8, 16, 32, 8, 8, 1, 1),
 ]
 
 COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net.hip", "conv.hip",
-                  "conv_wgrad.hip"]
+                  "conv_wgrad.hip", "vn.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -68,9 +79,10 @@ def _jobs():
     jobs = []
     for s in srcs:
         jobs.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".hip", ".o")), []))
-    for name, n1, n2, n3, t, wtc, wtr in SCHEDULES:
+    for name, n1, n2, n3, t, wtc, wtr, g, ks in SCHEDULES:
         defs = [f"-DMRX_N1={n1}", f"-DMRX_N2={n2}", f"-DMRX_N3={n3}", f"-DMRX_T={t}",
-                f"-DMRX_WTC={wtc}", f"-DMRX_WTR={wtr}", f'-DMRX_NAME="{name}"']
+                f"-DMRX_WTC={wtc}", f"-DMRX_WTR={wtr}", f"-DMRX_G={g}", f"-DMRX_KS={ks}",
+                f'-DMRX_NAME="{name}"']
         jobs.append((os.path.join(CSRC, "sense_inst.hip"), os.path.join(BUILD, f"sched_{name}.o"), defs))
     return jobs
 

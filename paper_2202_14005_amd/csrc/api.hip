@@ -83,7 +83,7 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   *out = nullptr;
   if (B <= 0 || B > (1 << 20)) return fail(MRX_EINVAL, "plan_create: batch size must be in [1, 2^20]");
   if (!H || !W || !C) return fail(MRX_EINVAL, "plan_create: null shape array");
-  if (flags & ~MRX_PLAN_NETWORK) return fail(MRX_EINVAL, "plan_create: unknown flags");
+  if (flags & ~(MRX_PLAN_NETWORK | MRX_PLAN_VN)) return fail(MRX_EINVAL, "plan_create: unknown flags");
   auto* p = new mrx_plan_s();
   p->B = B;
   p->flags = flags;
@@ -319,6 +319,23 @@ mrx_status mrx_status_word(mrx_plan p, uint32_t* dev_flags, int32_t clear, void*
     hipError_t e = clear_status(p, s);
     if (e != hipSuccess) return hip_fail(e, "status_word: clear");
   }
+  return MRX_OK;
+}
+
+const char* mrx_schedule_name(int32_t n, int32_t idx) {
+  auto v = col_variants(n);
+  if (idx < 0 || idx >= (int)v.size()) return nullptr;
+  return v[idx]->name;
+}
+
+mrx_status mrx_plan_set_schedule(mrx_plan p, int32_t n, const char* name) {
+  if (!p || !name) return fail(MRX_EINVAL, "plan_set_schedule: null argument");
+  const ColVariant* v = find_col(n, name);
+  if (!v) return fail(MRX_EUNSUPPORTED, std::string("plan_set_schedule: no schedule ") + name);
+  bool any = false;
+  for (auto& g : p->groups)
+    if (g.H == n) { g.col = v; any = true; }
+  if (!any) return fail(MRX_EINVAL, "plan_set_schedule: no slice of the plan has that H");
   return MRX_OK;
 }
 

@@ -49,6 +49,9 @@ struct mrx_plan_s {
   size_t ws_z = 0, ws_ximg[2] = {0, 0}, ws_gimg[2] = {0, 0}, ws_vimg = 0;
   size_t ws_pk = 0, ws_wpart = 0, ws_loss = 0;
   const float* net_b[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // VarNet workspace
+  size_t ws_vn_kt = 0, ws_vn_u = 0, ws_vn_e = 0, ws_vn_kg = 0, ws_vn_s = 0, ws_vn_qx = 0, ws_vn_qg = 0;
+  size_t ws_vn_plam = 0, ws_vn_pk = 0, ws_vn_pw = 0;
   bool net_ready = false;
 };
 
@@ -64,6 +67,7 @@ extern std::mutex g_tune_mu;
 extern std::map<std::tuple<int, int, int>, std::string> g_tune_cache;
 
 size_t extra_workspace_bytes(mrx_plan_s* p);
+size_t vn_workspace_bytes(mrx_plan_s* p, size_t base);
 CgElemArgs elem_args(mrx_plan_s* p, const float* lam);
 hipError_t clear_status(mrx_plan_s* p, hipStream_t s);
 hipError_t fill_u32(uint32_t* dst, uint32_t value, int64_t n, hipStream_t s);

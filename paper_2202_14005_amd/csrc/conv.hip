@@ -27,10 +27,24 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ __forceinline__ uint4 ldg16(const uint16_t* p) { return *(const uint4*)p; }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats -> two bf16 (round to nearest even, v_cvt_pk_bf16_f32), low
+// half first.
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const f32x2_t f = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
+}
+
 // LDS input tile: (16 + 2) x (32 + 2) pixels x 64 channels bf16, as 8 chunks
-// of 16 bytes per pixel; chunk c of pixel p sits at slot c ^ (p & 7) so the
-// 32 lanes reading one chunk of 32 consecutive pixels hit distinct banks.
+// of 16 bytes per pixel (128 bytes = 32 banks).  Chunk c of pixel p sits at
+// slot c ^ ((p >> 1) & 7): 16 consecutive pixels then cover the 64 banks
+// exactly once for a fixed chunk (pixel parity picks the bank half, the slot
+// the 4-bank group), so a 16-lane phase of a 16-byte read is conflict free.
 constexpr int TILE_PX = (CONV_TH + 2) * (CONV_TW + 2);
+
+__device__ __forceinline__ int swz(int px) { return (px >> 1) & 7; }
 
 __device__ __forceinline__ void load_tile64(uint4* tile, const uint16_t* in, int H, int W, int ty0, int tx0) {
   for (int q = threadIdx.x; q < TILE_PX * 8; q += 256) {
@@ -39,23 +53,34 @@ __device__ __forceinline__ void load_tile64(uint4* tile, const uint16_t* in, int
     const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
     uint4 v = make_uint4(0, 0, 0, 0);
     if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = ldg16(in + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
-    tile[px * 8 + (ch ^ (px & 7))] = v;
+    tile[px * 8 + (ch ^ swz(px))] = v;
   }
 }
 
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return (h & 0x8000u) == 0 && h != 0; }
 
 // ------------------------------------------------------------- 64 -> 64
-__global__ void __launch_bounds__(256) k_conv_mid(ConvArgs a) {
+// Two workgroups per CU (2 x 78 KB of LDS, <= 256 registers per lane) so
+// one workgroup's tile fill overlaps the other's MFMAs; the weight fragments
+// of step s + 1 are fetched while step s runs.
+__global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
   __shared__ uint4 tile[TILE_PX * 8];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
   const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
   if (tx0 >= W || ty0 >= H) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint16_t* wp = a.wpk + lane * 8;
+  // ring of the next four steps' weight fragments (step = tap * 4 + kc)
+  uint4 wr[4][2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    wr[k][0] = ldg16(wp + (k * 2 + 0) * 512);
+    wr[k][1] = ldg16(wp + (k * 2 + 1) * 512);
+  }
   load_tile64(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   f32x16 acc[2][4];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
@@ -63,18 +88,23 @@ __global__ void __launch_bounds__(256) k_conv_mid(ConvArgs a) {
     for (int n = 0; n < 4; ++n)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[m][n][v] = 0.f;
-  const uint16_t* wp = a.wpk + lane * 8;
+  const int pbase = wv * 4 * (CONV_TW + 2) + (lane & 31);
   for (int tap = 0; tap < 9; ++tap) {
-    const int dy = tap / 3, dx = tap % 3;
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    const int p0 = pbase + dy * (CONV_TW + 2) + dx;
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
-      const bf16x8 w0 = as_bf16x8(ldg16(wp + ((tap * 4 + kc) * 2 + 0) * 512));
-      const bf16x8 w1 = as_bf16x8(ldg16(wp + ((tap * 4 + kc) * 2 + 1) * 512));
+      const bf16x8 w0 = as_bf16x8(wr[kc][0]), w1 = as_bf16x8(wr[kc][1]);
+      const int nxt = (tap + 1) * 4 + kc;
+      if (nxt < 36) {
+        wr[kc][0] = ldg16(wp + (nxt * 2 + 0) * 512);
+        wr[kc][1] = ldg16(wp + (nxt * 2 + 1) * 512);
+      }
       const int ch = kc * 2 + (lane >> 5);
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        const int px = (wv * 4 + nb + dy) * (CONV_TW + 2) + (lane & 31) + dx;
-        const bf16x8 bv = as_bf16x8(tile[px * 8 + (ch ^ (px & 7))]);
+        const int px = p0 + nb * (CONV_TW + 2);
+        const bf16x8 bv = as_bf16x8(tile[px * 8 + (ch ^ swz(px))]);
         acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, bv, acc[0][nb], 0, 0, 0);
         acc[1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bv, acc[1][nb], 0, 0, 0);
       }
@@ -92,7 +122,7 @@ __global__ void __launch_bounds__(256) k_conv_mid(ConvArgs a) {
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int co0 = m * 32 + 8 * g + (lane >> 5) * 4;
-        uint16_t h[4];
+        float hv[4];
         uint2 mref = make_uint2(0, 0);
         if (a.mode == CONV_DGRAD) mref = *(const uint2*)(rref + po + co0);
 #pragma unroll
@@ -106,11 +136,11 @@ __global__ void __launch_bounds__(256) k_conv_mid(ConvArgs a) {
             const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
             if (!bf_pos(r)) v = 0.f;
           }
-          h[j] = f2bf(v);
+          hv[j] = v;
         }
         uint2 pk;
-        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        pk.x = pack_bf16x2(hv[0], hv[1]);
+        pk.y = pack_bf16x2(hv[2], hv[3]);
         *(uint2*)(out + po + co0) = pk;
       }
   }
@@ -179,7 +209,7 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvArgs a) {
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int co0 = m * 32 + 8 * g + (lane >> 5) * 4;
-        uint16_t h[4];
+        float hv[4];
         uint2 mref = make_uint2(0, 0);
         if (a.mode == CONV_DGRAD) mref = *(const uint2*)(rref + po + co0);
 #pragma unroll
@@ -193,11 +223,11 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvArgs a) {
             const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
             if (!bf_pos(r)) v = 0.f;
           }
-          h[j] = f2bf(v);
+          hv[j] = v;
         }
         uint2 pk;
-        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        pk.x = pack_bf16x2(hv[0], hv[1]);
+        pk.y = pack_bf16x2(hv[2], hv[3]);
         *(uint2*)(out + po + co0) = pk;
       }
   }
@@ -232,7 +262,7 @@ __global__ void __launch_bounds__(256) k_conv_last(ConvArgs a) {
 #pragma unroll
       for (int n = 0; n < 8; ++n) {
         const int px = (wv * 4 + (n >> 1) + dy) * (CONV_TW + 2) + (n & 1) * 16 + (lane & 15) + dx;
-        const bf16x8 bv = as_bf16x8(tile[px * 8 + (ch ^ (px & 7))]);
+        const bf16x8 bv = as_bf16x8(tile[px * 8 + (ch ^ swz(px))]);
         acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, bv, acc[n], 0, 0, 0);
       }
     }

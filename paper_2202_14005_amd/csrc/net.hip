@@ -18,10 +18,16 @@ constexpr int NOUT_FIRST = 64 * 2 * 9 + 64;
 constexpr int NOUT_LAST = 2 * 64 * 9 + 2;
 
 static int bands_of(mrx_plan_s* p) { return (p->maxH + WG_BAND - 1) / WG_BAND; }
+size_t net_workspace_bytes(mrx_plan_s* p);
 
 // Network workspace layout, appended after the SENSE/CG part (flags bit 0).
 size_t extra_workspace_bytes(mrx_plan_s* p) {
-  if (!(p->flags & MRX_PLAN_NETWORK)) return 0;
+  size_t w = 0;
+  if (p->flags & MRX_PLAN_NETWORK) w = net_workspace_bytes(p);
+  return w + vn_workspace_bytes(p, p->ws_bytes_base + w);
+}
+
+size_t net_workspace_bytes(mrx_plan_s* p) {
   const size_t ni = (size_t)p->n_image;
   size_t w = 0;
   auto take = [&](size_t bytes) { size_t o = p->ws_bytes_base + w; w += al(bytes); return o; };

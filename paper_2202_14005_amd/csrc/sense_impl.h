@@ -6,6 +6,13 @@
 
 namespace mrx {
 
+// Non-temporal 8-byte load (second read of a coil map within a workgroup;
+// also keeps the compiler from holding the first read live in registers).
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  const unsigned long long v = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
+  return __builtin_bit_cast(float2, v);
+}
+
 // Deterministic fixed-order sum of n floats by one wavefront: lane l adds
 // elements l, l+64, ... in order, then a fixed butterfly over lanes.
 __device__ __forceinline__ float wave_sum_fixed(const float* a, int n, int lane) {
@@ -31,34 +38,51 @@ __device__ __forceinline__ float block_sum_fixed(float v, float* red) {
 }
 
 // --------------------------------------------------------- normal operator
-// One workgroup = WT adjacent columns of one slice, T threads per column.
-// q = sum_c conj(S_c) F_H^H diag(m') F_H (S_c p) + lambda p, one HBM read of
-// every coil map per application.
-template <class Sd, int WT>
-__global__ void __launch_bounds__(Sd::T * WT)
+// One workgroup = WT adjacent columns of one slice.  G groups of T x WT
+// threads each take every G-th coil of that column tile:
+//   acc_g = sum_{c = g, g+G, ...} conj(S_c) F_H^H diag(m') F_H (S_c p),
+// then the G partial sums are added through LDS in a fixed order and
+// q = sum_g acc_g + lambda p.  Every coil map is read from HBM once per
+// application (the conjugate multiply re-reads it from L2).  All groups run
+// the same number of coil iterations (idle ones on zeros) so that every
+// barrier inside the transforms is reached by the whole workgroup.
+//
+// Launch: a 1-D grid over (slice, tile) pairs arranged so that tiles 2k and
+// 2k+1 of a slice (which share 128-byte lines when WT = 8) get block ids
+// that differ by 8 and so land on the same XCD (workgroups are dispatched
+// to the 8 XCDs round-robin) and share its L2.
+// KS: keep the coil values in registers for the conjugate multiply instead
+// of re-reading them from L2.
+template <class Sd, int WT, int G, bool KS>
+__global__ void __launch_bounds__(Sd::T * WT * G)
 k_normal(NormalArgs a) {
-  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T, NT = T * WT;
   using L = LdsInterleaved<N, WT>;
-  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 lds[G * L::SIZE];
   __shared__ float2 tw[N];
   __shared__ float mk[N];
-  __shared__ float red[(T * WT + 63) / 64];
+  __shared__ float red[(NT * G + 63) / 64];
   __shared__ float sc[2];
 
-  const int b = a.slices[blockIdx.y];
+  const int Lb = blockIdx.x;
+  const int tg = (((Lb >> 4) * 8 + (Lb & 7)) << 1) + ((Lb >> 3) & 1);
+  const int si = tg / a.tiles, tile = tg % a.tiles;
+  if (si >= a.nslices) return;
+  const int b = a.slices[si];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
   const int W = d.W;
-  const int tile = blockIdx.x;
   if (tile * WT >= W) return;
   const int lid = threadIdx.x;
-  const int c = lid % WT, tc = lid / WT;
+  const int grp = lid / NT, l2 = lid % NT;
+  const int c = l2 % WT, tc = l2 / WT;
   const int col = tile * WT + c;
   const bool valid = col < W;
   const bool cg = a.mode == 1;
   if (cg && a.stopped[b]) return;
+  float2* xl = lds + grp * L::SIZE;
 
-  for (int i = lid; i < N; i += T * WT) {
+  for (int i = lid; i < N; i += NT * G) {
     tw[i] = a.tw[i];
     mk[i] = a.mask[d.moff + (i + N / 2) % N] * (1.0f / N);
   }
@@ -78,23 +102,32 @@ k_normal(NormalArgs a) {
   if (cg && a.iter > 0) {
     const float beta = sc[0];
     const float2* rbase = a.r + d.xoff;
+    float2* pobase = a.pout + d.xoff;
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
-        const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+        const int o = Sd::a1(tc, i, r) * W + col;
         float2 pv = valid ? pbase[o] : make_float2(0.f, 0.f);
         float2 rv = valid ? rbase[o] : make_float2(0.f, 0.f);
         pv = make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
         p[i * Sd::N1 + r] = pv;
-        if (valid) a.pout[d.xoff + o] = pv;
       }
+    // p is updated in place (pout == pin): every group must have read the
+    // old values before group 0 writes the new ones.
+    if constexpr (G > 1) __syncthreads();
+    if (valid && grp == 0) {
+#pragma unroll
+      for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+        for (int r = 0; r < Sd::N1; ++r) pobase[Sd::a1(tc, i, r) * W + col] = p[i * Sd::N1 + r];
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
-        const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+        const int o = Sd::a1(tc, i, r) * W + col;
         p[i * Sd::N1 + r] = valid ? pbase[o] : make_float2(0.f, 0.f);
       }
   }
@@ -105,19 +138,23 @@ k_normal(NormalArgs a) {
 
   const int64_t plane = (int64_t)N * W;
   const float2* Sb = a.S + d.soff;
-  for (int coil = 0; coil < d.C; ++coil) {
-    const float2* Sc = Sb + coil * plane;
-    float2 s[P], v[P];
+  const int iters = (d.C + G - 1) / G;
+  for (int it = 0; it < iters; ++it) {
+    const int coil = it * G + grp;
+    const bool on = valid && coil < d.C;
+    const float2* Sc = Sb + (int64_t)(coil < d.C ? coil : 0) * plane;
+    float2 v[P];
+    float2 sk[KS ? P : 1];
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
-        const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
-        s[i * Sd::N1 + r] = valid ? Sc[o] : make_float2(0.f, 0.f);
+        const int o = Sd::a1(tc, i, r) * W + col;
+        const float2 s = on ? Sc[o] : make_float2(0.f, 0.f);
+        if constexpr (KS) sk[i * Sd::N1 + r] = s;
+        v[i * Sd::N1 + r] = cmul(s, p[i * Sd::N1 + r]);
       }
-#pragma unroll
-    for (int k = 0; k < P; ++k) v[k] = cmul(s[k], p[k]);
-    fft_forward<Sd, L>(v, lds, tw, tc, c);
+    fft_forward<Sd, L>(v, xl, tw, tc, c);
 #pragma unroll
     for (int i = 0; i < Sd::GFIN; ++i)
 #pragma unroll
@@ -125,26 +162,56 @@ k_normal(NormalArgs a) {
         const float m = mk[Sd::freq(tc, i, r)];
         v[i * Sd::NFIN + r] = cscale(v[i * Sd::NFIN + r], m);
       }
-    fft_inverse<Sd, L>(v, lds, tw, tc, c);
+    fft_inverse<Sd, L>(v, xl, tw, tc, c);
+    if (on) {
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-      const float2 t = cmulc(s[k], v[k]);
-      acc[k] = cadd(acc[k], t);
+      for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+        for (int r = 0; r < Sd::N1; ++r) {
+          const int k = i * Sd::N1 + r;
+          float2 s;
+          if constexpr (KS) s = sk[k];
+          else s = ld_stream(&Sc[Sd::a1(tc, i, r) * W + col]);
+          acc[k] = cadd(acc[k], cmulc(s, v[k]));
+        }
+    }
+  }
+
+  if constexpr (G > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) xl[L::idx(Sd::a1(tc, i, r), c)] = acc[i * Sd::N1 + r];
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+      for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+        for (int r = 0; r < Sd::N1; ++r) {
+          const int id = L::idx(Sd::a1(tc, i, r), c);
+          float2 s = lds[id];
+#pragma unroll
+          for (int g = 1; g < G; ++g) s = cadd(s, lds[g * L::SIZE + id]);
+          acc[i * Sd::N1 + r] = s;
+        }
     }
   }
 
   const float lam = a.lam ? a.lam[b] : 0.f;
   float dot = 0.f;
-  float2* qbase = a.qout + d.xoff;
+  if (grp == 0) {
+    float2* qbase = a.qout + d.xoff;
 #pragma unroll
-  for (int i = 0; i < Sd::G1; ++i)
+    for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
-    for (int r = 0; r < Sd::N1; ++r) {
-      const int k = i * Sd::N1 + r;
-      const float2 q = make_float2(acc[k].x + lam * p[k].x, acc[k].y + lam * p[k].y);
-      dot += p[k].x * q.x + p[k].y * q.y;
-      if (valid) qbase[(int64_t)Sd::a1(tc, i, r) * W + col] = q;
-    }
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int k = i * Sd::N1 + r;
+        const float2 q = make_float2(acc[k].x + lam * p[k].x, acc[k].y + lam * p[k].y);
+        dot += p[k].x * q.x + p[k].y * q.y;
+        if (valid) qbase[Sd::a1(tc, i, r) * W + col] = q;
+      }
+  }
   if (cg) {
     const float s = block_sum_fixed(dot, red);
     if (lid == 0) a.pq_part[(int64_t)b * a.npq + tile] = s;
@@ -351,10 +418,13 @@ k_adj_row(SenseRowArgs a) {
 }
 
 // ------------------------------------------------------------- launchers
-template <class Sd, int WT>
-hipError_t launch_normal(const NormalArgs& a, int maxW, hipStream_t s) {
-  dim3 grid((maxW + WT - 1) / WT, a.nslices);
-  hipLaunchKernelGGL((k_normal<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
+template <class Sd, int WT, int G, bool KS>
+hipError_t launch_normal(const NormalArgs& a0, int maxW, hipStream_t s) {
+  NormalArgs a = a0;
+  a.tiles = (maxW + WT - 1) / WT;
+  const int total = a.tiles * a.nslices;
+  dim3 grid((unsigned)(((total + 15) / 16) * 16));
+  hipLaunchKernelGGL((k_normal<Sd, WT, G, KS>), grid, dim3(Sd::T * WT * G), 0, s, a);
   return hipGetLastError();
 }
 template <class Sd, int WT>
@@ -383,11 +453,11 @@ hipError_t launch_adj_row(const SenseRowArgs& a, int maxH, int maxC, hipStream_t
 }
 
 // Registers one column schedule and one row schedule for a length.
-template <class Sd, int WTC, int WTR>
+template <class Sd, int WTC, int WTR, int G, bool KS>
 struct Registrar {
   Registrar(const char* name) {
     ColVariant cv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTC,
-                  &launch_normal<Sd, WTC>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name};
+                  &launch_normal<Sd, WTC, G, KS>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name};
     register_col_variant(cv);
     RowVariant rv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTR,
                   &launch_fwd_row<Sd, WTR>, &launch_adj_row<Sd, WTR>, name};

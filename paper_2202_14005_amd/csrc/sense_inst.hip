@@ -1,11 +1,11 @@
 // One transform schedule for one length, selected by the build with
-//   -DMRX_N1=.. -DMRX_N2=.. -DMRX_N3=.. -DMRX_T=.. -DMRX_WTC=.. -DMRX_WTR=.. -DMRX_NAME=".."
+//   -DMRX_N1=.. -DMRX_N2=.. -DMRX_N3=.. -DMRX_T=.. -DMRX_WTC=.. -DMRX_WTR=.. -DMRX_G=.. -DMRX_KS=0|1 -DMRX_NAME=".."
 // It registers its column and row kernels with the schedule registry when
 // the library is loaded.
 #include "sense_impl.h"
 
 namespace mrx {
 namespace {
-Registrar<Sched<MRX_N1, MRX_N2, MRX_N3, MRX_T>, MRX_WTC, MRX_WTR> registrar_(MRX_NAME);
+Registrar<Sched<MRX_N1, MRX_N2, MRX_N3, MRX_T>, MRX_WTC, MRX_WTR, MRX_G, (MRX_KS != 0)> registrar_(MRX_NAME);
 }  // namespace
 }  // namespace mrx

@@ -36,6 +36,7 @@ struct NormalArgs {
   float* pq_part;          // [B][npq]
   int npq;
   const int* stopped;      // [B] per-slice stop flag (CG breakdown)
+  int tiles;               // column tiles per slice (set by the launcher)
 };
 
 struct SenseColArgs {

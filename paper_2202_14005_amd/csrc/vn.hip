@@ -1,0 +1,406 @@
+// Variational-network stage (Variational Network subsection, eq. update_vn):
+//   x' = x - sum_i K_i^T Phi'_i(Re(k_i * x)) - lambda (A^H A x - A^H y)
+// with N_k = 24 complex 11 x 11 filters (cross-correlation, zero "same"
+// padding, imaginary part of the filter response discarded) and trainable
+// activations Phi'_i(s) = sum_j w_ij exp(-(s - mu_j)^2 / (2 sigma^2)),
+// mu_j = -1 + 2j/30, sigma = 2/30 (31 knots).  All in fp32 on the vector ALUs:
+// the activation's width (sigma = 1/15) turns a 2^-9 relative error of the
+// filter response into a several-percent error of Phi', so bf16 operands
+// would not hold parity.  Filter weights are read tap-major through scalar
+// loads (uniform across a wavefront); image tiles are staged in LDS.
+#include "../../include/mrx.h"
+#include "api_internal.h"
+#include "vn.h"
+
+namespace mrx {
+
+constexpr int VT = 16;                 // output tile edge (16 x 16 pixels, 256 threads)
+constexpr int VH = VT + 2 * VN_R;      // tile with halo
+constexpr float VN_SIG = 2.0f / (VN_NW - 1);
+constexpr float VN_INV2S2 = 1.0f / (2.0f * VN_SIG * VN_SIG);
+
+// kt[tap][i] = k_i[tap] (complex), from k[i][tap].
+__global__ void k_vn_pack(const float2* k, float2* kt) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= VN_NK * VN_TAPS) return;
+  const int i = idx % VN_NK, tap = idx / VN_NK;
+  kt[idx] = k[i * VN_TAPS + tap];
+}
+
+__device__ __forceinline__ void load_ctile(float2* tile, const float2* img, int H, int W, int y0, int x0) {
+  for (int p = threadIdx.x; p < VH * VH; p += 256) {
+    const int gy = y0 + p / VH - VN_R, gx = x0 + p % VH - VN_R;
+    float2 v = make_float2(0.f, 0.f);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = img[(int64_t)gy * W + gx];
+    tile[p] = v;
+  }
+}
+
+// Filter responses s_i = Re(k_i * x) (and Kg_i = Re(k_i * g) in the reverse
+// mode) for a 16 x 16 tile, then the activation:
+//   forward: u_i = Phi'_i(s_i)
+//   reverse: u_i = Phi'_i(s_i), e_i = Phi''_i(s_i) * Kg_i, and Kg_i, s_i kept
+// Outputs are [pixel][24] fp32 at offset xoff * 24.
+template <bool REV>
+__global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
+  __shared__ float2 tx[VH * VH];
+  __shared__ float2 tg[REV ? VH * VH : 1];
+  const int b = a.slices[blockIdx.z];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int x0 = blockIdx.x * VT, y0 = blockIdx.y * VT;
+  if (x0 >= W || y0 >= H) return;
+  load_ctile(tx, a.x + d.xoff, H, W, y0, x0);
+  if constexpr (REV) load_ctile(tg, a.g + d.xoff, H, W, y0, x0);
+  __syncthreads();
+  const int ly = threadIdx.x / VT, lx = threadIdx.x % VT;
+  float s[VN_NK], kg[REV ? VN_NK : 1];
+#pragma unroll
+  for (int i = 0; i < VN_NK; ++i) {
+    s[i] = 0.f;
+    if constexpr (REV) kg[i] = 0.f;
+  }
+  for (int dy = 0; dy < VN_KS; ++dy) {
+    for (int dx = 0; dx < VN_KS; ++dx) {
+      const int tap = dy * VN_KS + dx;
+      const int tp = (ly + dy) * VH + lx + dx;
+      const float2 xv = tx[tp];
+      float2 gv = make_float2(0.f, 0.f);
+      if constexpr (REV) gv = tg[tp];
+      const float2* kt = a.kt + tap * VN_NK;  // uniform: scalar loads
+#pragma unroll
+      for (int i = 0; i < VN_NK; ++i) {
+        const float2 kk = kt[i];
+        s[i] = fmaf(kk.x, xv.x, fmaf(-kk.y, xv.y, s[i]));
+        if constexpr (REV) kg[i] = fmaf(kk.x, gv.x, fmaf(-kk.y, gv.y, kg[i]));
+      }
+    }
+  }
+  const int gy = y0 + ly, gx = x0 + lx;
+  if (gy >= H || gx >= W) return;
+  const int64_t o = (d.xoff + (int64_t)gy * W + gx) * VN_NK;
+#pragma unroll
+  for (int i = 0; i < VN_NK; ++i) {
+    float p1 = 0.f, p2 = 0.f;
+    const float* wi = a.w + i * VN_NW;  // uniform
+    for (int j = 0; j < VN_NW; ++j) {
+      const float mu = -1.0f + (2.0f / (VN_NW - 1)) * (float)j;
+      const float t = s[i] - mu;
+      const float e = __expf(-t * t * VN_INV2S2);
+      p1 = fmaf(wi[j], e, p1);
+      if constexpr (REV) p2 = fmaf(wi[j] * (-t * (2.0f * VN_INV2S2)), e, p2);
+    }
+    a.u[o + i] = p1;
+    if constexpr (REV) {
+      a.e[o + i] = p2 * kg[i];
+      a.kg[o + i] = kg[i];
+      a.s[o + i] = s[i];
+    }
+  }
+}
+
+// r = K^T v (v: [pixel][24] fp32) for a 16 x 16 tile, fused with the update
+//   forward: out = x - r - lambda (q - aHy)        (q = A^H A x)
+//   reverse: out = g - r - lambda q                (q = A^H A g)
+// and, in the reverse mode, per-workgroup partials of Re<g, qx - aHy>.
+template <bool REV>
+__global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
+  __shared__ float tv[VH * VH * VN_NK];
+  __shared__ float red[4];
+  const int b = a.slices[blockIdx.z];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int x0 = blockIdx.x * VT, y0 = blockIdx.y * VT;
+  const int wgid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  float lam_part = 0.f;
+  if (x0 < W && y0 < H) {
+    const float* v = REV ? a.e : a.u;
+    for (int q = threadIdx.x; q < VH * VH * VN_NK; q += 256) {
+      const int p = q / VN_NK, i = q % VN_NK;
+      const int gy = y0 + p / VH - VN_R, gx = x0 + p % VH - VN_R;
+      float val = 0.f;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) val = v[(d.xoff + (int64_t)gy * W + gx) * VN_NK + i];
+      tv[i * VH * VH + p] = val;
+    }
+    __syncthreads();
+    const int ly = threadIdx.x / VT, lx = threadIdx.x % VT;
+    float rr = 0.f, ri = 0.f;
+    // s[p] used x[p + d] => adjoint gathers v[p - d]
+    for (int dy = 0; dy < VN_KS; ++dy) {
+      for (int dx = 0; dx < VN_KS; ++dx) {
+        const int tap = dy * VN_KS + dx;
+        const int tp = (ly + 2 * VN_R - dy) * VH + lx + 2 * VN_R - dx;
+        const float2* kt = a.kt + tap * VN_NK;
+#pragma unroll
+        for (int i = 0; i < VN_NK; ++i) {
+          const float vv = tv[i * VH * VH + tp];
+          const float2 kk = kt[i];
+          rr = fmaf(kk.x, vv, rr);
+          ri = fmaf(-kk.y, vv, ri);
+        }
+      }
+    }
+    const int gy = y0 + ly, gx = x0 + lx;
+    if (gy < H && gx < W) {
+      const int64_t o = d.xoff + (int64_t)gy * W + gx;
+      const float lam = a.lam[0];
+      const float2 q = a.q[o];
+      if constexpr (!REV) {
+        const float2 xv = a.x[o], ay = a.aHy[o];
+        a.out[o] = make_float2(xv.x - rr - lam * (q.x - ay.x), xv.y - ri - lam * (q.y - ay.y));
+      } else {
+        const float2 gv = a.g[o];
+        a.out[o] = make_float2(gv.x - rr - lam * q.x, gv.y - ri - lam * q.y);
+        const float2 qx = a.qx[o], ay = a.aHy[o];
+        lam_part = -(gv.x * (qx.x - ay.x) + gv.y * (qx.y - ay.y));
+      }
+    }
+  }
+  if constexpr (REV) {
+    float v = lam_part;
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) a.part_lam[wgid] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+// Filter gradients of one stage (reverse mode):
+//   dkr_i[d] = -sum_p (u_i[p] Re g[p+d] + e_i[p] Re x[p+d])
+//   dki_i[d] = +sum_p (u_i[p] Im g[p+d] + e_i[p] Im x[p+d])
+// One workgroup per (band of VN_BAND rows, slice); thread t < 121 owns tap t
+// and keeps 24 x 2 accumulators; partials per workgroup.
+__global__ void __launch_bounds__(128) k_vn_kgrad(VnArgs a) {
+  constexpr int RW = 256;  // row-buffer width; output chunk RW - 2R columns
+  __shared__ float2 rowg[VN_KS * RW];
+  __shared__ float2 rowx[VN_KS * RW];
+  __shared__ float uv[RW * VN_NK];
+  __shared__ float ev[RW * VN_NK];
+  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
+  float* part = a.part_k + (int64_t)wg * (VN_NK * VN_TAPS * 2);
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int tap = threadIdx.x, dy = tap / VN_KS, dx = tap % VN_KS;
+  float ar[VN_NK], ai[VN_NK];
+#pragma unroll
+  for (int i = 0; i < VN_NK; ++i) { ar[i] = 0.f; ai[i] = 0.f; }
+  for (int rr = 0; rr < VN_BAND; ++rr) {
+    const int row = blockIdx.x * VN_BAND + rr;
+    if (row >= H) break;
+    for (int c0 = 0; c0 < W; c0 += RW - 2 * VN_R) {
+      const int cw = min(RW - 2 * VN_R, W - c0);
+      __syncthreads();
+      // rows row-5 .. row+5 of g and x, columns c0-5 .. c0+cw+4
+      for (int q = threadIdx.x; q < VN_KS * RW; q += 128) {
+        const int r = q / RW, c = q % RW;
+        const int gy = row + r - VN_R, gx = c0 + c - VN_R;
+        float2 gv = make_float2(0.f, 0.f), xv = make_float2(0.f, 0.f);
+        if (c < cw + 2 * VN_R && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+          gv = a.g[d.xoff + (int64_t)gy * W + gx];
+          xv = a.x[d.xoff + (int64_t)gy * W + gx];
+        }
+        rowg[q] = gv;
+        rowx[q] = xv;
+      }
+      for (int q = threadIdx.x; q < cw * VN_NK; q += 128) {
+        const int64_t o = (d.xoff + (int64_t)row * W + c0) * VN_NK + q;
+        uv[q] = a.u[o];
+        ev[q] = a.e[o];
+      }
+      __syncthreads();
+      if (tap < VN_TAPS) {
+        for (int c = 0; c < cw; ++c) {
+          const int tp = dy * RW + c + dx;
+          const float2 gv = rowg[tp], xv = rowx[tp];
+#pragma unroll
+          for (int i = 0; i < VN_NK; ++i) {
+            const float u = uv[c * VN_NK + i], e = ev[c * VN_NK + i];
+            ar[i] = fmaf(u, gv.x, fmaf(e, xv.x, ar[i]));
+            ai[i] = fmaf(u, gv.y, fmaf(e, xv.y, ai[i]));
+          }
+        }
+      }
+    }
+  }
+  if (tap < VN_TAPS) {
+#pragma unroll
+    for (int i = 0; i < VN_NK; ++i) {
+      part[(i * VN_TAPS + tap) * 2 + 0] = -ar[i];
+      part[(i * VN_TAPS + tap) * 2 + 1] = ai[i];
+    }
+  }
+}
+
+// RBF-weight gradients: dw_ij = -sum_p Kg_i[p] exp(-(s_i[p] - mu_j)^2 / (2 sigma^2)).
+// One workgroup per (band, slice); thread t < 24 * 31 owns (i, j).
+__global__ void __launch_bounds__(768) k_vn_wgrad(VnArgs a) {
+  __shared__ float sv[256 * VN_NK];
+  __shared__ float gv[256 * VN_NK];
+  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
+  float* part = a.part_w + (int64_t)wg * (VN_NK * VN_NW);
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int t = threadIdx.x, i = t / VN_NW, j = t % VN_NW;
+  const float mu = -1.0f + (2.0f / (VN_NW - 1)) * (float)j;
+  float acc = 0.f;
+  for (int rr = 0; rr < VN_BAND; ++rr) {
+    const int row = blockIdx.x * VN_BAND + rr;
+    if (row >= H) break;
+    for (int c0 = 0; c0 < W; c0 += 256) {
+      const int cw = min(256, W - c0);
+      __syncthreads();
+      for (int q = t; q < cw * VN_NK; q += 768) {
+        const int64_t o = (d.xoff + (int64_t)row * W + c0) * VN_NK + q;
+        sv[q] = a.s[o];
+        gv[q] = a.kg[o];
+      }
+      __syncthreads();
+      if (t < VN_NK * VN_NW) {
+        for (int c = 0; c < cw; ++c) {
+          const float dd = sv[c * VN_NK + i] - mu;
+          acc = fmaf(gv[c * VN_NK + i], __expf(-dd * dd * VN_INV2S2), acc);
+        }
+      }
+    }
+  }
+  if (t < VN_NK * VN_NW) part[t] = -acc;
+}
+
+// out[i] (+)= sum_s part[s][i], fixed order.
+__global__ void k_vn_reduce(const float* part, int nslots, int nout, float* out, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nout) return;
+  float s = 0.f;
+  for (int k = 0; k < nslots; ++k) s += part[(int64_t)k * nout + i];
+  out[i] = accumulate ? out[i] + s : s;
+}
+
+}  // namespace mrx
+
+using namespace mrx;
+
+namespace {
+
+mrx_status vn_ready(mrx_plan_s* p, const char* who) {
+  if (!p->ws) return fail(MRX_ENOWORKSPACE, std::string(who) + ": workspace not set");
+  if (!(p->flags & MRX_PLAN_VN)) return fail(MRX_ENOWORKSPACE, std::string(who) + ": plan needs MRX_PLAN_VN");
+  return MRX_OK;
+}
+
+VnArgs vn_args(mrx_plan_s* p, const mrx_vn_params* prm) {
+  VnArgs a{};
+  a.desc = p->d_desc;
+  a.slices = p->d_all;
+  a.nslices = p->B;
+  a.kt = (const float2*)(p->ws + p->ws_vn_kt);
+  a.w = prm->w;
+  a.lam = prm->lam;
+  a.u = (float*)(p->ws + p->ws_vn_u);
+  a.e = (float*)(p->ws + p->ws_vn_e);
+  a.kg = (float*)(p->ws + p->ws_vn_kg);
+  a.s = (float*)(p->ws + p->ws_vn_s);
+  a.part_lam = (float*)(p->ws + p->ws_vn_plam);
+  a.part_k = (float*)(p->ws + p->ws_vn_pk);
+  a.part_w = (float*)(p->ws + p->ws_vn_pw);
+  return a;
+}
+
+}  // namespace
+
+namespace mrx {
+
+size_t vn_workspace_bytes(mrx_plan_s* p, size_t base) {
+  if (!(p->flags & MRX_PLAN_VN)) return 0;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t ni = (size_t)p->n_image;
+  size_t w = 0;
+  auto take = [&](size_t bytes) { size_t o = base + w; w += al(bytes); return o; };
+  p->ws_vn_kt = take(sizeof(float2) * VN_NK * VN_TAPS);
+  p->ws_vn_u = take(ni * VN_NK * 4);
+  p->ws_vn_e = take(ni * VN_NK * 4);
+  p->ws_vn_kg = take(ni * VN_NK * 4);
+  p->ws_vn_s = take(ni * VN_NK * 4);
+  p->ws_vn_qx = take(ni * 8);
+  p->ws_vn_qg = take(ni * 8);
+  const size_t tiles = (size_t)((p->maxW + VT - 1) / VT) * ((p->maxH + VT - 1) / VT) * p->B;
+  p->ws_vn_plam = take(tiles * 4);
+  const size_t bands = (size_t)((p->maxH + VN_BAND - 1) / VN_BAND) * p->B;
+  p->ws_vn_pk = take(bands * VN_NK * VN_TAPS * 2 * 4);
+  p->ws_vn_pw = take(bands * VN_NK * VN_NW * 4);
+  return w;
+}
+
+}  // namespace mrx
+
+extern "C" {
+
+mrx_status mrx_vn_stage(mrx_plan p, const float* x, const float* aHy, const float* S, const float* mask,
+                        const mrx_vn_params* prm, float* x_next, void* stream) {
+  if (!p || !prm) return fail(MRX_EINVAL, "vn_stage: null argument");
+  if (!x || !aHy || !S || !mask || !x_next || !prm->k || !prm->w || !prm->lam)
+    return fail(MRX_EINVAL, "vn_stage: null data pointer");
+  if (x == x_next) return fail(MRX_EINVAL, "vn_stage: x and x_next must not alias");
+  mrx_status st = vn_ready(p, "vn_stage");
+  if (st != MRX_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  VnArgs a = vn_args(p, prm);
+  float2* q = (float2*)(p->ws + p->ws_vn_qx);
+  hipLaunchKernelGGL(k_vn_pack, dim3((VN_NK * VN_TAPS + 255) / 256), dim3(256), 0, s, (const float2*)prm->k,
+                     (float2*)(p->ws + p->ws_vn_kt));
+  st = normal_impl(p, (const float2*)x, (const float2*)S, mask, nullptr, q, s);
+  if (st != MRX_OK) return st;
+  a.x = (const float2*)x;
+  a.aHy = (const float2*)aHy;
+  a.q = q;
+  a.out = (float2*)x_next;
+  dim3 grid((p->maxW + VT - 1) / VT, (p->maxH + VT - 1) / VT, p->B);
+  hipLaunchKernelGGL(k_vn_filter<false>, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_vn_adjoint<false>, grid, dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "vn_stage");
+}
+
+mrx_status mrx_vn_stage_backward(mrx_plan p, const float* g, const float* x, const float* aHy, const float* S,
+                                 const float* mask, const mrx_vn_params* prm, float* g_x, float* g_k, float* g_w,
+                                 float* g_lam, int32_t accumulate, void* stream) {
+  if (!p || !prm) return fail(MRX_EINVAL, "vn_stage_backward: null argument");
+  if (!g || !x || !aHy || !S || !mask || !g_x || !g_k || !g_w || !g_lam || !prm->k || !prm->w || !prm->lam)
+    return fail(MRX_EINVAL, "vn_stage_backward: null data pointer");
+  if (g == g_x) return fail(MRX_EINVAL, "vn_stage_backward: g and g_x must not alias");
+  mrx_status st = vn_ready(p, "vn_stage_backward");
+  if (st != MRX_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  VnArgs a = vn_args(p, prm);
+  float2* qx = (float2*)(p->ws + p->ws_vn_qx);
+  float2* qg = (float2*)(p->ws + p->ws_vn_qg);
+  hipLaunchKernelGGL(k_vn_pack, dim3((VN_NK * VN_TAPS + 255) / 256), dim3(256), 0, s, (const float2*)prm->k,
+                     (float2*)(p->ws + p->ws_vn_kt));
+  st = normal_impl(p, (const float2*)x, (const float2*)S, mask, nullptr, qx, s);
+  if (st == MRX_OK) st = normal_impl(p, (const float2*)g, (const float2*)S, mask, nullptr, qg, s);
+  if (st != MRX_OK) return st;
+  a.x = (const float2*)x;
+  a.g = (const float2*)g;
+  a.aHy = (const float2*)aHy;
+  a.q = qg;
+  a.qx = qx;
+  a.out = (float2*)g_x;
+  dim3 grid((p->maxW + VT - 1) / VT, (p->maxH + VT - 1) / VT, p->B);
+  const int tiles = grid.x * grid.y * grid.z;
+  hipLaunchKernelGGL(k_vn_filter<true>, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_vn_adjoint<true>, grid, dim3(256), 0, s, a);
+  const int bands = (p->maxH + VN_BAND - 1) / VN_BAND;
+  hipLaunchKernelGGL(k_vn_kgrad, dim3(bands, p->B), dim3(128), 0, s, a);
+  hipLaunchKernelGGL(k_vn_wgrad, dim3(bands, p->B), dim3(768), 0, s, a);
+  const int nk = VN_NK * VN_TAPS * 2, nw = VN_NK * VN_NW;
+  hipLaunchKernelGGL(k_vn_reduce, dim3((nk + 255) / 256), dim3(256), 0, s, a.part_k, bands * p->B, nk, g_k,
+                     accumulate);
+  hipLaunchKernelGGL(k_vn_reduce, dim3((nw + 255) / 256), dim3(256), 0, s, a.part_w, bands * p->B, nw, g_w,
+                     accumulate);
+  hipLaunchKernelGGL(k_vn_reduce, dim3(1), dim3(64), 0, s, a.part_lam, tiles, 1, g_lam, accumulate);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "vn_stage_backward");
+}
+
+}  // extern "C"

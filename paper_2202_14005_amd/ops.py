@@ -32,7 +32,7 @@ class Plan:
     ``H``, ``W``, ``C`` are ints (even batch of ``B`` slices) or per-slice
     sequences (uneven batch)."""
 
-    def __init__(self, H, W, C, B: int | None = None, device=None, network: bool = False):
+    def __init__(self, H, W, C, B: int | None = None, device=None, network: bool = False, vn: bool = False):
         L = lib()
         if isinstance(H, int):
             if B is None:
@@ -50,9 +50,10 @@ class Plan:
         arr = lambda v: (ctypes.c_int32 * len(v))(*v)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            check(L.mrx_plan_create(ctypes.byref(h), self.B, arr(Hs), arr(Ws), arr(Cs), 1 if network else 0),
-                  "plan_create")
+            flags = (1 if network else 0) | (2 if vn else 0)
+            check(L.mrx_plan_create(ctypes.byref(h), self.B, arr(Hs), arr(Ws), arr(Cs), flags), "plan_create")
         self.network = network
+        self.vn = vn
         self._weights_key = None
         self._h = h
         ni, nc, nm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -185,6 +186,9 @@ class Plan:
     def schedule(self, b=0):
         return lib().mrx_plan_schedule(self._h, int(b)).decode()
 
+    def set_schedule(self, n, name):
+        check(lib().mrx_plan_set_schedule(self._h, int(n), name.encode()), "plan_set_schedule")
+
 
     # ------------------------------------------------------------- network
     def set_weights(self, cnn: "CNN", force=False):
@@ -247,6 +251,43 @@ class Plan:
                                       _ptr(lt), int(T), int(n_cg), ctypes.byref(grads.c_grads()), _ptr(gl),
                                       _ptr(ga), int(bool(accumulate)), _stream(self.device)), "modl_backward")
         return gl, ga
+
+    # ------------------------------------------------------------- VarNet
+    def _vn_params(self, k, w, lam):
+        from ._lib import VnParams
+        if k.dtype != torch.complex64 or tuple(k.shape) != (24, 11, 11) or not k.is_contiguous():
+            raise ValueError("k must be a contiguous complex64 tensor [24, 11, 11]")
+        if w.dtype != torch.float32 or tuple(w.shape) != (24, 31) or not w.is_contiguous():
+            raise ValueError("w must be a contiguous float32 tensor [24, 31]")
+        if lam.dtype != torch.float32 or lam.numel() != 1:
+            raise ValueError("lam must be a float32 tensor with one element")
+        for t, n in ((k, "k"), (w, "w"), (lam, "lam")):
+            if t.device != self.device:
+                raise ValueError(f"{n} must be on {self.device}")
+        return VnParams(k.data_ptr(), w.data_ptr(), lam.data_ptr())
+
+    def vn_stage(self, x, aHy, S, mask, k, w, lam, out=None):
+        """x' = x - sum_i K_i^T Phi'_i(Re(k_i * x)) - lam (A^H A x - aHy)."""
+        self._img(x, "x"); self._img(aHy, "aHy"); self._coil(S, "S"); self._mask(mask, "mask")
+        prm = self._vn_params(k, w, lam)
+        xn = self._img(out, "out") if out is not None else self._empty_img()
+        check(lib().mrx_vn_stage(self._h, _ptr(x), _ptr(aHy), _ptr(S), _ptr(mask), ctypes.byref(prm), _ptr(xn),
+                                 _stream(self.device)), "vn_stage")
+        return xn
+
+    def vn_stage_backward(self, g, x, aHy, S, mask, k, w, lam, grads=None, accumulate=False):
+        """Returns (g_x, (g_k, g_w, g_lam)); gradients written into grads if given."""
+        self._img(g, "g"); self._img(x, "x"); self._img(aHy, "aHy"); self._coil(S, "S"); self._mask(mask, "mask")
+        prm = self._vn_params(k, w, lam)
+        gx = self._empty_img()
+        if grads is None:
+            grads = (torch.zeros_like(k), torch.zeros_like(w), torch.zeros(1, dtype=torch.float32,
+                                                                            device=self.device))
+        gk, gw, gl = grads
+        check(lib().mrx_vn_stage_backward(self._h, _ptr(g), _ptr(x), _ptr(aHy), _ptr(S), _ptr(mask),
+                                          ctypes.byref(prm), _ptr(gx), _ptr(gk), _ptr(gw), _ptr(gl),
+                                          int(bool(accumulate)), _stream(self.device)), "vn_stage_backward")
+        return gx, grads
 
     def mse_grad(self, x, ref):
         """Returns (loss as a device float tensor [1], gradient)."""
@@ -373,6 +414,53 @@ class MoDL:
         p.modl_backward(g, states, aHy, S, mask, self.cnn, self.lam, self.T, self.n_cg, grads)
         opt.step(grads)
         return loss
+
+
+class VarNet:
+    """Variational network: x^0 = A^H y, then T stages (eq. update_vn) with
+    per-stage filters k [T, 24, 11, 11] complex64, RBF weights w [T, 24, 31]
+    and step sizes lam [T] (device tensors)."""
+
+    def __init__(self, plan: Plan, k, w, lam):
+        if not plan.vn:
+            raise ValueError("VarNet needs a plan created with vn=True")
+        self.plan, self.k, self.w, self.lam = plan, k.contiguous(), w.contiguous(), lam.contiguous()
+        self.T = k.shape[0]
+
+    @classmethod
+    def init(cls, plan: Plan, seed=1, T=10):
+        from synthetic import vn_params
+        p = vn_params(seed, n_stages=T)
+        d = plan.device
+        return cls(plan, torch.from_numpy(p["k"]).to(d), torch.from_numpy(p["w"]).to(d),
+                   torch.from_numpy(p["lam"]).to(d))
+
+    def forward(self, aHy, S, mask):
+        """Returns (x^T, states [T + 1, ...])."""
+        states = [aHy]
+        for t in range(self.T):
+            states.append(self.plan.vn_stage(states[-1], aHy, S, mask, self.k[t], self.w[t], self.lam[t:t + 1]))
+        return states[-1], states
+
+    def backward(self, g, states, aHy, S, mask):
+        """Reverse pass from the stored states; returns (gk, gw, glam, g_x0)."""
+        gk, gw = torch.zeros_like(self.k), torch.zeros_like(self.w)
+        gl = torch.zeros_like(self.lam)
+        for t in range(self.T - 1, -1, -1):
+            g, _ = self.plan.vn_stage_backward(g, states[t], aHy, S, mask, self.k[t], self.w[t],
+                                               self.lam[t:t + 1], grads=(gk[t], gw[t], gl[t:t + 1]))
+        return gk, gw, gl, g
+
+
+def schedules(n: int):
+    """Names of the registered column schedules for transform length n."""
+    out, i = [], 0
+    while True:
+        s = lib().mrx_schedule_name(int(n), i)
+        if not s:
+            return out
+        out.append(s.decode())
+        i += 1
 
 
 def supported_length(n: int) -> bool:
