@@ -53,7 +53,7 @@ typedef enum {
 #define MRX_FLAG_NONFINITE 1u     /* non-finite CG scalar (NaN/Inf input) */
 #define MRX_FLAG_CG_BREAKDOWN 2u  /* Re<p, S p> <= 0 with rho > 0 */
 #define MRX_FLAG_CNN_NONFINITE 4u /* non-finite denoiser output */
-#define MRX_FLAG_DC_JUDGE 8u      /* reserved */
+#define MRX_FLAG_DC_JUDGE 8u      /* mrx_dc_judge replaced the slice by CG-SENSE */
 
 typedef struct mrx_plan_s* mrx_plan;
 
@@ -177,8 +177,27 @@ mrx_status mrx_cg_dc_backward(mrx_plan plan, const float* gx, const float* x, co
                               int32_t n_iter, float* g_aHy, float* g_z, float* g_lambda,
                               int32_t accumulate, void* stream);
 
-/* Copy the per-slice status words (uint32[B]) to dev_flags (device) and, if
- * clear != 0, reset them.  Enqueued on stream. */
+/*
+ * Fallback and judge for a learned reconstruction.  x_cg is the plain
+ * Tikhonov CG-SENSE solution (mrx_cg_dc with z = NULL), the reconstruction
+ * MoDL reduces to without its denoiser (eq. update_modl with lambda z = 0).
+ * Per slice b, the data-consistency residual r(x) = ||A^H A x - aHy||_2 is
+ * evaluated for x_net and x_cg; out[b] = x_cg[b] (and MRX_FLAG_DC_JUDGE is
+ * raised, dev_choice[b] = 1) when x_net[b] has a non-finite entry, the slice
+ * already carries MRX_FLAG_NONFINITE, _CG_BREAKDOWN or _CNN_NONFINITE, or
+ * r(x_net) > ratio * r(x_cg); otherwise out[b] = x_net[b], dev_choice[b] = 0.
+ * x_net, x_cg, aHy, out: packed images; out may alias x_net or x_cg (the
+ * selection is element-wise, after both residuals).  dev_choice: device
+ * uint32[B].  ratio > 0, else MRX_EINVAL.  Uses the workspace (its CG
+ * buffers), so it must not overlap a CG call of the same plan.
+ */
+mrx_status mrx_dc_judge(mrx_plan plan, const float* x_net, const float* x_cg, const float* aHy,
+                        const float* S, const float* mask, float ratio, float* out,
+                        uint32_t* dev_choice, void* stream);
+
+/* Copy the per-slice status words (uint32[B]) to dev_flags (device; NULL
+ * skips the copy) and, if clear != 0, reset them.  Enqueued on stream, with a
+ * copy and a fill kernel only, so it may be captured in a graph. */
 mrx_status mrx_status_word(mrx_plan plan, uint32_t* dev_flags, int32_t clear, void* stream);
 
 /*
@@ -289,6 +308,15 @@ const char* mrx_plan_schedule(mrx_plan plan, int32_t b);
 const char* mrx_schedule_name(int32_t n, int32_t idx);
 /* Force the column schedule `name` for the slices of the plan with H = n. */
 mrx_status mrx_plan_set_schedule(mrx_plan plan, int32_t n, const char* name);
+/* Write the in-process tuning cache to a text file, one "H W C name" entry a
+ * line.  MRX_EINVAL if the file cannot be written. */
+mrx_status mrx_tune_cache_save(const char* path);
+/* Merge the entries of a file written by mrx_tune_cache_save into the
+ * in-process cache; plans created afterwards use them.  Every entry is checked
+ * first (known schedule for its H, positive W and C): on a bad entry nothing is
+ * merged and MRX_EINVAL names the line.  n_loaded (nullable) receives the
+ * number of entries. */
+mrx_status mrx_tune_cache_load(const char* path, int32_t* n_loaded);
 
 #ifdef __cplusplus
 }

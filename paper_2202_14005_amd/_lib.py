@@ -53,6 +53,9 @@ SIGNATURES = {
     "mrx_vn_stage": (c_int32, [P, P, P, P, P, P, P, P]),
     "mrx_vn_stage_backward": (c_int32, [P, P, P, P, P, P, P, P, P, P, P, c_int32, P]),
     "mrx_plan_set_schedule": (c_int32, [P, c_int32, c_char_p]),
+    "mrx_dc_judge": (c_int32, [P, P, P, P, P, P, c_float, P, P, P]),
+    "mrx_tune_cache_save": (c_int32, [c_char_p]),
+    "mrx_tune_cache_load": (c_int32, [c_char_p, ctypes.POINTER(c_int32)]),
 }
 
 STATUS = {0: "MRX_OK", -1: "MRX_EINVAL", -2: "MRX_EUNSUPPORTED", -3: "MRX_ENOMEM",

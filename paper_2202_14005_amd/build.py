@@ -24,7 +24,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # name, N1, N2, N3, threads per transform T, column tile width, row tile
 # height, coil groups per normal-operator workgroup, keep coil values in
-# registers (1) or re-read them from L2 (0).
+# registers (1) or re-read them from L2 (0), and optionally 1 for the
+# wave-local normal operator (each wavefront transforms 64 / T columns with
+# its own LDS region; G wavefronts per workgroup split the coils).
 # The first schedule listed for a length is its default; the autotuner
 # times all schedules of a length on the normal operator.
 SCHEDULES = [
@@ -56,10 +58,22 @@ SCHEDULES = [
     ("n384_4x4x24_t16_w8_g3_rl", 4, 4, 24, 16, 8, 16, 3, 0),
     ("n384_4x4x24_t16_w16", 4, 4, 24, 16, 16, 16, 1, 1),
     ("n512_4x8x16_t32_w8", 4, 8, 16, 32, 8, 8, 1, 1),
+    ("n128_4x4x8_t16_wl_g3", 4, 4, 8, 16, 16, 16, 3, 1, 1),
+    ("n128_4x4x8_t16_wl_g4", 4, 4, 8, 16, 16, 16, 4, 1, 1),
+    ("n192_4x4x12_t16_wl_g3", 4, 4, 12, 16, 16, 16, 3, 1, 1),
+    ("n192_4x4x12_t16_wl_g4", 4, 4, 12, 16, 16, 16, 4, 1, 1),
+    ("n256_4x4x16_t16_wl_g3", 4, 4, 16, 16, 16, 16, 3, 1, 1),
+    ("n256_4x4x16_t16_wl_g4", 4, 4, 16, 16, 16, 16, 4, 1, 1),
+    ("n320_4x4x20_t16_wl_g2", 4, 4, 20, 16, 16, 16, 2, 1, 1),
+    ("n320_4x4x20_t16_wl_g3", 4, 4, 20, 16, 16, 16, 3, 1, 1),
+    ("n320_4x4x20_t16_wl_g4", 4, 4, 20, 16, 16, 16, 4, 1, 1),
+    ("n320_4x4x20_t16_wl_g5", 4, 4, 20, 16, 16, 16, 5, 1, 1),
+    ("n384_4x4x24_t16_wl_g3", 4, 4, 24, 16, 16, 16, 3, 1, 1),
+    ("n384_4x4x24_t16_wl_g4", 4, 4, 24, 16, 16, 16, 4, 1, 1),
 ]
 
 COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net.hip", "conv.hip",
-                  "conv_wgrad.hip", "vn.hip"]
+                  "conv_wgrad.hip", "vn.hip", "judge.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -79,10 +93,12 @@ def _jobs():
     jobs = []
     for s in srcs:
         jobs.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".hip", ".o")), []))
-    for name, n1, n2, n3, t, wtc, wtr, g, ks in SCHEDULES:
+    for entry in SCHEDULES:
+        name, n1, n2, n3, t, wtc, wtr, g, ks = entry[:9]
+        wl = entry[9] if len(entry) > 9 else 0
         defs = [f"-DMRX_N1={n1}", f"-DMRX_N2={n2}", f"-DMRX_N3={n3}", f"-DMRX_T={t}",
                 f"-DMRX_WTC={wtc}", f"-DMRX_WTR={wtr}", f"-DMRX_G={g}", f"-DMRX_KS={ks}",
-                f'-DMRX_NAME="{name}"']
+                f"-DMRX_WL={wl}", f'-DMRX_NAME="{name}"']
         jobs.append((os.path.join(CSRC, "sense_inst.hip"), os.path.join(BUILD, f"sched_{name}.o"), defs))
     return jobs
 

@@ -1,6 +1,7 @@
 // Project-written schedule autotuner: times every registered column schedule
 // of each distinct (H, W, C) group of a plan on the normal operator and keeps
 // the fastest, in the plan and in an in-process cache.
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <string>
@@ -47,4 +48,44 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   return hipGetLastError() == hipSuccess ? MRX_OK : fail(MRX_EHIP, "autotune: launch failed");
+}
+
+// Text form of the cache, one entry a line: "H W C schedule_name".
+extern "C" mrx_status mrx_tune_cache_save(const char* path) {
+  if (!path) return fail(MRX_EINVAL, "tune_cache_save: null path");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(MRX_EINVAL, std::string("tune_cache_save: cannot open ") + path);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune_cache)
+      fprintf(f, "%d %d %d %s\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+              kv.second.c_str());
+  }
+  return fclose(f) == 0 ? MRX_OK : fail(MRX_EINVAL, std::string("tune_cache_save: write failed: ") + path);
+}
+
+extern "C" mrx_status mrx_tune_cache_load(const char* path, int32_t* n_loaded) {
+  if (!path) return fail(MRX_EINVAL, "tune_cache_load: null path");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(MRX_EINVAL, std::string("tune_cache_load: cannot open ") + path);
+  std::map<std::tuple<int, int, int>, std::string> entries;
+  char line[512];
+  int lineno = 0;
+  while (fgets(line, sizeof line, f)) {
+    ++lineno;
+    int H = 0, W = 0, C = 0;
+    char name[256] = {0};
+    if (line[0] == '\n' || line[0] == '#') continue;
+    if (sscanf(line, "%d %d %d %255s", &H, &W, &C, name) != 4 || !find_col(H, name) || W <= 0 || C <= 0) {
+      fclose(f);
+      return fail(MRX_EINVAL, std::string("tune_cache_load: bad entry at line ") + std::to_string(lineno) +
+                                  " of " + path);
+    }
+    entries[{H, W, C}] = name;
+  }
+  fclose(f);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : entries) g_tune_cache[kv.first] = kv.second;
+  if (n_loaded) *n_loaded = (int32_t)entries.size();
+  return MRX_OK;
 }

@@ -147,6 +147,21 @@ struct Sched {
   static constexpr int NFIN = (LEVELS == 3) ? N3 : N2;
 };
 
+// Synchronisation between the LDS exchanges of a transform.  BlockSync: the T
+// threads of a transform span several wavefronts.  WaveSync: they all belong
+// to one wavefront, whose LDS operations execute in issue order, so only the
+// compiler has to be kept from moving LDS accesses across the exchange.
+struct BlockSync {
+  __device__ static __forceinline__ void sync() { __syncthreads(); }
+};
+struct WaveSync {
+  __device__ static __forceinline__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
 // LDS layouts: element (address a, transform c) of a tile of WT transforms.
 // Column tiles keep the WT transforms interleaved (a * WT + c) so that a row
 // of the image maps to contiguous LDS; row tiles keep each transform
@@ -164,7 +179,7 @@ struct LdsContig {
 
 // Forward transform of the thread's P points (level-1 layout in, final-level
 // layout out).  tw = table of exp(-2 pi i j / N), j < N, in LDS.
-template <class S, class L>
+template <class S, class L, class Sync = BlockSync>
 __device__ __forceinline__ void fft_forward(float2* v, float2* lds, const float2* tw, int tc, int c) {
   // level 1
 #pragma unroll
@@ -174,12 +189,12 @@ __device__ __forceinline__ void fft_forward(float2* v, float2* lds, const float2
 #pragma unroll
     for (int r = 1; r < S::N1; ++r) v[i * S::N1 + r] = cmul(v[i * S::N1 + r], tw[g * r]);
   }
-  __syncthreads();
+  Sync::sync();
 #pragma unroll
   for (int i = 0; i < S::G1; ++i)
 #pragma unroll
     for (int r = 0; r < S::N1; ++r) lds[L::idx(S::a1(tc, i, r), c)] = v[i * S::N1 + r];
-  __syncthreads();
+  Sync::sync();
 #pragma unroll
   for (int i = 0; i < S::G2; ++i)
 #pragma unroll
@@ -195,12 +210,12 @@ __device__ __forceinline__ void fft_forward(float2* v, float2* lds, const float2
     }
   }
   if constexpr (S::LEVELS == 3) {
-    __syncthreads();
+    Sync::sync();
 #pragma unroll
     for (int i = 0; i < S::G2; ++i)
 #pragma unroll
       for (int r = 0; r < S::N2; ++r) lds[L::idx(S::a2(tc, i, r), c)] = v[i * S::N2 + r];
-    __syncthreads();
+    Sync::sync();
 #pragma unroll
     for (int i = 0; i < S::G3; ++i)
 #pragma unroll
@@ -212,17 +227,17 @@ __device__ __forceinline__ void fft_forward(float2* v, float2* lds, const float2
 
 // Exact adjoint of fft_forward (unscaled inverse): final-level layout in,
 // level-1 layout out.
-template <class S, class L>
+template <class S, class L, class Sync = BlockSync>
 __device__ __forceinline__ void fft_inverse(float2* v, float2* lds, const float2* tw, int tc, int c) {
   if constexpr (S::LEVELS == 3) {
 #pragma unroll
     for (int i = 0; i < S::G3; ++i) dft<S::N3, true>(v + i * S::N3);
-    __syncthreads();
+    Sync::sync();
 #pragma unroll
     for (int i = 0; i < S::G3; ++i)
 #pragma unroll
       for (int r = 0; r < S::N3; ++r) lds[L::idx(S::a3(tc, i, r), c)] = v[i * S::N3 + r];
-    __syncthreads();
+    Sync::sync();
 #pragma unroll
     for (int i = 0; i < S::G2; ++i)
 #pragma unroll
@@ -236,12 +251,12 @@ __device__ __forceinline__ void fft_inverse(float2* v, float2* lds, const float2
   }
 #pragma unroll
   for (int i = 0; i < S::G2; ++i) dft<S::N2, true>(v + i * S::N2);
-  __syncthreads();
+  Sync::sync();
 #pragma unroll
   for (int i = 0; i < S::G2; ++i)
 #pragma unroll
     for (int r = 0; r < S::N2; ++r) lds[L::idx(S::a2(tc, i, r), c)] = v[i * S::N2 + r];
-  __syncthreads();
+  Sync::sync();
 #pragma unroll
   for (int i = 0; i < S::G1; ++i)
 #pragma unroll

@@ -218,6 +218,208 @@ k_normal(NormalArgs a) {
   }
 }
 
+// ------------------------------------- normal operator, wave-local variant
+// Each wavefront owns CW = 64 / T adjacent columns and transforms them with
+// its own LDS region, so the exchanges inside the transforms need no
+// workgroup barrier and the wavefronts of a workgroup drift freely.  The G
+// wavefronts of a workgroup work on the same CW columns and take every G-th
+// coil; the coil map of a wavefront's next coil is loaded while the current
+// one is transformed, and the current one is re-read (from L2) for the
+// conjugate multiply.  The G partial sums are added through LDS in a fixed
+// order at the end.
+//
+// Launch: 1-D grid over (slice, column tile) pairs, rounded up to a multiple
+// of 32, arranged so that four consecutive tiles (CW = 4: one 128-byte row
+// segment) get block ids 8 apart and land on the same XCD and its L2.
+template <class Sd, int G>
+__global__ void __launch_bounds__(64 * G, 2)
+k_normal_wl(NormalArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T, CW = 64 / T;
+  static_assert(64 % T == 0, "a transform must fit in one wavefront");
+  using L = LdsInterleaved<N, CW>;
+  __shared__ float2 lds[G * L::SIZE];
+  __shared__ float2 pl[L::SIZE];
+  __shared__ float2 tw[N];
+  __shared__ float mk[N];
+  __shared__ float sc[1];
+
+  const int Lb = blockIdx.x;
+  const int k8 = Lb >> 3;
+  const int tg = (((k8 >> 2) * 8 + (Lb & 7)) << 2) + (k8 & 3);
+  const int si = tg / a.tiles, tile = tg % a.tiles;
+  if (si >= a.nslices) return;
+  const int b = a.slices[si];
+  const SliceDesc d = a.desc[b];
+  if (d.H != N) return;
+  const int W = d.W;
+  if (tile * CW >= W) return;
+  const bool cg = a.mode == 1;
+  if (cg && a.stopped[b]) return;
+  const int lid = threadIdx.x, lane = lid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(lid >> 6);
+  const int c = lane % CW, tc = lane / CW;
+  const int col = tile * CW + c;
+  const bool valid = col < W;
+  // Columns past W (ragged last tile) read column 0 instead: their transforms
+  // are independent of the others and their results are never stored.
+  const unsigned colv = valid ? (unsigned)col : 0u;
+  // Coil-map and image elements of register slot (i, r) sit at row
+  // tc + T i + M1 r: a per-thread offset plus a wave-uniform row offset.
+  const unsigned toff = ((unsigned)tc * (unsigned)W + colv) * (unsigned)sizeof(float2);  // bytes
+  float2* xl = lds + wv * L::SIZE;
+
+  for (int i = lid; i < N; i += 64 * G) {
+    tw[i] = a.tw[i];
+    mk[i] = a.mask[d.moff + (i + N / 2) % N] * (1.0f / N);
+  }
+  if (cg && lid < 64) {
+    float beta = 0.f;
+    if (a.iter > 0) {
+      const float rc = wave_sum_fixed(a.rr_cur + (int64_t)b * a.nrr, a.nrr, lid);
+      const float rp = wave_sum_fixed(a.rr_prev + (int64_t)b * a.nrr, a.nrr, lid);
+      beta = rp > 0.f ? rc / rp : 0.f;
+    }
+    if (lid == 0) sc[0] = beta;
+  }
+  __syncthreads();
+
+  // The operand tile (N rows x CW columns, element (row, j) at LDS row * CW + j)
+  // is loaded once per workgroup; in CG mode it is first replaced by
+  // r + beta p and written back (each element by the thread that read it).
+  {
+    const bool upd = cg && a.iter > 0;
+    const float beta = upd ? sc[0] : 0.f;
+    const float2* pbase = a.pin + d.xoff;
+    const float2* rbase = a.r + d.xoff;
+    float2* pobase = a.pout + d.xoff;
+    for (int e = lid; e < N * CW; e += 64 * G) {
+      const int row = e / CW, j = e % CW;
+      const int cc = tile * CW + j;
+      float2 pv = make_float2(0.f, 0.f);
+      if (cc < W) {
+        const unsigned o = (unsigned)row * (unsigned)W + (unsigned)cc;
+        pv = pbase[o];
+        if (upd) {
+          const float2 rv = rbase[o];
+          pv = make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
+          pobase[o] = pv;
+        }
+      }
+      pl[e] = pv;
+    }
+  }
+  __syncthreads();
+
+  float2 acc[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) acc[k] = make_float2(0.f, 0.f);
+
+  const unsigned plane = (unsigned)N * (unsigned)W;
+  const float2* Sb = a.S + d.soff;
+  const float2* plt = pl + L::idx(tc, c);  // operand slot (i, r) at plt[(T i + M1 r) CW]
+  // Coil-map rows through a buffer resource on the coil plane: the row offset
+  // of slot (i, r) is wave-uniform, the column offset per thread, so the
+  // loads need no vector address arithmetic.
+  auto plane_rsrc = [&](int coil) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(Sb + (size_t)coil * plane), (short)0,
+                                             (int)(plane * sizeof(float2)), 0x00020000);
+  };
+  auto load_coil = [&](float2* dst, int coil) {
+    const auto rs = plane_rsrc(coil);
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const unsigned so = (unsigned)((T * i + Sd::M1 * r) * W) * (unsigned)sizeof(float2);
+        dst[i * Sd::N1 + r] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, toff, so, 0));
+      }
+  };
+  auto body = [&](const float2* sv, int coil) {
+    float2 v[P];
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int k = i * Sd::N1 + r;
+        v[k] = cmul(sv[k], plt[(T * i + Sd::M1 * r) * CW]);
+      }
+    fft_forward<Sd, L, WaveSync>(v, xl, tw, tc, c);
+#pragma unroll
+    for (int i = 0; i < Sd::GFIN; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::NFIN; ++r) {
+        const float m = mk[Sd::freq(tc, i, r)];
+        v[i * Sd::NFIN + r] = cscale(v[i * Sd::NFIN + r], m);
+      }
+    fft_inverse<Sd, L, WaveSync>(v, xl, tw, tc, c);
+    // the conjugate multiply re-reads this coil's values (non-temporal; an
+    // L2 hit)
+    const auto rs = plane_rsrc(coil);
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int k = i * Sd::N1 + r;
+        const unsigned so = (unsigned)((T * i + Sd::M1 * r) * W) * (unsigned)sizeof(float2);
+        const float2 s2 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, toff, so, 2));
+        acc[k] = cadd(acc[k], cmulc(s2, v[k]));
+      }
+  };
+  // two register buffers for the coil maps: the next coil's values load
+  // while the current coil is transformed
+  float2 sa[P], sb[P];
+  if (wv < d.C) load_coil(sa, wv);
+  for (int coil = wv; coil < d.C; coil += 2 * G) {
+    if (coil + G < d.C) load_coil(sb, coil + G);
+    body(sa, coil);
+    if (coil + G >= d.C) break;
+    if (coil + 2 * G < d.C) load_coil(sa, coil + 2 * G);
+    body(sb, coil + G);
+  }
+
+  if constexpr (G > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) xl[L::idx(Sd::a1(tc, i, r), c)] = acc[i * Sd::N1 + r];
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+        for (int r = 0; r < Sd::N1; ++r) {
+          const int id = L::idx(Sd::a1(tc, i, r), c);
+          float2 t = lds[id];
+#pragma unroll
+          for (int g = 1; g < G; ++g) t = cadd(t, lds[g * L::SIZE + id]);
+          acc[i * Sd::N1 + r] = t;
+        }
+    }
+  }
+
+  if (wv == 0) {
+    const float lam = a.lam ? a.lam[b] : 0.f;
+    float dot = 0.f;
+    float2* qbase = a.qout + d.xoff;
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int k = i * Sd::N1 + r;
+        const float2 pv = pl[L::idx(Sd::a1(tc, i, r), c)];
+        const float2 q = make_float2(acc[k].x + lam * pv.x, acc[k].y + lam * pv.y);
+        dot += pv.x * q.x + pv.y * q.y;
+        if (valid) qbase[(unsigned)Sd::a1(tc, i, r) * (unsigned)W + colv] = q;
+      }
+    if (cg) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) dot += __shfl_xor(dot, off, 64);
+      if (lane == 0) a.pq_part[(int64_t)b * a.npq + tile] = dot;
+    }
+  }
+}
+
 // ----------------------------------------------- forward column pass (A, H)
 // v = S_c x, transform along H, keep sampled rows: out[c, k, :] for m[k] = 1
 // gets (-1)^j (F v)[j] / sqrt(H) with k = (j + H/2) mod H.
@@ -427,6 +629,16 @@ hipError_t launch_normal(const NormalArgs& a0, int maxW, hipStream_t s) {
   hipLaunchKernelGGL((k_normal<Sd, WT, G, KS>), grid, dim3(Sd::T * WT * G), 0, s, a);
   return hipGetLastError();
 }
+template <class Sd, int G>
+hipError_t launch_normal_wl(const NormalArgs& a0, int maxW, hipStream_t s) {
+  constexpr int CW = 64 / Sd::T;
+  NormalArgs a = a0;
+  a.tiles = (maxW + CW - 1) / CW;
+  const int total = a.tiles * a.nslices;
+  dim3 grid((unsigned)(((total + 31) / 32) * 32));
+  hipLaunchKernelGGL((k_normal_wl<Sd, G>), grid, dim3(64 * G), 0, s, a);
+  return hipGetLastError();
+}
 template <class Sd, int WT>
 hipError_t launch_fwd_col(const SenseColArgs& a, int maxW, hipStream_t s) {
   dim3 grid((maxW + WT - 1) / WT, a.nslices);
@@ -458,6 +670,20 @@ struct Registrar {
   Registrar(const char* name) {
     ColVariant cv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTC,
                   &launch_normal<Sd, WTC, G, KS>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name};
+    register_col_variant(cv);
+    RowVariant rv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTR,
+                  &launch_fwd_row<Sd, WTR>, &launch_adj_row<Sd, WTR>, name};
+    register_row_variant(rv);
+  }
+};
+
+// Registers a wave-local normal-operator schedule (column passes of the
+// forward and adjoint operators use tiles of WTC columns).
+template <class Sd, int WTC, int WTR, int G>
+struct RegistrarWL {
+  RegistrarWL(const char* name) {
+    ColVariant cv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, 64 / Sd::T,
+                  &launch_normal_wl<Sd, G>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name};
     register_col_variant(cv);
     RowVariant rv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTR,
                   &launch_fwd_row<Sd, WTR>, &launch_adj_row<Sd, WTR>, name};

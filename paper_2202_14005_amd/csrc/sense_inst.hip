@@ -1,11 +1,16 @@
 // One transform schedule for one length, selected by the build with
 //   -DMRX_N1=.. -DMRX_N2=.. -DMRX_N3=.. -DMRX_T=.. -DMRX_WTC=.. -DMRX_WTR=.. -DMRX_G=.. -DMRX_KS=0|1 -DMRX_NAME=".."
+// and -DMRX_WL=1 for the wave-local normal operator (k_normal_wl).
 // It registers its column and row kernels with the schedule registry when
 // the library is loaded.
 #include "sense_impl.h"
 
 namespace mrx {
 namespace {
+#if defined(MRX_WL) && MRX_WL
+RegistrarWL<Sched<MRX_N1, MRX_N2, MRX_N3, MRX_T>, MRX_WTC, MRX_WTR, MRX_G> registrar_(MRX_NAME);
+#else
 Registrar<Sched<MRX_N1, MRX_N2, MRX_N3, MRX_T>, MRX_WTC, MRX_WTR, MRX_G, (MRX_KS != 0)> registrar_(MRX_NAME);
+#endif
 }  // namespace
 }  // namespace mrx

@@ -171,11 +171,32 @@ class Plan:
                                        _stream(self.device)), "cg_dc_backward")
         return ga, gz, gl
 
-    def status(self, clear=False):
-        """Per-slice status bits (uint32 as int64 tensor on the device)."""
-        f = torch.zeros(self.B, dtype=torch.int32, device=self.device)
+    def dc_judge(self, x_net, x_cg, aHy, S, mask, ratio, out=None, choice=None):
+        """Per slice keep x_net unless it is non-finite, flagged, or its
+        residual ||A^H A x - aHy|| exceeds ratio times that of the CG-SENSE
+        result x_cg.  Returns (out, choice int32 [B]: 1 = fallback taken)."""
+        self._img(x_net, "x_net"); self._img(x_cg, "x_cg"); self._img(aHy, "aHy")
+        self._coil(S, "S"); self._mask(mask, "mask")
+        o = self._img(out, "out") if out is not None else self._empty_img()
+        if choice is None:
+            choice = torch.empty(self.B, dtype=torch.int32, device=self.device)
+        elif choice.dtype != torch.int32 or choice.numel() != self.B or not choice.is_contiguous():
+            raise ValueError("choice must be a contiguous int32 tensor [B]")
+        check(lib().mrx_dc_judge(self._h, _ptr(x_net), _ptr(x_cg), _ptr(aHy), _ptr(S), _ptr(mask), float(ratio),
+                                 _ptr(o), _ptr(choice), _stream(self.device)), "dc_judge")
+        return o, choice
+
+    def status(self, clear=False, out=None):
+        """Per-slice status bits (uint32 words in an int32 tensor [B] on the device)."""
+        f = torch.zeros(self.B, dtype=torch.int32, device=self.device) if out is None else out
+        if f.dtype != torch.int32 or f.numel() != self.B or not f.is_contiguous() or f.device != self.device:
+            raise ValueError("out must be a contiguous int32 tensor [B] on the plan's device")
         check(lib().mrx_status_word(self._h, _ptr(f), int(bool(clear)), _stream(self.device)), "status_word")
         return f
+
+    def clear_status(self):
+        """Reset the per-slice status words (enqueued; no copy)."""
+        check(lib().mrx_status_word(self._h, None, 1, _stream(self.device)), "status_word")
 
     def autotune(self, S, mask):
         a = self._empty_img().normal_()
@@ -228,11 +249,13 @@ class Plan:
                                      int(bool(accumulate)), _stream(self.device)), "cnn_backward")
         return gx
 
-    def modl_forward(self, aHy, S, mask, cnn: "CNN", lam, T, n_cg, states=False):
+    def modl_forward(self, aHy, S, mask, cnn: "CNN", lam, T, n_cg, states=False, out=None):
+        """x^T of eq. update_modl from x^0 = aHy; with states=True also the
+        iterates x^0..x^T [T + 1, ...]."""
         self._img(aHy, "aHy"); self._coil(S, "S"); self._mask(mask, "mask")
         self.set_weights(cnn)
         lt = self.lam(lam)
-        x = self._empty_img()
+        x = self._img(out, "out") if out is not None else self._empty_img()
         st = (torch.empty((T + 1,) + tuple(x.shape), dtype=torch.complex64, device=self.device)
               if states else None)
         check(lib().mrx_modl_forward(self._h, _ptr(aHy), _ptr(S), _ptr(mask), _ptr(lt), int(T), int(n_cg),
@@ -461,6 +484,19 @@ def schedules(n: int):
             return out
         out.append(s.decode())
         i += 1
+
+
+def tune_cache_save(path: str):
+    """Write the schedules chosen by Plan.autotune in this process to a file."""
+    check(lib().mrx_tune_cache_save(str(path).encode()), "tune_cache_save")
+
+
+def tune_cache_load(path: str) -> int:
+    """Merge a saved tuning cache; plans created afterwards use it.  Returns
+    the number of entries."""
+    n = ctypes.c_int32(0)
+    check(lib().mrx_tune_cache_load(str(path).encode(), ctypes.byref(n)), "tune_cache_load")
+    return n.value
 
 
 def supported_length(n: int) -> bool:

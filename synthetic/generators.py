@@ -186,3 +186,30 @@ def batch_inputs(seeds, H: int, W: int, C: int, R: int, n_center: int,
     noise [B,C,H,W]."""
     sl = [slice_inputs(s, H, W, C, R, n_center, mask_kind, sigma) for s in seeds]
     return {k: np.stack([d[k] for d in sl]) for k in sl[0]}
+
+
+# Matrix sizes of the uneven-batch workload (H x W), drawn per slice.
+UNEVEN_SHAPES = ((192, 192), (256, 256), (320, 320), (384, 320))
+
+
+def uneven_specs(seed: int, n: int = 64, shapes=UNEVEN_SHAPES, coils=(8, 20), accel=(4, 6, 8)):
+    """Per-slice (H, W, C, R) of an uneven batch: shape uniform over ``shapes``,
+    C ~ U{coils[0]..coils[1]}, R uniform over ``accel``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        H, W = shapes[int(rng.integers(0, len(shapes)))]
+        C = int(rng.integers(coils[0], coils[1] + 1))
+        R = int(accel[int(rng.integers(0, len(accel)))])
+        out.append((H, W, C, R))
+    return out
+
+
+def uneven_inputs(specs, seed0: int, n_center: int = 24, mask_kind: str = "vd", sigma: float = 1e-3):
+    """``slice_inputs`` for each (H, W, C, R) of ``specs`` (seed seed0 + i),
+    plus the same arrays packed flat in slice order (images, coil data and
+    masks concatenated)."""
+    sl = [slice_inputs(seed0 + i, H, W, C, R, min(n_center, H // R), mask_kind, sigma)
+          for i, (H, W, C, R) in enumerate(specs)]
+    packed = {k: np.concatenate([s[k].ravel() for s in sl]) for k in sl[0]}
+    return sl, packed

@@ -76,3 +76,21 @@ def test_operators_reject_null_plan():
     assert "null plan" in L.mrx_last_error().decode()
     assert L.mrx_cg_dc(None, None, None, None, None, None, 10, None, None, None) == -1
     assert L.mrx_plan_workspace_bytes(None) == 0
+
+
+def test_tune_cache_file_roundtrip_and_errors(tmp_path):
+    from paper_2202_14005_amd import ops
+    from paper_2202_14005_amd._lib import MrxError
+    name = ops.schedules(320)[0]
+    good = tmp_path / "good.txt"
+    good.write_text(f"# comment\n320 320 15 {name}\n")
+    assert ops.tune_cache_load(str(good)) == 1
+    out = tmp_path / "saved.txt"
+    ops.tune_cache_save(str(out))
+    assert f"320 320 15 {name}" in out.read_text().splitlines()
+    bad = tmp_path / "bad.txt"
+    bad.write_text(f"320 320 15 {name}\n320 320 15 no_such_schedule\n")
+    with pytest.raises(MrxError, match="line 2"):
+        ops.tune_cache_load(str(bad))
+    with pytest.raises(MrxError):
+        ops.tune_cache_load(str(tmp_path / "missing.txt"))

@@ -196,3 +196,28 @@ def test_full_size_batch_parity():
     assert rel(host(a), aref) < OP_TOL
     xref, _ = ocg.cg_dc(host(a), None, d["S"], d["mask"], np.full(B, 0.05), 10)
     assert rel(host(xs), xref) < CG_TOL
+
+
+@pytest.mark.parametrize("H,W,C", [(320, 30, 5), (384, 36, 4), (256, 20, 7), (192, 24, 3), (128, 40, 6)])
+def test_every_schedule_normal_and_cg(H, W, C):
+    """Each registered column schedule of a length (workgroup-tiled and
+    wave-local variants) against the oracle, on a ragged last column tile."""
+    from paper_2202_14005_amd import ops
+    B = 2
+    d = inputs([1700 + i for i in range(B)], H, W, C)
+    y = osense.measure(d["x"], d["S"], d["mask"], d["noise"])
+    aHy = osense.sense_adj(y, d["S"], d["mask"]).astype(np.complex64)
+    q_ref = osense.sense_normal(d["x"], d["S"], d["mask"], 0.1)
+    x_ref, _ = ocg.cg_dc(aHy, None, d["S"], d["mask"], np.full(B, 0.05), 10)
+    S, m = dev(d["S"]), dev(d["mask"])
+    names = ops.schedules(H)
+    assert names
+    for name in names:
+        plan = Plan(H, W, C, B=B)
+        plan.set_schedule(H, name)
+        assert plan.schedule(0) == name
+        e_q = rel(host(plan.sense_normal(dev(d["x"]), S, m, 0.1)), q_ref)
+        e_x = rel(host(plan.cg_dc(dev(aHy), S, m, 0.05, 10)), x_ref)
+        print(f"{name}: normal {e_q:.2e} cg {e_x:.2e}")
+        assert e_q < OP_TOL, name
+        assert e_x < CG_TOL, name
