@@ -97,7 +97,11 @@ class MoDLNet(torch.nn.Module):
         self.cnn = CNN(list(self.weights), list(self.biases))
 
     def forward(self, y, S, mask):
-        aHy = self.plan.sense_adj(y, S, mask)
+        """Reconstruct from k-space y (x^0 = A^H y computed here)."""
+        return self.forward_from_adjoint(self.plan.sense_adj(y, S, mask), S, mask)
+
+    def forward_from_adjoint(self, aHy, S, mask):
+        """Reconstruct from a precomputed A^H y (differentiable w.r.t. it)."""
         params = []
         for w, b in zip(self.weights, self.biases):
             params += [w, b]

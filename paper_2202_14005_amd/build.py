@@ -26,7 +26,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # height, coil groups per normal-operator workgroup, keep coil values in
 # registers (1) or re-read them from L2 (0), and optionally 1 for the
 # wave-local normal operator (each wavefront transforms 64 / T columns with
-# its own LDS region; G wavefronts per workgroup split the coils).
+# its own LDS region; G wavefronts per workgroup split the coils), 2 for the
+# same with a padded LDS layout; optionally the coil split of CG steps (a
+# column tile's coils over that many workgroups, partial outputs added by
+# the CG update).
 # The first schedule listed for a length is its default; the autotuner
 # times all schedules of a length on the normal operator.
 SCHEDULES = [
@@ -70,6 +73,21 @@ SCHEDULES = [
     ("n320_4x4x20_t16_wl_g5", 4, 4, 20, 16, 16, 16, 5, 1, 1),
     ("n384_4x4x24_t16_wl_g3", 4, 4, 24, 16, 16, 16, 3, 1, 1),
     ("n384_4x4x24_t16_wl_g4", 4, 4, 24, 16, 16, 16, 4, 1, 1),
+    ("n192_4x4x12_t16_wlp_g4", 4, 4, 12, 16, 16, 16, 4, 1, 2),
+    ("n256_4x4x16_t16_wlp_g4", 4, 4, 16, 16, 16, 16, 4, 1, 2),
+    ("n320_4x4x20_t16_wlp_g2", 4, 4, 20, 16, 16, 16, 2, 1, 2),
+    ("n320_4x4x20_t16_wlp_g4", 4, 4, 20, 16, 16, 16, 4, 1, 2),
+    ("n384_4x4x24_t16_wlp_g4", 4, 4, 24, 16, 16, 16, 4, 1, 2),
+    ("n192_4x4x12_t16_w16_k3", 4, 4, 12, 16, 16, 16, 1, 1, 0, 3),
+    ("n256_4x4x16_t16_w16_k3", 4, 4, 16, 16, 16, 16, 1, 1, 0, 3),
+    ("n320_4x4x20_t16_w16_k2", 4, 4, 20, 16, 16, 16, 1, 1, 0, 2),
+    ("n320_4x4x20_t16_w16_k3", 4, 4, 20, 16, 16, 16, 1, 1, 0, 3),
+    ("n320_4x4x20_t16_w16_k4", 4, 4, 20, 16, 16, 16, 1, 1, 0, 4),
+    ("n320_4x4x20_t16_w16_rl_k3", 4, 4, 20, 16, 16, 16, 1, 0, 0, 3),
+    ("n320_4x4x20_t16_w16_g2_rl_k2", 4, 4, 20, 16, 16, 16, 2, 0, 0, 2),
+    ("n320_4x4x20_t16_w16_g2_rl_k3", 4, 4, 20, 16, 16, 16, 2, 0, 0, 3),
+    ("n320_4x4x20_t16_w8_g2_rl_k2", 4, 4, 20, 16, 8, 16, 2, 0, 0, 2),
+    ("n384_4x4x24_t16_w16_k3", 4, 4, 24, 16, 16, 16, 1, 1, 0, 3),
 ]
 
 COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net.hip", "conv.hip",
@@ -96,9 +114,10 @@ def _jobs():
     for entry in SCHEDULES:
         name, n1, n2, n3, t, wtc, wtr, g, ks = entry[:9]
         wl = entry[9] if len(entry) > 9 else 0
+        kspl = entry[10] if len(entry) > 10 else 1
         defs = [f"-DMRX_N1={n1}", f"-DMRX_N2={n2}", f"-DMRX_N3={n3}", f"-DMRX_T={t}",
                 f"-DMRX_WTC={wtc}", f"-DMRX_WTR={wtr}", f"-DMRX_G={g}", f"-DMRX_KS={ks}",
-                f"-DMRX_WL={wl}", f'-DMRX_NAME="{name}"']
+                f"-DMRX_WL={wl}", f"-DMRX_KSPL={kspl}", f'-DMRX_NAME="{name}"']
         jobs.append((os.path.join(CSRC, "sense_inst.hip"), os.path.join(BUILD, f"sched_{name}.o"), defs))
     return jobs
 

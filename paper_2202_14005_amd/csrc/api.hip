@@ -140,7 +140,8 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
       g.rowH = find_row(g.H);
     }
   }
-  p->npq = (p->maxW + 1) / 2;  // upper bound on column tiles (tile width >= 2)
+  refresh_desc(p, false);
+  p->npq = (p->maxW + 1) / 2;  // upper bound on column tiles x coil split (tile width >= 8)
   p->nrr = (int)((p->maxHW + CG_EPB - 1) / CG_EPB);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { delete p; return hip_fail(e, "plan_create: hipGetDevice"); }
@@ -187,7 +188,8 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   p->ws_tmp = take(sizeof(float2) * p->n_coil);
   p->ws_r = take(sizeof(float2) * p->n_image);
   p->ws_p = take(sizeof(float2) * p->n_image);
-  p->ws_q = take(sizeof(float2) * p->n_image);
+  p->ws_p2 = take(sizeof(float2) * p->n_image);
+  p->ws_q = take(sizeof(float2) * p->n_image * KSPL_MAX);
   p->ws_v = take(sizeof(float2) * p->n_image);
   p->ws_pq = take(sizeof(float) * B * p->npq);
   p->ws_rr0 = take(sizeof(float) * B * p->nrr);
@@ -336,7 +338,7 @@ mrx_status mrx_plan_set_schedule(mrx_plan p, int32_t n, const char* name) {
   for (auto& g : p->groups)
     if (g.H == n) { g.col = v; any = true; }
   if (!any) return fail(MRX_EINVAL, "plan_set_schedule: no slice of the plan has that H");
-  return MRX_OK;
+  return refresh_desc(p, true);
 }
 
 const char* mrx_plan_schedule(mrx_plan p, int32_t b) {

@@ -41,7 +41,7 @@ struct mrx_plan_s {
   // borrowed workspace and its layout (byte offsets)
   char* ws = nullptr;
   size_t ws_given = 0, ws_bytes = 0, ws_bytes_base = 0;
-  size_t ws_tmp = 0, ws_r = 0, ws_p = 0, ws_q = 0, ws_v = 0;
+  size_t ws_tmp = 0, ws_r = 0, ws_p = 0, ws_p2 = 0, ws_q = 0, ws_v = 0;  // ws_q: KSPL_MAX planes
   size_t ws_pq = 0, ws_rr0 = 0, ws_rr1 = 0, ws_part = 0, ws_stop = 0, ws_status = 0;
   uint32_t flags = 0;
   // network workspace (set by extra_workspace_bytes)
@@ -67,6 +67,9 @@ extern std::mutex g_tune_mu;
 extern std::map<std::tuple<int, int, int>, std::string> g_tune_cache;
 
 size_t extra_workspace_bytes(mrx_plan_s* p);
+// Set desc[b].nq from the column schedule of each slice's group; with
+// upload, also copy the descriptors to the device (synchronous).
+mrx_status refresh_desc(mrx_plan_s* p, bool upload);
 size_t vn_workspace_bytes(mrx_plan_s* p, size_t base);
 CgElemArgs elem_args(mrx_plan_s* p, const float* lam);
 hipError_t clear_status(mrx_plan_s* p, hipStream_t s);

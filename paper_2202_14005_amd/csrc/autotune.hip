@@ -47,7 +47,8 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  return hipGetLastError() == hipSuccess ? MRX_OK : fail(MRX_EHIP, "autotune: launch failed");
+  if (hipGetLastError() != hipSuccess) return fail(MRX_EHIP, "autotune: launch failed");
+  return refresh_desc(p, true);
 }
 
 // Text form of the cache, one entry a line: "H W C schedule_name".

@@ -25,7 +25,8 @@ struct CgElemArgs {
   float2* x;             // bwd tail: the adjoint solution v
   float2* r;
   float2* p;
-  const float2* q;
+  const float2* q;       // q = sum of desc[b].nq partial planes, qstride apart
+  int64_t qstride;
   const float* pq;       // [B][npq]
   const float* rr_cur;   // [B][nrr]
   float* rr_next;        // [B][nrr]

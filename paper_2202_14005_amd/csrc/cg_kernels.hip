@@ -94,7 +94,9 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_update(CgElemArgs a) {
     const int64_t o = d.xoff + i;
     float2 r = a.r[o];
     if (!stop) {
-      const float2 p = a.p[o], q = a.q[o];
+      const float2 p = a.p[o];
+      float2 q = a.q[o];
+      for (int k = 1; k < d.nq; ++k) q = cadd(q, a.q[k * a.qstride + o]);
       float2 x = a.x[o];
       x.x += alpha * p.x; x.y += alpha * p.y;
       r.x -= alpha * q.x; r.y -= alpha * q.y;

@@ -9,7 +9,8 @@ namespace mrx {
 // of the respective packed buffer: image-sized buffers (x, p, q, ...) use
 // xoff, coil-sized buffers (S, y) use soff, masks use moff.
 struct SliceDesc {
-  int32_t H, W, C, pad_;
+  int32_t H, W, C;
+  int32_t nq;  // partial planes of the normal operator's output in CG mode (coil split)
   int64_t xoff, soff, moff;
 };
 

@@ -46,25 +46,50 @@ constexpr int TILE_PX = (CONV_TH + 2) * (CONV_TW + 2);
 
 __device__ __forceinline__ int swz(int px) { return (px >> 1) & 7; }
 
+// Fill the LDS tile: every thread owns the chunks q = tid + 256 k; the loads
+// of a batch are all issued before any of them is written to LDS, so the
+// memory latency is paid once per batch rather than once per chunk.
+constexpr int TILE_CHUNKS = TILE_PX * 8;
+constexpr int TILE_PER_THREAD = (TILE_CHUNKS + 255) / 256;
+
 __device__ __forceinline__ void load_tile64(uint4* tile, const uint16_t* in, int H, int W, int ty0, int tx0) {
-  for (int q = threadIdx.x; q < TILE_PX * 8; q += 256) {
-    const int px = q >> 3, ch = q & 7;
-    const int ly = px / (CONV_TW + 2), lx = px % (CONV_TW + 2);
-    const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = ldg16(in + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
-    tile[px * 8 + (ch ^ swz(px))] = v;
+  constexpr int BATCH = 10;
+#pragma unroll
+  for (int k0 = 0; k0 < TILE_PER_THREAD; k0 += BATCH) {
+    uint4 v[BATCH];
+    int slot[BATCH];
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j) {
+      const int q = threadIdx.x + 256 * (k0 + j);
+      v[j] = make_uint4(0, 0, 0, 0);
+      slot[j] = -1;
+      if (k0 + j < TILE_PER_THREAD && q < TILE_CHUNKS) {
+        const int px = q >> 3, ch = q & 7;
+        const int ly = px / (CONV_TW + 2), lx = px - ly * (CONV_TW + 2);
+        const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+        slot[j] = px * 8 + (ch ^ swz(px));
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) v[j] = ldg16(in + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j)
+      if (slot[j] >= 0) tile[slot[j]] = v[j];
   }
 }
 
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return (h & 0x8000u) == 0 && h != 0; }
 
 // ------------------------------------------------------------- 64 -> 64
-// Two workgroups per CU (2 x 78 KB of LDS, <= 256 registers per lane) so
-// one workgroup's tile fill overlaps the other's MFMAs; the weight fragments
-// of step s + 1 are fetched while step s runs.
+// Each wave computes 4 rows x 32 columns x 64 output channels (8
+// accumulator blocks of 32 x 32).  K runs over 9 taps x 4 chunks of 16 input
+// channels; the weight fragments of the next tap are fetched from L2 while
+// the current tap runs (two register sets used in turn, so the loop carries
+// no register copies).  Bias (forward) or the ReLU mask
+// source (input gradient) is fetched ahead of the epilogue.  Sized for two
+// workgroups per CU (2 x 78 KB of LDS).
 __global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
   __shared__ uint4 tile[TILE_PX * 8];
+  __shared__ float sbias[CNN_F];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
@@ -72,13 +97,15 @@ __global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
   if (tx0 >= W || ty0 >= H) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint16_t* wp = a.wpk + lane * 8;
-  // ring of the next four steps' weight fragments (step = tap * 4 + kc)
-  uint4 wr[4][2];
+  // weight fragments of one tap (4 chunks x 2 output blocks); two sets in
+  // turn: the next tap's fragments load while the current tap runs
+  uint4 wa[4][2], wb[4][2];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    wr[k][0] = ldg16(wp + (k * 2 + 0) * 512);
-    wr[k][1] = ldg16(wp + (k * 2 + 1) * 512);
+  for (int kc = 0; kc < 4; ++kc) {
+    wa[kc][0] = ldg16(wp + (kc * 2 + 0) * 512);
+    wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
   }
+  if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
   load_tile64(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
   __syncthreads();
   f32x16 acc[2][4];
@@ -89,50 +116,71 @@ __global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[m][n][v] = 0.f;
   const int pbase = wv * 4 * (CONV_TW + 2) + (lane & 31);
-  for (int tap = 0; tap < 9; ++tap) {
+  const int hsel = lane >> 5;
+  auto tap_step = [&](int tap, uint4 (&cur)[4][2], uint4 (&nxt)[4][2]) {
     const int dy = tap / 3, dx = tap - 3 * dy;
-    const int p0 = pbase + dy * (CONV_TW + 2) + dx;
+    if (tap + 1 < 9) {
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-      const bf16x8 w0 = as_bf16x8(wr[kc][0]), w1 = as_bf16x8(wr[kc][1]);
-      const int nxt = (tap + 1) * 4 + kc;
-      if (nxt < 36) {
-        wr[kc][0] = ldg16(wp + (nxt * 2 + 0) * 512);
-        wr[kc][1] = ldg16(wp + (nxt * 2 + 1) * 512);
-      }
-      const int ch = kc * 2 + (lane >> 5);
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int px = p0 + nb * (CONV_TW + 2);
-        const bf16x8 bv = as_bf16x8(tile[px * 8 + (ch ^ swz(px))]);
-        acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, bv, acc[0][nb], 0, 0, 0);
-        acc[1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bv, acc[1][nb], 0, 0, 0);
+      for (int kc = 0; kc < 4; ++kc) {
+        nxt[kc][0] = ldg16(wp + (((tap + 1) * 4 + kc) * 2 + 0) * 512);
+        nxt[kc][1] = ldg16(wp + (((tap + 1) * 4 + kc) * 2 + 1) * 512);
       }
     }
+    // keep the scheduler from sinking these loads next to their use
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const bf16x8 w0 = as_bf16x8(cur[kc][0]), w1 = as_bf16x8(cur[kc][1]);
+      const int ch = kc * 2 + hsel;
+      bf16x8 bv[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int px = pbase + (dy + nb) * (CONV_TW + 2) + dx;
+        bv[nb] = as_bf16x8(tile[px * 8 + (ch ^ swz(px))]);
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, bv[nb], acc[0][nb], 0, 0, 0);
+        acc[1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bv[nb], acc[1][nb], 0, 0, 0);
+      }
+    }
+  };
+  for (int tap = 0; tap < 8; tap += 2) {
+    tap_step(tap, wa, wb);
+    tap_step(tap + 1, wb, wa);
   }
+  tap_step(8, wa, wb);
   uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
   const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
+  const int gx = tx0 + (lane & 31);
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
-    const int gy = ty0 + wv * 4 + nb, gx = tx0 + (lane & 31);
-    if (gy >= H || gx >= W) continue;
-    const int64_t po = ((int64_t)gy * W + gx) * CNN_F;
+    const int gy = ty0 + wv * 4 + nb;
+    const bool ok = gy < H && gx < W;
+    const int64_t po = ok ? ((int64_t)gy * W + gx) * CNN_F : 0;
+    uint2 mref[2][4];
+    if (a.mode == CONV_DGRAD) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          mref[m][g] = ok ? *(const uint2*)(rref + po + m * 32 + 8 * g + hsel * 4) : make_uint2(0, 0);
+    }
+    if (!ok) continue;
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int co0 = m * 32 + 8 * g + (lane >> 5) * 4;
+        const int co0 = m * 32 + 8 * g + hsel * 4;
         float hv[4];
-        uint2 mref = make_uint2(0, 0);
-        if (a.mode == CONV_DGRAD) mref = *(const uint2*)(rref + po + co0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float v = acc[m][nb][4 * g + j];
           if (a.mode == CONV_FWD) {
-            v += a.bias[co0 + j];
+            v += sbias[co0 + j];
             v = v > 0.f ? v : 0.f;
           } else {
-            const uint32_t word = (j < 2) ? mref.x : mref.y;
+            const uint32_t word = (j < 2) ? mref[m][g].x : mref[m][g].y;
             const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
             if (!bf_pos(r)) v = 0.f;
           }

@@ -171,6 +171,14 @@ struct LdsInterleaved {
   static constexpr int SIZE = N * WT;
   __device__ static __forceinline__ int idx(int a, int c) { return a * WT + c; }
 };
+// Interleaved with CW = WT transforms and one pad row of WT slots after
+// every SEG addresses: for WT = 4 and SEG = N3 the reads of the last level
+// (addresses N3 apart across threads) fall in distinct bank groups.
+template <int N, int WT, int SEG>
+struct LdsPadded {
+  static constexpr int SIZE = (N + N / SEG) * WT;
+  __device__ static __forceinline__ int idx(int a, int c) { return (a + a / SEG) * WT + c; }
+};
 template <int N, int WT>
 struct LdsContig {
   static constexpr int SIZE = (N + 1) * WT;

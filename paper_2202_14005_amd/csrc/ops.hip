@@ -22,6 +22,14 @@ hipError_t clear_status(mrx_plan_s* p, hipStream_t s) {
   return fill_u32((uint32_t*)(p->ws + p->ws_status), 0u, p->B, s);
 }
 
+mrx_status refresh_desc(mrx_plan_s* p, bool upload) {
+  for (auto& g : p->groups)
+    for (int b : g.slices) p->desc[b].nq = (g.col && g.col->kspl > 1) ? g.col->kspl : 1;
+  if (!upload) return MRX_OK;
+  hipError_t e = hipMemcpy(p->d_desc, p->desc.data(), sizeof(SliceDesc) * p->B, hipMemcpyHostToDevice);
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "plan: descriptor upload");
+}
+
 CgElemArgs elem_args(mrx_plan_s* p, const float* lam) {
   CgElemArgs a{};
   a.desc = p->d_desc;
@@ -73,7 +81,11 @@ mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const fl
 mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,
                    const float* lam, int n_iter, float2* x, float* hist, hipStream_t s) {
   float2* r = (float2*)(p->ws + p->ws_r);
-  float2* pv = (float2*)(p->ws + p->ws_p);
+  // p_k lives in pb[k & 1]: the step that forms p_k = r_k + beta p_{k-1}
+  // reads the other buffer, so workgroups splitting a tile's coils never
+  // see a half-updated p
+  float2* pb[2] = {(float2*)(p->ws + p->ws_p), (float2*)(p->ws + p->ws_p2)};
+  float2* pv = pb[0];
   float2* q = (float2*)(p->ws + p->ws_q);
   float* pq = (float*)(p->ws + p->ws_pq);
   float* rr[2] = {(float*)(p->ws + p->ws_rr0), (float*)(p->ws + p->ws_rr1)};
@@ -84,6 +96,7 @@ mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const floa
   a.r = r;
   a.p = pv;
   a.q = q;
+  a.qstride = p->n_image;
   a.pq = pq;
   a.hist = hist;
   a.rr_next = rr[0];
@@ -108,13 +121,14 @@ mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const floa
       na.S = S;
       na.mask = mask;
       na.lam = lam;
-      na.pin = pv;
+      na.pin = pb[k == 0 ? 0 : ((k - 1) & 1)];
       na.qout = q;
+      na.qstride = p->n_image;
       na.tw = p->tw.at(g.H);
       na.mode = 1;
       na.iter = k;
       na.r = r;
-      na.pout = pv;
+      na.pout = pb[k & 1];
       na.rr_cur = rr_cur;
       na.rr_prev = rr_prev;
       na.nrr = p->nrr;
@@ -126,6 +140,7 @@ mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const floa
     }
     a.rr_cur = rr_cur;
     a.rr_next = rr_prev;  // rho_{k+1} overwrites rho_{k-1}
+    a.p = pb[k & 1];
     e = cg_update(a, s);
     if (e != hipSuccess) return hip_fail(e, "cg: update");
   }

@@ -1,6 +1,8 @@
 // Kernel templates for the SENSE column and row passes.  Included by the
 // per-length instantiation units only.
 #pragma once
+#include <type_traits>
+
 #include "fft.h"
 #include "sense_kernels.h"
 
@@ -53,8 +55,8 @@ __device__ __forceinline__ float block_sum_fixed(float v, float* red) {
 // to the 8 XCDs round-robin) and share its L2.
 // KS: keep the coil values in registers for the conjugate multiply instead
 // of re-reading them from L2.
-template <class Sd, int WT, int G, bool KS>
-__global__ void __launch_bounds__(Sd::T * WT * G)
+template <class Sd, int WT, int G, bool KS, int KSPL>
+__global__ void __launch_bounds__(Sd::T * WT * G, 2)
 k_normal(NormalArgs a) {
   constexpr int N = Sd::N, P = Sd::P, T = Sd::T, NT = T * WT;
   using L = LdsInterleaved<N, WT>;
@@ -65,7 +67,8 @@ k_normal(NormalArgs a) {
   __shared__ float sc[2];
 
   const int Lb = blockIdx.x;
-  const int tg = (((Lb >> 4) * 8 + (Lb & 7)) << 1) + ((Lb >> 3) & 1);
+  const int ug = (((Lb >> 4) * 8 + (Lb & 7)) << 1) + ((Lb >> 3) & 1);
+  const int ks = ug % KSPL, tg = ug / KSPL;
   const int si = tg / a.tiles, tile = tg % a.tiles;
   if (si >= a.nslices) return;
   const int b = a.slices[si];
@@ -73,6 +76,8 @@ k_normal(NormalArgs a) {
   if (d.H != N) return;
   const int W = d.W;
   if (tile * WT >= W) return;
+  // this workgroup's coils: [c_begin, c_end) of the slice's C
+  const int c_begin = (ks * d.C) / KSPL, c_end = ((ks + 1) * d.C) / KSPL;
   const int lid = threadIdx.x;
   const int grp = lid / NT, l2 = lid % NT;
   const int c = l2 % WT, tc = l2 / WT;
@@ -113,10 +118,12 @@ k_normal(NormalArgs a) {
         pv = make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
         p[i * Sd::N1 + r] = pv;
       }
-    // p is updated in place (pout == pin): every group must have read the
-    // old values before group 0 writes the new ones.
-    if constexpr (G > 1) __syncthreads();
-    if (valid && grp == 0) {
+    // p updated in place (pout == pin): every group must have read the old
+    // values before group 0 writes the new ones.  With a coil split the
+    // workgroups of a tile all read pin, so pout must be another buffer; the
+    // first split writes it.
+    if (G > 1 && a.pout == a.pin) __syncthreads();
+    if (valid && grp == 0 && ks == 0) {
 #pragma unroll
       for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
@@ -138,11 +145,11 @@ k_normal(NormalArgs a) {
 
   const int64_t plane = (int64_t)N * W;
   const float2* Sb = a.S + d.soff;
-  const int iters = (d.C + G - 1) / G;
+  const int iters = (c_end - c_begin + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
-    const int coil = it * G + grp;
-    const bool on = valid && coil < d.C;
-    const float2* Sc = Sb + (int64_t)(coil < d.C ? coil : 0) * plane;
+    const int coil = c_begin + it * G + grp;
+    const bool on = valid && coil < c_end;
+    const float2* Sc = Sb + (int64_t)(coil < c_end ? coil : c_begin) * plane;
     float2 v[P];
     float2 sk[KS ? P : 1];
 #pragma unroll
@@ -198,10 +205,11 @@ k_normal(NormalArgs a) {
     }
   }
 
-  const float lam = a.lam ? a.lam[b] : 0.f;
+  // the first split adds lambda p; each split writes its own partial plane
+  const float lam = (a.lam && ks == 0) ? a.lam[b] : 0.f;
   float dot = 0.f;
   if (grp == 0) {
-    float2* qbase = a.qout + d.xoff;
+    float2* qbase = a.qout + (int64_t)ks * a.qstride + d.xoff;
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
@@ -214,7 +222,7 @@ k_normal(NormalArgs a) {
   }
   if (cg) {
     const float s = block_sum_fixed(dot, red);
-    if (lid == 0) a.pq_part[(int64_t)b * a.npq + tile] = s;
+    if (lid == 0) a.pq_part[(int64_t)b * a.npq + tile * KSPL + ks] = s;
   }
 }
 
@@ -231,14 +239,15 @@ k_normal(NormalArgs a) {
 // Launch: 1-D grid over (slice, column tile) pairs, rounded up to a multiple
 // of 32, arranged so that four consecutive tiles (CW = 4: one 128-byte row
 // segment) get block ids 8 apart and land on the same XCD and its L2.
-template <class Sd, int G>
+template <class Sd, int G, bool PAD>
 __global__ void __launch_bounds__(64 * G, 2)
 k_normal_wl(NormalArgs a) {
   constexpr int N = Sd::N, P = Sd::P, T = Sd::T, CW = 64 / T;
   static_assert(64 % T == 0, "a transform must fit in one wavefront");
-  using L = LdsInterleaved<N, CW>;
+  using L = std::conditional_t<PAD && Sd::LEVELS == 3 && Sd::N3 % 4 == 0, LdsPadded<N, CW, Sd::N3>,
+                               LdsInterleaved<N, CW>>;
   __shared__ float2 lds[G * L::SIZE];
-  __shared__ float2 pl[L::SIZE];
+  __shared__ float2 pl[N * CW];
   __shared__ float2 tw[N];
   __shared__ float mk[N];
   __shared__ float sc[1];
@@ -316,7 +325,7 @@ k_normal_wl(NormalArgs a) {
 
   const unsigned plane = (unsigned)N * (unsigned)W;
   const float2* Sb = a.S + d.soff;
-  const float2* plt = pl + L::idx(tc, c);  // operand slot (i, r) at plt[(T i + M1 r) CW]
+  const float2* plt = pl + tc * CW + c;  // operand slot (i, r) at plt[(T i + M1 r) CW]
   // Coil-map rows through a buffer resource on the coil plane: the row offset
   // of slot (i, r) is wave-uniform, the column offset per thread, so the
   // loads need no vector address arithmetic.
@@ -407,7 +416,7 @@ k_normal_wl(NormalArgs a) {
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
         const int k = i * Sd::N1 + r;
-        const float2 pv = pl[L::idx(Sd::a1(tc, i, r), c)];
+        const float2 pv = plt[(T * i + Sd::M1 * r) * CW];
         const float2 q = make_float2(acc[k].x + lam * pv.x, acc[k].y + lam * pv.y);
         dot += pv.x * q.x + pv.y * q.y;
         if (valid) qbase[(unsigned)Sd::a1(tc, i, r) * (unsigned)W + colv] = q;
@@ -620,23 +629,33 @@ k_adj_row(SenseRowArgs a) {
 }
 
 // ------------------------------------------------------------- launchers
-template <class Sd, int WT, int G, bool KS>
+// Operator applications (mode 0) run unsplit; CG steps (mode 1) split each
+// column tile's coils over KSPL workgroups writing partial planes that the CG
+// update adds (a.qstride apart; pin and pout must then differ).
+template <class Sd, int WT, int G, bool KS, int KSPL>
 hipError_t launch_normal(const NormalArgs& a0, int maxW, hipStream_t s) {
   NormalArgs a = a0;
   a.tiles = (maxW + WT - 1) / WT;
-  const int total = a.tiles * a.nslices;
-  dim3 grid((unsigned)(((total + 15) / 16) * 16));
-  hipLaunchKernelGGL((k_normal<Sd, WT, G, KS>), grid, dim3(Sd::T * WT * G), 0, s, a);
+  if (a.mode == 1 && KSPL > 1) {
+    if (a.tiles * KSPL > a.npq || (a.iter > 0 && a.pin == a.pout)) return hipErrorInvalidValue;
+    const int total = a.tiles * a.nslices * KSPL;
+    dim3 grid((unsigned)(((total + 15) / 16) * 16));
+    hipLaunchKernelGGL((k_normal<Sd, WT, G, KS, KSPL>), grid, dim3(Sd::T * WT * G), 0, s, a);
+  } else {
+    const int total = a.tiles * a.nslices;
+    dim3 grid((unsigned)(((total + 15) / 16) * 16));
+    hipLaunchKernelGGL((k_normal<Sd, WT, G, KS, 1>), grid, dim3(Sd::T * WT * G), 0, s, a);
+  }
   return hipGetLastError();
 }
-template <class Sd, int G>
+template <class Sd, int G, bool PAD>
 hipError_t launch_normal_wl(const NormalArgs& a0, int maxW, hipStream_t s) {
   constexpr int CW = 64 / Sd::T;
   NormalArgs a = a0;
   a.tiles = (maxW + CW - 1) / CW;
   const int total = a.tiles * a.nslices;
   dim3 grid((unsigned)(((total + 31) / 32) * 32));
-  hipLaunchKernelGGL((k_normal_wl<Sd, G>), grid, dim3(64 * G), 0, s, a);
+  hipLaunchKernelGGL((k_normal_wl<Sd, G, PAD>), grid, dim3(64 * G), 0, s, a);
   return hipGetLastError();
 }
 template <class Sd, int WT>
@@ -665,11 +684,13 @@ hipError_t launch_adj_row(const SenseRowArgs& a, int maxH, int maxC, hipStream_t
 }
 
 // Registers one column schedule and one row schedule for a length.
-template <class Sd, int WTC, int WTR, int G, bool KS>
+template <class Sd, int WTC, int WTR, int G, bool KS, int KSPL>
 struct Registrar {
   Registrar(const char* name) {
+    static_assert(KSPL >= 1 && KSPL <= KSPL_MAX, "coil split out of range");
     ColVariant cv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTC,
-                  &launch_normal<Sd, WTC, G, KS>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name};
+                  &launch_normal<Sd, WTC, G, KS, KSPL>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name,
+                  KSPL};
     register_col_variant(cv);
     RowVariant rv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTR,
                   &launch_fwd_row<Sd, WTR>, &launch_adj_row<Sd, WTR>, name};
@@ -679,11 +700,11 @@ struct Registrar {
 
 // Registers a wave-local normal-operator schedule (column passes of the
 // forward and adjoint operators use tiles of WTC columns).
-template <class Sd, int WTC, int WTR, int G>
+template <class Sd, int WTC, int WTR, int G, bool PAD>
 struct RegistrarWL {
   RegistrarWL(const char* name) {
     ColVariant cv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, 64 / Sd::T,
-                  &launch_normal_wl<Sd, G>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name};
+                  &launch_normal_wl<Sd, G, PAD>, &launch_fwd_col<Sd, WTC>, &launch_adj_col<Sd, WTC>, name};
     register_col_variant(cv);
     RowVariant rv{Sd::N, Sd::N1, Sd::N2, Sd::N3, Sd::T, WTR,
                   &launch_fwd_row<Sd, WTR>, &launch_adj_row<Sd, WTR>, name};

@@ -1,6 +1,8 @@
 // One transform schedule for one length, selected by the build with
 //   -DMRX_N1=.. -DMRX_N2=.. -DMRX_N3=.. -DMRX_T=.. -DMRX_WTC=.. -DMRX_WTR=.. -DMRX_G=.. -DMRX_KS=0|1 -DMRX_NAME=".."
-// and -DMRX_WL=1 for the wave-local normal operator (k_normal_wl).
+// and -DMRX_WL=1 for the wave-local normal operator (k_normal_wl), =2 for it
+// with the padded LDS layout; -DMRX_KSPL=k splits a column tile's coils over
+// k workgroups in CG steps.
 // It registers its column and row kernels with the schedule registry when
 // the library is loaded.
 #include "sense_impl.h"
@@ -8,9 +10,12 @@
 namespace mrx {
 namespace {
 #if defined(MRX_WL) && MRX_WL
-RegistrarWL<Sched<MRX_N1, MRX_N2, MRX_N3, MRX_T>, MRX_WTC, MRX_WTR, MRX_G> registrar_(MRX_NAME);
+RegistrarWL<Sched<MRX_N1, MRX_N2, MRX_N3, MRX_T>, MRX_WTC, MRX_WTR, MRX_G, (MRX_WL == 2)> registrar_(MRX_NAME);
 #else
-Registrar<Sched<MRX_N1, MRX_N2, MRX_N3, MRX_T>, MRX_WTC, MRX_WTR, MRX_G, (MRX_KS != 0)> registrar_(MRX_NAME);
+#ifndef MRX_KSPL
+#define MRX_KSPL 1
+#endif
+Registrar<Sched<MRX_N1, MRX_N2, MRX_N3, MRX_T>, MRX_WTC, MRX_WTR, MRX_G, (MRX_KS != 0), MRX_KSPL> registrar_(MRX_NAME);
 #endif
 }  // namespace
 }  // namespace mrx

@@ -37,6 +37,7 @@ struct NormalArgs {
   int npq;
   const int* stopped;      // [B] per-slice stop flag (CG breakdown)
   int tiles;               // column tiles per slice (set by the launcher)
+  int64_t qstride;         // CG mode: distance between the partial output planes
 };
 
 struct SenseColArgs {
@@ -71,7 +72,9 @@ struct ColVariant {
   ColFn fwd_col;
   ColFn adj_col;
   const char* name;
+  int kspl = 1;  // CG mode: workgroups per column tile (coil split), partial planes written
 };
+constexpr int KSPL_MAX = 4;
 struct RowVariant {
   int N, N1, N2, N3, T, WT;
   RowFn fwd_row;

@@ -1,8 +1,10 @@
 """The torch.autograd bindings (CGDC, MoDLFunction, MoDLNet) against the FP64
 oracle's reverse passes and against finite differences of the HIP forward.
 
-Tolerances: gradients 1e-3 (CG adjoint, fp32) and the MoDL reverse-pass bound
-2e-2 of test_gpu_net (bf16 ReLU decisions on states that carry fp32 CG error).
+Tolerances: gradients 1e-3 (CG adjoint, fp32); the MoDL module's gradients
+equal one direct library reverse pass, and for T = 1 (no CG error in the
+denoiser's input) meet the denoiser bound 5e-3 against the bf16-operand
+oracle.
 Finite differences are taken on a well-conditioned problem (lambda = 1, so
 cond(A^H A + lambda I) <= 2 and 10 CG steps reach fp32 accuracy), where the
 truncated CG map and its adjoint-CG derivative coincide.
@@ -20,7 +22,7 @@ from tests.gpu_util import dev, host, inputs, rel
 pytestmark = pytest.mark.gpu
 
 GRAD_TOL = 1e-3
-MODL_GRAD_TOL = 2e-2
+NET_GRAD_TOL = 5e-3   # denoiser reverse pass against the bf16-operand oracle
 
 
 def problem(B, H, W, C, seed):
@@ -112,20 +114,52 @@ def test_cgdc_autograd_finite_differences():
     assert abs(fd_l - an_l) < GRAD_TOL * abs(an_l)
 
 
-def test_modlnet_autograd_vs_oracle_and_optimizer_step():
-    B, H, W, C, T, n = 2, 48, 40, 4, 2, 10
-    d, y, aHy = problem(B, H, W, C, 760)
+def _modlnet(B, H, W, C, T, n, seed):
+    d, y, aHy = problem(B, H, W, C, seed)
     plan = ops.Plan(H, W, C, B=B, network=True)
     net = autograd.MoDLNet(plan, T=T, n_cg=n, lam=0.05, learn_lam=True)
     with torch.no_grad():
         net.weights[4].mul_(0.1)
         net.biases[4].mul_(0.1)
-    S, m = dev(d["S"]), dev(d["mask"])
-    x = net(dev(y), S, m)
-    ref = dev(d["x"])
+    return d, y.astype(np.complex64), aHy, plan, net
+
+
+def _mse(x, ref):
     diff = x - ref
-    loss = (torch.view_as_real(diff) ** 2).sum() / diff.numel()
-    loss.backward()
+    return (torch.view_as_real(diff) ** 2).sum() / diff.numel()
+
+
+def test_modlnet_autograd_equals_library_reverse_pass():
+    """Through autograd, T = 2: the gradients are exactly those of one direct
+    mrx_modl_backward call (same kernels, fixed-order reductions)."""
+    B, H, W, C, T, n = 2, 48, 40, 4, 2, 10
+    d, y, aHy, plan, net = _modlnet(B, H, W, C, T, n, 760)
+    S, m, ref, a = dev(d["S"]), dev(d["mask"]), dev(d["x"]), dev(aHy)
+    a.requires_grad_()
+    x = net.forward_from_adjoint(a, S, m)
+    _mse(x, ref).backward()
+    xT, st = plan.modl_forward(dev(aHy), S, m, net.cnn, 0.05, T, n, states=True)
+    assert torch.equal(xT, x.detach())
+    _, g = plan.mse_grad(xT, ref)
+    grads = ops.CNNGrads(net.cnn)
+    gl, ga = plan.modl_backward(g, st, dev(aHy), S, m, net.cnn, 0.05, T, n, grads, need_aHy=True)
+    for l in range(5):
+        assert torch.allclose(net.weights[l].grad, grads.w[l], rtol=1e-6, atol=0), l
+        assert torch.allclose(net.biases[l].grad, grads.b[l], rtol=1e-6, atol=0), l
+    assert torch.allclose(net.lam.grad, gl.sum().reshape(1), rtol=1e-6)
+    assert torch.allclose(a.grad, ga, rtol=1e-6, atol=1e-12)
+
+
+def test_modlnet_autograd_vs_oracle_and_optimizer_step():
+    """T = 1 (the denoiser sees x^0 = A^H y, identical on both sides, so no
+    bf16 ReLU decision differs): gradients against the bf16-operand oracle to
+    the denoiser bound 5e-3; an optimizer step then changes the weights in
+    place and the next forward must use them."""
+    B, H, W, C, T, n = 2, 48, 40, 4, 1, 10
+    d, y, aHy, plan, net = _modlnet(B, H, W, C, T, n, 780)
+    S, m = dev(d["S"]), dev(d["mask"])
+    x = net.forward_from_adjoint(dev(aHy), S, m)
+    _mse(x, dev(d["x"])).backward()
     w = [(wt.detach().cpu().numpy(), bt.detach().cpu().numpy()) for wt, bt in zip(net.weights, net.biases)]
     lam = np.full(B, 0.05, dtype=np.float32)
     xr, sr, zr = omodl.forward(aHy, d["S"], d["mask"], w, lam, T, n, bf16=True)
@@ -135,14 +169,15 @@ def test_modlnet_autograd_vs_oracle_and_optimizer_step():
     for l in range(5):
         ew, eb = rel(host(net.weights[l].grad), gw_ref[l][0]), rel(host(net.biases[l].grad), gw_ref[l][1])
         print(f"modlnet layer {l}: dW {ew:.2e} db {eb:.2e}")
-        assert ew < MODL_GRAD_TOL and eb < MODL_GRAD_TOL
-    assert abs(float(net.lam.grad) - gl_ref.sum()) < MODL_GRAD_TOL * abs(gl_ref.sum())
-    # an optimizer step changes the weights in place; the next forward must use them
+        assert ew < NET_GRAD_TOL and eb < NET_GRAD_TOL
+    assert abs(float(net.lam.grad) - gl_ref.sum()) < NET_GRAD_TOL * abs(gl_ref.sum())
     opt = torch.optim.SGD(net.parameters(), lr=1e-2)
     opt.step()
-    x2 = net(dev(y), S, m)
+    x2 = net.forward_from_adjoint(dev(aHy), S, m)
     w2 = [(wt.detach().cpu().numpy(), bt.detach().cpu().numpy()) for wt, bt in zip(net.weights, net.biases)]
     lam2 = np.full(B, float(net.lam.detach()), dtype=np.float32)
     xr2, _, _ = omodl.forward(aHy, d["S"], d["mask"], w2, lam2, T, n, bf16=True)
     assert rel(host(x2), xr2) < 1e-2
     assert rel(host(x2), host(x)) > 1e-6
+    # the k-space entry point computes A^H y itself
+    assert rel(host(net(dev(y), S, m)), host(x2)) < 1e-3
