@@ -297,9 +297,12 @@ mrx_status mrx_vn_stage_backward(mrx_plan plan, const float* g, const float* x, 
                                  float* g_x, float* g_k, float* g_w, float* g_lam,
                                  int32_t accumulate, void* stream);
 
-/* Choose the fastest registered schedule per distinct length of the plan by
- * timing each on the given stream (synchronises the host).  The choice is
- * kept in the plan and in an in-process cache keyed by (H, W, C). */
+/* Choose the fastest registered column schedule for each (H, W) group of the
+ * plan by timing each on the given stream (synchronises the host): four CG
+ * iterations over the plan when its workspace is set (scratch_a is the
+ * right-hand side, scratch_b the solution; both image-sized and
+ * overwritten), else five normal-operator applications of the group.  The
+ * choice is kept in the plan and in an in-process cache keyed by (H, W, C). */
 mrx_status mrx_plan_autotune(mrx_plan plan, const float* S, const float* mask, float* scratch_a,
                              float* scratch_b, void* stream);
 /* Name of the schedule the plan uses for slice b's column transform. */

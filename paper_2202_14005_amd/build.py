@@ -45,18 +45,22 @@ SCHEDULES = [
     ("n128_4x4x8_t16_w8_g3_rl", 4, 4, 8, 16, 8, 16, 3, 0),
     ("n128_4x4x8_t16_w16", 4, 4, 8, 16, 16, 16, 1, 1),
     ("n160_4x4x10_t8_w16_g2_rl", 4, 4, 10, 8, 16, 16, 2, 0),
+    ("n192_4x4x12_t16_w8_g2_rl", 4, 4, 12, 16, 8, 16, 2, 0),
     ("n192_4x4x12_t16_w16_g2_rl", 4, 4, 12, 16, 16, 16, 2, 0),
     ("n192_4x4x12_t16_w8_g3_rl", 4, 4, 12, 16, 8, 16, 3, 0),
     ("n192_4x4x12_t16_w16", 4, 4, 12, 16, 16, 16, 1, 1),
+    ("n256_4x4x16_t16_w8_g2_rl", 4, 4, 16, 16, 8, 16, 2, 0),
     ("n256_4x4x16_t16_w16_g2_rl", 4, 4, 16, 16, 16, 16, 2, 0),
     ("n256_4x4x16_t16_w8_g3_rl", 4, 4, 16, 16, 8, 16, 3, 0),
     ("n256_4x4x16_t16_w16", 4, 4, 16, 16, 16, 16, 1, 1),
+    ("n320_4x4x20_t16_w8_g2_rl", 4, 4, 20, 16, 8, 16, 2, 0),
     ("n320_4x4x20_t16_w16_g2_rl", 4, 4, 20, 16, 16, 16, 2, 0),
     ("n320_4x4x20_t16_w16_g3_rl", 4, 4, 20, 16, 16, 16, 3, 0),
     ("n320_4x4x20_t16_w8_g3_rl", 4, 4, 20, 16, 8, 16, 3, 0),
     ("n320_4x4x20_t16_w8_g4_rl", 4, 4, 20, 16, 8, 16, 4, 0),
     ("n320_8x40_t8_w16_g2_rl", 8, 40, 1, 8, 16, 16, 2, 0),
     ("n320_4x4x20_t16_w16", 4, 4, 20, 16, 16, 16, 1, 1),
+    ("n384_4x4x24_t16_w8_g2_rl", 4, 4, 24, 16, 8, 16, 2, 0),
     ("n384_4x4x24_t16_w16_g2_rl", 4, 4, 24, 16, 16, 16, 2, 0),
     ("n384_4x4x24_t16_w8_g3_rl", 4, 4, 24, 16, 8, 16, 3, 0),
     ("n384_4x4x24_t16_w16", 4, 4, 24, 16, 16, 16, 1, 1),
@@ -80,6 +84,7 @@ SCHEDULES = [
     ("n384_4x4x24_t16_wlp_g4", 4, 4, 24, 16, 16, 16, 4, 1, 2),
     ("n192_4x4x12_t16_w16_k3", 4, 4, 12, 16, 16, 16, 1, 1, 0, 3),
     ("n256_4x4x16_t16_w16_k3", 4, 4, 16, 16, 16, 16, 1, 1, 0, 3),
+    ("n320_4x4x20_t16_w8_g1_rl", 4, 4, 20, 16, 8, 16, 1, 0),
     ("n320_4x4x20_t16_w16_k2", 4, 4, 20, 16, 16, 16, 1, 1, 0, 2),
     ("n320_4x4x20_t16_w16_k3", 4, 4, 20, 16, 16, 16, 1, 1, 0, 3),
     ("n320_4x4x20_t16_w16_k4", 4, 4, 20, 16, 16, 16, 1, 1, 0, 4),

@@ -79,6 +79,59 @@ __device__ __forceinline__ void load_tile64(uint4* tile, const uint16_t* in, int
 
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return (h & 0x8000u) == 0 && h != 0; }
 
+// Epilogue of the 64-channel-output layers: each wave holds 4 rows x 32
+// columns x 64 channels (acc[m][nb], 32 x 32 blocks).  Forward: + bias
+// (from LDS), ReLU; input gradient: zero where the ReLU input was not
+// positive (the mask source is read for all blocks of a row before use).
+// Output: bf16 NHWC.
+__device__ __forceinline__ void epilogue64(const f32x16 (&acc)[2][4], const float* sbias, const ConvArgs& a,
+                                           const SliceDesc& d, int ty0, int tx0, int wv, int lane) {
+  const int H = d.H, W = d.W;
+  const int hsel = lane >> 5;
+  uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
+  const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
+  const int gx = tx0 + (lane & 31);
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int gy = ty0 + wv * 4 + nb;
+    const bool ok = gy < H && gx < W;
+    const int64_t po = ok ? ((int64_t)gy * W + gx) * CNN_F : 0;
+    uint2 mref[2][4];
+    if (a.mode == CONV_DGRAD) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          mref[m][g] = ok ? *(const uint2*)(rref + po + m * 32 + 8 * g + hsel * 4) : make_uint2(0, 0);
+    }
+    if (!ok) continue;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int co0 = m * 32 + 8 * g + hsel * 4;
+        float hv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v = acc[m][nb][4 * g + j];
+          if (a.mode == CONV_FWD) {
+            v += sbias[co0 + j];
+            v = v > 0.f ? v : 0.f;
+          } else {
+            const uint32_t word = (j < 2) ? mref[m][g].x : mref[m][g].y;
+            const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
+            if (!bf_pos(r)) v = 0.f;
+          }
+          hv[j] = v;
+        }
+        uint2 pk;
+        pk.x = pack_bf16x2(hv[0], hv[1]);
+        pk.y = pack_bf16x2(hv[2], hv[3]);
+        *(uint2*)(out + po + co0) = pk;
+      }
+  }
+}
+
 // ------------------------------------------------------------- 64 -> 64
 // Each wave computes 4 rows x 32 columns x 64 output channels (8
 // accumulator blocks of 32 x 32).  K runs over 9 taps x 4 chunks of 16 input
@@ -150,70 +203,50 @@ __global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
     tap_step(tap + 1, wb, wa);
   }
   tap_step(8, wa, wb);
-  uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
-  const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
-  const int gx = tx0 + (lane & 31);
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int gy = ty0 + wv * 4 + nb;
-    const bool ok = gy < H && gx < W;
-    const int64_t po = ok ? ((int64_t)gy * W + gx) * CNN_F : 0;
-    uint2 mref[2][4];
-    if (a.mode == CONV_DGRAD) {
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-          mref[m][g] = ok ? *(const uint2*)(rref + po + m * 32 + 8 * g + hsel * 4) : make_uint2(0, 0);
-    }
-    if (!ok) continue;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int co0 = m * 32 + 8 * g + hsel * 4;
-        float hv[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          float v = acc[m][nb][4 * g + j];
-          if (a.mode == CONV_FWD) {
-            v += sbias[co0 + j];
-            v = v > 0.f ? v : 0.f;
-          } else {
-            const uint32_t word = (j < 2) ? mref[m][g].x : mref[m][g].y;
-            const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
-            if (!bf_pos(r)) v = 0.f;
-          }
-          hv[j] = v;
-        }
-        uint2 pk;
-        pk.x = pack_bf16x2(hv[0], hv[1]);
-        pk.y = pack_bf16x2(hv[2], hv[3]);
-        *(uint2*)(out + po + co0) = pk;
-      }
-  }
+  epilogue64(acc, sbias, a, d, ty0, tx0, wv, lane);
 }
 
 // ---------------------------------------------------------------- 2 -> 64
 // Input: complex image (fp32 pairs), rounded to bf16.  K = 9 taps x 2 channels
 // = 18, padded to 32 (two 16-deep MFMA steps).
-__global__ void __launch_bounds__(256) k_conv_first(ConvArgs a) {
+__global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
   __shared__ uint32_t tile[TILE_PX];
+  __shared__ float sbias[CNN_F];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
   const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
   if (tx0 >= W || ty0 >= H) return;
   const float2* in = a.in_c + d.xoff;
-  for (int px = threadIdx.x; px < TILE_PX; px += 256) {
-    const int ly = px / (CONV_TW + 2), lx = px % (CONV_TW + 2);
-    const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
-    float2 v = make_float2(0.f, 0.f);
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = in[(int64_t)gy * W + gx];
-    tile[px] = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint16_t* wp = a.wpk + lane * 8;
+  uint4 wf[2][2];  // all four weight fragments, fetched before the tile
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    wf[k][0] = ldg16(wp + (k * 2 + 0) * 512);
+    wf[k][1] = ldg16(wp + (k * 2 + 1) * 512);
+  }
+  if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
+  {
+    constexpr int PT = (TILE_PX + 255) / 256;
+    float2 v[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int px = threadIdx.x + 256 * j;
+      v[j] = make_float2(0.f, 0.f);
+      if (px < TILE_PX) {
+        const int ly = px / (CONV_TW + 2), lx = px - ly * (CONV_TW + 2);
+        const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) v[j] = in[(int64_t)gy * W + gx];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int px = threadIdx.x + 256 * j;
+      if (px < TILE_PX) tile[px] = (uint32_t)f2bf(v[j].x) | ((uint32_t)f2bf(v[j].y) << 16);
+    }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   f32x16 acc[2][4];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
@@ -221,11 +254,10 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvArgs a) {
     for (int n = 0; n < 4; ++n)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[m][n][v] = 0.f;
-  const uint16_t* wp = a.wpk + lane * 8;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const bf16x8 w0 = as_bf16x8(ldg16(wp + (s * 2 + 0) * 512));
-    const bf16x8 w1 = as_bf16x8(ldg16(wp + (s * 2 + 1) * 512));
+    const bf16x8 w0 = as_bf16x8(wf[s][0]);
+    const bf16x8 w1 = as_bf16x8(wf[s][1]);
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
       uint4 raw;
@@ -245,67 +277,41 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvArgs a) {
       acc[1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bv, acc[1][nb], 0, 0, 0);
     }
   }
-  uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
-  const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int gy = ty0 + wv * 4 + nb, gx = tx0 + (lane & 31);
-    if (gy >= H || gx >= W) continue;
-    const int64_t po = ((int64_t)gy * W + gx) * CNN_F;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int co0 = m * 32 + 8 * g + (lane >> 5) * 4;
-        float hv[4];
-        uint2 mref = make_uint2(0, 0);
-        if (a.mode == CONV_DGRAD) mref = *(const uint2*)(rref + po + co0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          float v = acc[m][nb][4 * g + j];
-          if (a.mode == CONV_FWD) {
-            v += a.bias[co0 + j];
-            v = v > 0.f ? v : 0.f;
-          } else {
-            const uint32_t word = (j < 2) ? mref.x : mref.y;
-            const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
-            if (!bf_pos(r)) v = 0.f;
-          }
-          hv[j] = v;
-        }
-        uint2 pk;
-        pk.x = pack_bf16x2(hv[0], hv[1]);
-        pk.y = pack_bf16x2(hv[2], hv[3]);
-        *(uint2*)(out + po + co0) = pk;
-      }
-  }
+  epilogue64(acc, sbias, a, d, ty0, tx0, wv, lane);
 }
 
 // ---------------------------------------------------------------- 64 -> 2
 // v_mfma_f32_16x16x32_bf16 with the two output channels padded to 16 rows;
 // each wave covers 4 rows x 32 columns = 8 blocks of 16 pixels.
 // Output: out_c = resid + (acc + bias)  (fwd: z = x + N(x); dgrad: g_x).
-__global__ void __launch_bounds__(256) k_conv_last(ConvArgs a) {
+__global__ void __launch_bounds__(256, 2) k_conv_last(ConvArgs a) {
   __shared__ uint4 tile[TILE_PX * 8];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
   const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
   if (tx0 >= W || ty0 >= H) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint16_t* wp = a.wpk + lane * 8;
+  uint4 wf[9][2];  // all 18 weight fragments, fetched before the tile
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    wf[k][0] = ldg16(wp + (k * 2 + 0) * 512);
+    wf[k][1] = ldg16(wp + (k * 2 + 1) * 512);
+  }
   load_tile64(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   f32x4 acc[8];
 #pragma unroll
   for (int n = 0; n < 8; ++n)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[n][v] = 0.f;
-  const uint16_t* wp = a.wpk + lane * 8;
+#pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc) {
-      const bf16x8 w = as_bf16x8(ldg16(wp + (tap * 2 + cc) * 512));
+      const bf16x8 w = as_bf16x8(wf[tap][cc]);
       const int ch = cc * 4 + (lane >> 4);
 #pragma unroll
       for (int n = 0; n < 8; ++n) {
@@ -320,13 +326,18 @@ __global__ void __launch_bounds__(256) k_conv_last(ConvArgs a) {
   float2* out = a.out_c + d.xoff;
   const float2* res = a.resid ? a.resid + d.xoff : nullptr;
   bool bad = false;
+  float2 rv[8];
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    const int gy = ty0 + wv * 4 + (n >> 1), gx = tx0 + (n & 1) * 16 + lane;
+    rv[n] = (res && gy < H && gx < W) ? res[(int64_t)gy * W + gx] : make_float2(0.f, 0.f);
+  }
 #pragma unroll
   for (int n = 0; n < 8; ++n) {
     const int gy = ty0 + wv * 4 + (n >> 1), gx = tx0 + (n & 1) * 16 + lane;
     if (gy >= H || gx >= W) continue;
     const int64_t o = (int64_t)gy * W + gx;
-    float2 r = res ? res[o] : make_float2(0.f, 0.f);
-    float2 v = make_float2(r.x + acc[n][0] + b0, r.y + acc[n][1] + b1);
+    float2 v = make_float2(rv[n].x + acc[n][0] + b0, rv[n].y + acc[n][1] + b1);
     bad |= !isfinite(v.x) || !isfinite(v.y);
     out[o] = v;
   }

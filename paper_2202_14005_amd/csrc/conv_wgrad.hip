@@ -26,31 +26,71 @@ constexpr int RT = WG_ROWS;             // rows per tile
 constexpr int TPX = RT * 32;            // pixels per tile
 
 // gT[ch][p] = g[tile pixel p][ch] for 64-channel bf16 NHWC g (zero outside).
+// All of a thread's loads are issued before its LDS writes.
 __device__ __forceinline__ void fill_gT(uint16_t* gT, const uint16_t* g, int H, int W, int row0, int col0) {
-  for (int q = threadIdx.x; q < TPX * 8; q += 256) {
+  constexpr int PER = (TPX * 8 + 255) / 256;
+  uint4 v[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int q = threadIdx.x + 256 * j;
     const int p = q % TPX, ch = q / TPX;
     const int gy = row0 + p / 32, gx = col0 + p % 32;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (gy < H && gx < W) v = *(const uint4*)(g + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
-    const uint16_t* h = (const uint16_t*)&v;
+    v[j] = make_uint4(0, 0, 0, 0);
+    if (q < TPX * 8 && gy < H && gx < W) v[j] = *(const uint4*)(g + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int q = threadIdx.x + 256 * j;
+    if (q >= TPX * 8) break;
+    const int p = q % TPX, ch = q / TPX;
+    const uint16_t* h = (const uint16_t*)&v[j];
 #pragma unroll
     for (int e = 0; e < 8; ++e) gT[(ch * 8 + e) * TPX + p] = h[e];
   }
 }
 
-// aT[dx][ch][r * 32 + c] = a[row0 - 1 + r][col0 + c + dx - 1][ch], r < RT + 2.
+// aT[dx][ch][r * 32 + c] = a[row0 - 1 + r][col0 + c + dx - 1][ch], r < RT + 2:
+// every pixel of the (RT + 2) x 34 halo tile is loaded once and written to
+// the (up to three) column-shifted copies that use it.
 __device__ __forceinline__ void fill_aT3(uint16_t* aT, const uint16_t* a, int H, int W, int row0, int col0) {
   constexpr int HP = (RT + 2) * 32;
-  for (int q = threadIdx.x; q < 3 * HP * 8; q += 256) {
-    const int p = q % HP, rest = q / HP;
-    const int ch = rest % 8, dx = rest / 8;
-    const int gy = row0 - 1 + p / 32, gx = col0 + p % 32 + dx - 1;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = *(const uint4*)(a + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
-    const uint16_t* h = (const uint16_t*)&v;
+  constexpr int NQ = (RT + 2) * 34 * 8;
+  constexpr int PER = (NQ + 255) / 256;
+  uint4 v[PER];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) aT[(dx * 64 + ch * 8 + e) * HP + p] = h[e];
+  for (int j = 0; j < PER; ++j) {
+    const int q = threadIdx.x + 256 * j;
+    const int hp = q % ((RT + 2) * 34), ch = q / ((RT + 2) * 34);
+    const int r = hp / 34, hx = hp % 34;
+    const int gy = row0 - 1 + r, gx = col0 - 1 + hx;
+    v[j] = make_uint4(0, 0, 0, 0);
+    if (q < NQ && gy >= 0 && gy < H && gx >= 0 && gx < W)
+      v[j] = *(const uint4*)(a + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
   }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int q = threadIdx.x + 256 * j;
+    if (q >= NQ) break;
+    const int hp = q % ((RT + 2) * 34), ch = q / ((RT + 2) * 34);
+    const int r = hp / 34, hx = hp % 34;
+    const uint16_t* h = (const uint16_t*)&v[j];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int c = hx - dx;
+      if (c < 0 || c >= 32) continue;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) aT[(dx * 64 + ch * 8 + e) * HP + r * 32 + c] = h[e];
+    }
+  }
+}
+
+// Sum of the 8 bf16 values of a fragment, in fp32, in index order.
+__device__ __forceinline__ float frag_sum(uint4 v) {
+  const uint16_t* h = (const uint16_t*)&v;
+  float s = 0.f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) s += bf2f_w(h[e]);
+  return s;
 }
 
 // ------------------------------------------------------------ 64 -> 64
@@ -81,12 +121,13 @@ __global__ void __launch_bounds__(256) k_wgrad_mid(WgradArgs a) {
       fill_gT(gT, g, H, W, row0, col0);
       fill_aT3(aT, act, H, W, row0, col0);
       __syncthreads();
-      if (threadIdx.x < 64)
-        for (int p = 0; p < TPX; ++p) bsum += bf2f_w(gT[threadIdx.x * TPX + p]);
 #pragma unroll
       for (int ks = 0; ks < TPX / 16; ++ks) {
         const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
-        const bf16x8 av = as_bf(*(const uint4*)&gT[(mb * 32 + (lane & 31)) * TPX + r * 32 + c]);
+        const uint4 araw = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * TPX + r * 32 + c];
+        const bf16x8 av = as_bf(araw);
+        // bias gradient of channel mb * 32 + lane % 32: this lane's 8 pixels
+        if (nb == 0) bsum += frag_sum(araw);
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
           const int dy = tap / 3, dx = tap % 3;
@@ -105,7 +146,9 @@ __global__ void __launch_bounds__(256) k_wgrad_mid(WgradArgs a) {
       const int ci = nb * 32 + (lane & 31);
       part[(co * 64 + ci) * 9 + tap] = acc[tap][v];
     }
-  if (threadIdx.x < 64) part[64 * 64 * 9 + threadIdx.x] = bsum;
+  // lanes l and l + 32 hold the two pixel halves of channel mb * 32 + l % 32
+  bsum += __shfl_xor(bsum, 32, 64);
+  if (nb == 0 && lane < 32) part[64 * 64 * 9 + mb * 32 + lane] = bsum;
 }
 
 // ------------------------------------------------------------- 2 -> 64
@@ -145,13 +188,12 @@ __global__ void __launch_bounds__(256) k_wgrad_first(WgradArgs a) {
         xT[(RT + 2) * 34 + p] = f2bf_w(v.y);
       }
       __syncthreads();
-      if (par == 0 && mb == 0) {
-        for (int p = 0; p < TPX; ++p) bsum += bf2f_w(gT[lane * TPX + p]);
-      }
 #pragma unroll
       for (int ks = par; ks < TPX / 16; ks += 2) {
         const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
-        const bf16x8 av = as_bf(*(const uint4*)&gT[(mb * 32 + (lane & 31)) * TPX + r * 32 + c]);
+        const uint4 araw = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * TPX + r * 32 + c];
+        const bf16x8 av = as_bf(araw);
+        bsum += frag_sum(araw);  // bias gradient, this parity's pixels
         uint4 raw;
         uint16_t* h = (uint16_t*)&raw;
 #pragma unroll
@@ -166,8 +208,8 @@ __global__ void __launch_bounds__(256) k_wgrad_first(WgradArgs a) {
     const int co = mb * 32 + 8 * (v >> 2) + (lane >> 5) * 4 + (v & 3);
     if (j < 18) part[(co * 2 + ci) * 9 + tap] = acc[v];
   }
-  if (par == 0 && mb == 0) part[64 * 2 * 9 + lane] = bsum;
-  if (par == 1 && mb == 0) part[64 * 2 * 9 + lane] = 0.f;
+  bsum += __shfl_xor(bsum, 32, 64);
+  if (lane < 32) part[64 * 2 * 9 + mb * 32 + lane] = bsum;
 }
 
 // ------------------------------------------------------------- 64 -> 2
@@ -207,14 +249,12 @@ __global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
         gH[(RT + 2) * 34 + p] = f2bf_w(v.y);
       }
       __syncthreads();
-      if (threadIdx.x == 0) {  // bias gradient from the fp32 output gradient
-        for (int p = 0; p < TPX; ++p) {
-          const int gy = row0 + p / 32, gx = col0 + p % 32;
-          if (gy < H && gx < W) {
-            const float2 v = g5[(int64_t)gy * W + gx];
-            bs0 += v.x;
-            bs1 += v.y;
-          }
+      if (threadIdx.x < TPX) {  // bias gradient from the fp32 output gradient
+        const int gy = row0 + threadIdx.x / 32, gx = col0 + threadIdx.x % 32;
+        if (gy < H && gx < W) {
+          const float2 v = g5[(int64_t)gy * W + gx];
+          bs0 += v.x;
+          bs1 += v.y;
         }
       }
 #pragma unroll
@@ -237,9 +277,18 @@ __global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
     const int ci = nb * 32 + (lane & 31);
     if (ii < 18) part[((ii & 1) * 64 + ci) * 9 + (ii >> 1)] = acc[v];
   }
-  if (threadIdx.x == 0) {
-    part[2 * 64 * 9 + 0] = par == 0 && nb == 0 ? bs0 : 0.f;
-    part[2 * 64 * 9 + 1] = par == 0 && nb == 0 ? bs1 : 0.f;
+  // threads 0..63 (wave 0: par 0) hold per-position sums; fixed butterfly
+  if (wv == 0) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      bs0 += __shfl_xor(bs0, off, 64);
+      bs1 += __shfl_xor(bs1, off, 64);
+    }
+  }
+  // slot (wg, par 0) carries the bias sums, slot (wg, par 1) zeros
+  if (wv == 0 && lane == 0) {
+    part[2 * 64 * 9 + 0] = bs0;
+    part[2 * 64 * 9 + 1] = bs1;
   }
   if (wv == 2 && lane == 0) {
     part[2 * 64 * 9 + 0] = 0.f;
@@ -247,15 +296,31 @@ __global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
   }
 }
 
-// out[i] (+)= sum_s partial[s][i] over nslots slots, fixed order.
-__global__ void k_wgrad_reduce(const float* partial, int nslots, int nout, float* w_out, float* b_out,
-                               int nweights, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nout) return;
+// out[i] (+)= sum_s partial[s][i] over nslots slots in a fixed order: a
+// block takes 64 outputs; its 4 waves sum the slots s = w, w + 4, ... in
+// increasing order, then the 4 wave sums are added in wave order.
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* partial, int nslots, int nout, float* w_out,
+                                                      float* b_out, int nweights, int accumulate) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int k = 0; k < nslots; ++k) s += partial[(int64_t)k * nout + i];
-  float* dst = i < nweights ? w_out + i : b_out + (i - nweights);
-  *dst = accumulate ? *dst + s : s;
+  if (i < nout) {
+    int k = wv;
+    for (; k + 12 < nslots; k += 16) {
+      const float a0 = partial[(int64_t)k * nout + i], a1 = partial[(int64_t)(k + 4) * nout + i];
+      const float a2 = partial[(int64_t)(k + 8) * nout + i], a3 = partial[(int64_t)(k + 12) * nout + i];
+      s += a0; s += a1; s += a2; s += a3;
+    }
+    for (; k < nslots; k += 4) s += partial[(int64_t)k * nout + i];
+  }
+  red[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && i < nout) {
+    const float t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    float* dst = i < nweights ? w_out + i : b_out + (i - nweights);
+    *dst = accumulate ? *dst + t : t;
+  }
 }
 
 hipError_t wgrad_launch(int kind, const WgradArgs& a, int bands, hipStream_t s) {
@@ -268,7 +333,7 @@ hipError_t wgrad_launch(int kind, const WgradArgs& a, int bands, hipStream_t s) 
 
 hipError_t wgrad_reduce(const float* partial, int nslots, int nout, float* w_out, float* b_out, int nweights,
                         int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 255) / 256), dim3(256), 0, s, partial, nslots, nout, w_out,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 63) / 64), dim3(256), 0, s, partial, nslots, nout, w_out,
                      b_out, nweights, accumulate);
   return hipGetLastError();
 }

@@ -373,6 +373,21 @@ class CNN:
     def numpy(self):
         return [(w.detach().cpu().numpy(), b.detach().cpu().numpy()) for w, b in zip(self.w, self.b)]
 
+    def save(self, path):
+        """Weights and biases as plain float32 arrays w0, b0, ..., w4, b4."""
+        import numpy as np
+        arrs = {}
+        for l, (w, b) in enumerate(self.numpy()):
+            arrs[f"w{l}"], arrs[f"b{l}"] = w, b
+        np.savez(path, **arrs)
+
+    @classmethod
+    def load(cls, path, device=None):
+        import numpy as np
+        with np.load(path, allow_pickle=False) as f:
+            wb = [(f[f"w{l}"].astype(np.float32), f[f"b{l}"].astype(np.float32)) for l in range(5)]
+        return cls.from_numpy(wb, device)
+
 
 class CNNGrads:
     """Gradient buffers shaped like a CNN's parameters."""

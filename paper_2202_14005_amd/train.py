@@ -44,16 +44,23 @@ class PhantomSource:
         self.S = [torch.from_numpy(coil_maps(coil_seed + k, C, H, W)).to(dev) for k in range(n_coilsets)]
         self.M = [torch.from_numpy(pe_mask(coil_seed + 500 + k, H, R, n_center, kind)).to(dev)
                   for k in range(n_coilsets)]
+        self._cache = {}  # seed -> (phantom, noise) on the device, drawn once
+
+    def _draw(self, s):
+        from synthetic import kspace_noise, phantom
+        if s not in self._cache:
+            dev = self.plan.device
+            self._cache[s] = (torch.from_numpy(phantom(s, self.H, self.W)).to(dev),
+                              torch.from_numpy(kspace_noise(s + 31, self.C, self.H, self.W, self.sigma)).to(dev))
+        return self._cache[s]
 
     def batch(self, seeds):
-        from synthetic import kspace_noise, phantom
-        dev = self.plan.device
         B = len(seeds)
-        x = torch.from_numpy(np.stack([phantom(s, self.H, self.W) for s in seeds])).to(dev)
+        xs, ns = zip(*(self._draw(s) for s in seeds))
+        x = torch.stack(xs).contiguous()
         S = torch.stack([self.S[s % len(self.S)] for s in seeds]).contiguous()
         m = torch.stack([self.M[s % len(self.M)] for s in seeds]).contiguous()
-        n = torch.from_numpy(np.stack([kspace_noise(s + 31, self.C, self.H, self.W, self.sigma)
-                                       for s in seeds])).to(dev)
+        n = torch.stack(ns).contiguous()
         assert B == self.plan.B
         y = self.plan.sense_fwd(x, S, m, noise=n)
         return y, S, m, x
@@ -138,8 +145,11 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-4)
     ap.add_argument("--n-eval", type=int, default=64)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--save", default=None, help="write the trained weights (.npz, arrays only)")
     a = ap.parse_args()
     cnn, hist = train(H=a.size, W=a.size, C=a.coils, B=a.batch, T=a.unrolls, lr=a.lr, steps=a.steps)
+    if a.save:
+        cnn.save(a.save)
     ev = evaluate(cnn, H=a.size, W=a.size, C=a.coils, B=a.batch, T=a.unrolls, n_eval=a.n_eval)
     out = {"train": hist, "eval": ev}
     if a.out:
