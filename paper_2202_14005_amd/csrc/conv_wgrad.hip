@@ -24,6 +24,11 @@ __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf1
 
 constexpr int RT = WG_ROWS;             // rows per tile
 constexpr int TPX = RT * 32;            // pixels per tile
+// Row strides of the channel-major LDS tiles, padded by 16 bytes so that the
+// 16-byte fragment reads of 16 consecutive channels start in distinct bank
+// groups (an unpadded 128- or 256-byte stride puts them all in one).
+constexpr int GROW = TPX + 8;
+constexpr int AROW = (RT + 2) * 32 + 8;
 
 // gT[ch][p] = g[tile pixel p][ch] for 64-channel bf16 NHWC g (zero outside).
 // All of a thread's loads are issued before its LDS writes.
@@ -45,42 +50,7 @@ __device__ __forceinline__ void fill_gT(uint16_t* gT, const uint16_t* g, int H, 
     const int p = q % TPX, ch = q / TPX;
     const uint16_t* h = (const uint16_t*)&v[j];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) gT[(ch * 8 + e) * TPX + p] = h[e];
-  }
-}
-
-// aT[dx][ch][r * 32 + c] = a[row0 - 1 + r][col0 + c + dx - 1][ch], r < RT + 2:
-// every pixel of the (RT + 2) x 34 halo tile is loaded once and written to
-// the (up to three) column-shifted copies that use it.
-__device__ __forceinline__ void fill_aT3(uint16_t* aT, const uint16_t* a, int H, int W, int row0, int col0) {
-  constexpr int HP = (RT + 2) * 32;
-  constexpr int NQ = (RT + 2) * 34 * 8;
-  constexpr int PER = (NQ + 255) / 256;
-  uint4 v[PER];
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int q = threadIdx.x + 256 * j;
-    const int hp = q % ((RT + 2) * 34), ch = q / ((RT + 2) * 34);
-    const int r = hp / 34, hx = hp % 34;
-    const int gy = row0 - 1 + r, gx = col0 - 1 + hx;
-    v[j] = make_uint4(0, 0, 0, 0);
-    if (q < NQ && gy >= 0 && gy < H && gx >= 0 && gx < W)
-      v[j] = *(const uint4*)(a + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
-  }
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int q = threadIdx.x + 256 * j;
-    if (q >= NQ) break;
-    const int hp = q % ((RT + 2) * 34), ch = q / ((RT + 2) * 34);
-    const int r = hp / 34, hx = hp % 34;
-    const uint16_t* h = (const uint16_t*)&v[j];
-#pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      const int c = hx - dx;
-      if (c < 0 || c >= 32) continue;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) aT[(dx * 64 + ch * 8 + e) * HP + r * 32 + c] = h[e];
-    }
+    for (int e = 0; e < 8; ++e) gT[(ch * 8 + e) * GROW + p] = h[e];
   }
 }
 
@@ -94,68 +64,156 @@ __device__ __forceinline__ float frag_sum(uint4 v) {
 }
 
 // ------------------------------------------------------------ 64 -> 64
-__global__ void __launch_bounds__(256) k_wgrad_mid(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t gT[64 * TPX];
-  __shared__ __attribute__((aligned(16))) uint16_t aT[3 * 64 * (RT + 2) * 32];
-  const int slot = blockIdx.y * gridDim.x + blockIdx.x;
-  float* part = a.partial + (int64_t)slot * a.nout;
-  const int b = a.slices[blockIdx.y];
-  const SliceDesc d = a.desc[b];
-  const int H = d.H, W = d.W;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int mb = wv >> 1, nb = wv & 1;
-  f32x16 acc[9];
+// A fixed grid of WGM_WGS workgroups walks the batch's tiles (RT rows x 32
+// columns, slices in order) in contiguous ranges; each keeps its sums in
+// registers over all its tiles and writes one slot at the end.  8 waves:
+// (co block, ci block, tap half).  The next tile's global data are loaded
+// into registers while the current tile's MFMAs run, then transposed into
+// the channel-major LDS tiles.
+struct TileCursor {
+  int si;         // slice index (into a.slices)
+  int64_t base;   // global index of the slice's first tile
+  int ntx, ntiles, H, W;
+  int64_t xoff;
+};
+
+__device__ __forceinline__ void cursor_load(TileCursor& c, const WgradArgs& a, int si, int64_t base) {
+  c.si = si;
+  c.base = base;
+  if (si < a.nslices) {
+    const SliceDesc d = a.desc[a.slices[si]];
+    c.H = d.H; c.W = d.W; c.xoff = d.xoff;
+    c.ntx = (d.W + 31) / 32;
+    c.ntiles = ((d.H + RT - 1) / RT) * c.ntx;
+  } else {
+    c.H = c.W = c.ntx = c.ntiles = 0; c.xoff = 0;
+  }
+}
+// advance the cursor to the slice holding tile t (t never decreases)
+__device__ __forceinline__ void cursor_seek(TileCursor& c, const WgradArgs& a, int64_t t) {
+  while (c.si < a.nslices && t >= c.base + c.ntiles) cursor_load(c, a, c.si + 1, c.base + c.ntiles);
+}
+
+constexpr int WGM_PER_A = ((RT + 2) * 34 * 8 + 511) / 512;
+
+__device__ __forceinline__ void wgm_load(uint4& gv, uint4 (&av)[WGM_PER_A], const WgradArgs& a, const TileCursor& c,
+                                         int64_t t) {
+  const int loc = (int)(t - c.base);
+  const int row0 = (loc / c.ntx) * RT, col0 = (loc % c.ntx) * 32;
+  const uint16_t* g = a.g + c.xoff * CNN_F;
+  const uint16_t* act = a.act + c.xoff * CNN_F;
+  {
+    const int q = threadIdx.x, p = q % TPX, ch = q / TPX;
+    const int gy = row0 + p / 32, gx = col0 + p % 32;
+    gv = make_uint4(0, 0, 0, 0);
+    if (gy < c.H && gx < c.W) gv = *(const uint4*)(g + ((int64_t)gy * c.W + gx) * CNN_F + ch * 8);
+  }
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
+  for (int j = 0; j < WGM_PER_A; ++j) {
+    const int q = threadIdx.x + 512 * j;
+    const int hp = q % ((RT + 2) * 34), ch = q / ((RT + 2) * 34);
+    const int gy = row0 - 1 + hp / 34, gx = col0 - 1 + hp % 34;
+    av[j] = make_uint4(0, 0, 0, 0);
+    if (q < (RT + 2) * 34 * 8 && gy >= 0 && gy < c.H && gx >= 0 && gx < c.W)
+      av[j] = *(const uint4*)(act + ((int64_t)gy * c.W + gx) * CNN_F + ch * 8);
+  }
+}
+
+__device__ __forceinline__ void wgm_store(uint16_t* gT, uint16_t* aT, const uint4& gv, const uint4 (&av)[WGM_PER_A]) {
+  {
+    const int q = threadIdx.x, p = q % TPX, ch = q / TPX;
+    const uint16_t* h = (const uint16_t*)&gv;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) gT[(ch * 8 + e) * GROW + p] = h[e];
+  }
+#pragma unroll
+  for (int j = 0; j < WGM_PER_A; ++j) {
+    const int q = threadIdx.x + 512 * j;
+    if (q >= (RT + 2) * 34 * 8) break;
+    const int hp = q % ((RT + 2) * 34), ch = q / ((RT + 2) * 34);
+    const int r = hp / 34, hx = hp % 34;
+    const uint16_t* h = (const uint16_t*)&av[j];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int c = hx - dx;
+      if (c < 0 || c >= 32) continue;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) aT[(dx * 64 + ch * 8 + e) * AROW + r * 32 + c] = h[e];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512) k_wgrad_mid(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t gT[64 * GROW];
+  __shared__ __attribute__((aligned(16))) uint16_t aT[3 * 64 * AROW];
+  float* part = a.partial + (int64_t)blockIdx.x * a.nout;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int mb = wv & 1, nb = (wv >> 1) & 1, th = wv >> 2;
+  const int tap0 = th ? 5 : 0;
+  // this workgroup's tiles [t0, t1) of the batch
+  int64_t total = 0;
+  for (int si = 0; si < a.nslices; ++si) {
+    const SliceDesc d = a.desc[a.slices[si]];
+    total += (int64_t)((d.H + RT - 1) / RT) * ((d.W + 31) / 32);
+  }
+  const int64_t t0 = total * blockIdx.x / gridDim.x, t1 = total * (blockIdx.x + 1) / gridDim.x;
+  f32x16 acc[5];
+#pragma unroll
+  for (int t = 0; t < 5; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
   float bsum = 0.f;
-  const uint16_t* g = a.g + d.xoff * CNN_F;
-  const uint16_t* act = a.act + d.xoff * CNN_F;
-  const int band0 = blockIdx.x * WG_BAND;
-  for (int rt = 0; rt < WG_BAND / RT; ++rt) {
-    const int row0 = band0 + rt * RT;
-    if (row0 >= H) break;
-    for (int col0 = 0; col0 < W; col0 += 32) {
-      __syncthreads();
-      fill_gT(gT, g, H, W, row0, col0);
-      fill_aT3(aT, act, H, W, row0, col0);
-      __syncthreads();
+  TileCursor cur, nxt;
+  cursor_load(cur, a, 0, 0);
+  cursor_seek(cur, a, t0);
+  nxt = cur;
+  uint4 gv, av[WGM_PER_A];
+  if (t0 < t1) wgm_load(gv, av, a, cur, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    wgm_store(gT, aT, gv, av);
+    __syncthreads();
+    if (t + 1 < t1) {
+      cursor_seek(nxt, a, t + 1);
+      wgm_load(gv, av, a, nxt, t + 1);
+    }
 #pragma unroll
-      for (int ks = 0; ks < TPX / 16; ++ks) {
-        const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
-        const uint4 araw = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * TPX + r * 32 + c];
-        const bf16x8 av = as_bf(araw);
-        // bias gradient of channel mb * 32 + lane % 32: this lane's 8 pixels
-        if (nb == 0) bsum += frag_sum(araw);
+    for (int ks = 0; ks < TPX / 16; ++ks) {
+      const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
+      const uint4 araw = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * GROW + r * 32 + c];
+      const bf16x8 avf = as_bf(araw);
+      if (nb == 0 && th == 0) bsum += frag_sum(araw);  // bias gradient, channel mb * 32 + lane % 32
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-          const int dy = tap / 3, dx = tap % 3;
-          const bf16x8 bv = as_bf(*(const uint4*)&aT[(dx * 64 + nb * 32 + (lane & 31)) * ((RT + 2) * 32) +
-                                                     (r + dy) * 32 + c]);
-          acc[tap] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[tap], 0, 0, 0);
-        }
+      for (int k = 0; k < 5; ++k) {
+        const int tap = tap0 + k;
+        if (tap > 8) break;
+        const int dy = tap / 3, dx = tap % 3;
+        const bf16x8 bv = as_bf(*(const uint4*)&aT[(dx * 64 + nb * 32 + (lane & 31)) * AROW + (r + dy) * 32 + c]);
+        acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(avf, bv, acc[k], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap)
+  for (int k = 0; k < 5; ++k) {
+    const int tap = tap0 + k;
+    if (tap > 8) break;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int co = mb * 32 + 8 * (v >> 2) + (lane >> 5) * 4 + (v & 3);
       const int ci = nb * 32 + (lane & 31);
-      part[(co * 64 + ci) * 9 + tap] = acc[tap][v];
+      part[(co * 64 + ci) * 9 + tap] = acc[k][v];
     }
+  }
   // lanes l and l + 32 hold the two pixel halves of channel mb * 32 + l % 32
   bsum += __shfl_xor(bsum, 32, 64);
-  if (nb == 0 && lane < 32) part[64 * 64 * 9 + mb * 32 + lane] = bsum;
+  if (nb == 0 && th == 0 && lane < 32) part[64 * 64 * 9 + mb * 32 + lane] = bsum;
 }
 
 // ------------------------------------------------------------- 2 -> 64
 // dW1[co][ci][tap] with N = (tap, ci) = 18 padded to 32; waves split
 // (co block) x (k-step parity); each parity has its own partial slot.
 __global__ void __launch_bounds__(256) k_wgrad_first(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t gT[64 * TPX];
+  __shared__ __attribute__((aligned(16))) uint16_t gT[64 * GROW];
   __shared__ uint16_t xT[2 * (RT + 2) * 34];
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -191,7 +249,7 @@ __global__ void __launch_bounds__(256) k_wgrad_first(WgradArgs a) {
 #pragma unroll
       for (int ks = par; ks < TPX / 16; ks += 2) {
         const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
-        const uint4 araw = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * TPX + r * 32 + c];
+        const uint4 araw = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * GROW + r * 32 + c];
         const bf16x8 av = as_bf(araw);
         bsum += frag_sum(araw);  // bias gradient, this parity's pixels
         uint4 raw;
@@ -216,7 +274,7 @@ __global__ void __launch_bounds__(256) k_wgrad_first(WgradArgs a) {
 // dW5[co][ci][tap] = sum_q g5[q - d][co] a4[q][ci]; M = (tap, co) = 18 padded
 // to 32, N = ci (two blocks); waves split (ci block) x (k-step parity).
 __global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t aT[64 * TPX];
+  __shared__ __attribute__((aligned(16))) uint16_t aT[64 * GROW];
   __shared__ uint16_t gH[2 * (RT + 2) * 34];
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -266,7 +324,7 @@ __global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
 #pragma unroll
         for (int e = 0; e < 8; ++e)
           h[e] = (i < 18) ? gH[co * (RT + 2) * 34 + (r + 2 - dy) * 34 + c + e + 2 - dx] : (uint16_t)0;
-        const bf16x8 bv = as_bf(*(const uint4*)&aT[(nb * 32 + (lane & 31)) * TPX + r * 32 + c]);
+        const bf16x8 bv = as_bf(*(const uint4*)&aT[(nb * 32 + (lane & 31)) * GROW + r * 32 + c]);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(raw), bv, acc, 0, 0, 0);
       }
     }
@@ -326,7 +384,7 @@ __global__ void __launch_bounds__(256) k_wgrad_reduce(const float* partial, int 
 hipError_t wgrad_launch(int kind, const WgradArgs& a, int bands, hipStream_t s) {
   dim3 grid(bands, a.nslices);
   if (kind == 0) hipLaunchKernelGGL(k_wgrad_first, grid, dim3(256), 0, s, a);
-  else if (kind == 1) hipLaunchKernelGGL(k_wgrad_mid, grid, dim3(256), 0, s, a);
+  else if (kind == 1) hipLaunchKernelGGL(k_wgrad_mid, dim3(WGM_WGS), dim3(512), 0, s, a);
   else hipLaunchKernelGGL(k_wgrad_last, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }

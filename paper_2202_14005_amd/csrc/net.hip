@@ -1,6 +1,7 @@
 // Network entry points: the MoDL residual denoiser (forward, reverse mode),
 // the MoDL unrolled network (eq. update_modl) with its reverse pass by adjoint
 // CG and recomputed unroll activations, the MSE loss gradient and Adam.
+#include <algorithm>
 #include "../../include/mrx.h"
 #include "api_internal.h"
 #include "conv.h"
@@ -39,7 +40,7 @@ size_t net_workspace_bytes(mrx_plan_s* p) {
   p->ws_vimg = take(ni * 8);
   p->ws_pk = take((size_t)2 * (PK_FIRST + 3 * PK_MID + PK_LAST) * 2);
   const size_t slots = (size_t)bands_of(p) * p->B;
-  p->ws_wpart = take(std::max<size_t>(slots * NOUT_MID, 2 * slots * NOUT_FIRST) * 4);
+  p->ws_wpart = take(std::max<size_t>({(size_t)WGM_WGS * NOUT_MID, 2 * slots * NOUT_FIRST, 2 * slots * NOUT_LAST}) * 4);
   p->ws_loss = take((size_t)p->B * p->nrr * 4);
   return w;
 }
@@ -135,7 +136,7 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     w.nout = kind == 1 ? NOUT_MID : kind == 0 ? NOUT_FIRST : NOUT_LAST;
     hipError_t r = wgrad_launch(kind, w, bands, s);
     if (r != hipSuccess) return r;
-    const int nslots = kind == 1 ? slots : 2 * slots;
+    const int nslots = kind == 1 ? WGM_WGS : 2 * slots;
     const int nw = w.nout - (kind == 2 ? 2 : 64);
     return wgrad_reduce(part, nslots, w.nout, g->w[layer], g->b[layer], nw, accumulate, s);
   };

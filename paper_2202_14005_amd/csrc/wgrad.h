@@ -5,7 +5,8 @@
 namespace mrx {
 
 constexpr int WG_ROWS = 2;   // rows per LDS tile
-constexpr int WG_BAND = 4;   // rows per workgroup (a band of tiles)
+constexpr int WG_BAND = 4;   // rows per workgroup (a band of tiles), first and last layers
+constexpr int WGM_WGS = 256; // workgroups (and partial slots) of the middle-layer kernel
 
 struct WgradArgs {
   const SliceDesc* desc;

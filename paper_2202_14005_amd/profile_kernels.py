@@ -1,0 +1,60 @@
+"""Run the hot kernels alone, for profilers (rocprofv3 --pmc / --kernel-trace).
+
+    python -m paper_2202_14005_amd.profile_kernels [--reps 3] [--what normal,conv,copy]
+
+Workload: the MoDL inference batch (8 slices of 320 x 320, 15 coils, R = 4
+variable-density mask with 24 centre lines).  ``normal`` applies the normal
+operator (A^H A + lambda I) once per repetition (one k_normal launch per
+repetition: the kernel whose HBM bytes the benchmark's roofline reports),
+``conv`` one 64 -> 64 denoiser layer (k_conv_mid), ``copy`` a device-to-device
+copy of 256 MiB (256 MiB read, 256 MiB written) whose counter readings
+calibrate FETCH_SIZE and WRITE_SIZE.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+import numpy as np
+import torch
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_2202_14005_amd import ops  # noqa: E402
+from synthetic import batch_inputs  # noqa: E402
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--what", default="normal,conv,copy")
+    a = ap.parse_args()
+    what = set(a.what.split(","))
+    dev = torch.device("cuda", 0)
+    B, H, W, C = 8, 320, 320, 15
+    d = batch_inputs([2000 + i for i in range(B)], H, W, C, 4, 24, "vd")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    plan = ops.Plan(H, W, C, B=B, device=dev, network=True)
+    x, S, m = t(d["x"]), t(d["S"]), t(d["mask"])
+    lam = plan.lam(0.05)
+    q = torch.empty_like(x)
+    cnn = ops.CNN.init(7, dev)
+    a_in = torch.randn(B * H * W * 64, device=dev).to(torch.bfloat16)
+    a_out = torch.empty_like(a_in)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(a.reps):
+        if "normal" in what:
+            plan.sense_normal(x, S, m, lam, out=q)
+        if "conv" in what:
+            plan.cnn_layer_forward(2, a_in, cnn, out=a_out)
+        if "copy" in what:
+            dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"done: {sorted(what)} x {a.reps}; schedule {plan.schedule(0)}", flush=True)
+
+
+if __name__ == "__main__":
+    main()
