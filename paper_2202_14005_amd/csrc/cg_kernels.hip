@@ -88,18 +88,39 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_update(CgElemArgs a) {
   const float alpha = stop ? 0.f : rho / pq;
   float rr = 0.f;
   const int64_t base = (int64_t)blockIdx.x * CG_EPB;
-  for (int k = threadIdx.x; k < CG_EPB; k += CG_THREADS) {
-    const int64_t i = base + k;
+  // all of a thread's loads are issued before the updates (one memory
+  // latency per block instead of one per element)
+  constexpr int PER = CG_EPB / CG_THREADS;
+  float2 rv[PER], pv[PER], qv[PER], xv[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = base + threadIdx.x + j * CG_THREADS;
+    const int64_t o = d.xoff + (i < n ? i : 0);
+    rv[j] = a.r[o];
+    if (!stop) {
+      pv[j] = a.p[o];
+      qv[j] = a.q[o];
+      xv[j] = a.x[o];
+    }
+  }
+  if (!stop && d.nq > 1) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int64_t i = base + threadIdx.x + j * CG_THREADS;
+      const int64_t o = d.xoff + (i < n ? i : 0);
+      for (int k = 1; k < d.nq; ++k) qv[j] = cadd(qv[j], a.q[k * a.qstride + o]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = base + threadIdx.x + j * CG_THREADS;
     if (i >= n) break;
     const int64_t o = d.xoff + i;
-    float2 r = a.r[o];
+    float2 r = rv[j];
     if (!stop) {
-      const float2 p = a.p[o];
-      float2 q = a.q[o];
-      for (int k = 1; k < d.nq; ++k) q = cadd(q, a.q[k * a.qstride + o]);
-      float2 x = a.x[o];
-      x.x += alpha * p.x; x.y += alpha * p.y;
-      r.x -= alpha * q.x; r.y -= alpha * q.y;
+      float2 x = xv[j];
+      x.x += alpha * pv[j].x; x.y += alpha * pv[j].y;
+      r.x -= alpha * qv[j].x; r.y -= alpha * qv[j].y;
       a.x[o] = x;
       a.r[o] = r;
     }
