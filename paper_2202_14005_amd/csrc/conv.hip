@@ -1,7 +1,8 @@
 // MFMA 3x3 convolutions for the MoDL denoiser (bf16 operands, fp32
 // accumulation, NHWC activations).  One workgroup (4 waves) computes a tile
-// of 16 rows x 32 columns of one slice; the input tile with its one-pixel
-// halo is staged in LDS, weights stream from L1/L2 as MFMA fragments.
+// of 16 rows x 32 columns (first and last layer) or 16 x 16 (middle layers)
+// of one slice; the input tile with its one-pixel halo is staged in LDS,
+// weights stream from L1/L2 as MFMA fragments.
 //   first layer:  2 -> 64 channels, v_mfma_f32_32x32x16_bf16, K = 18 -> 32
 //   middle layer: 64 -> 64, v_mfma_f32_32x32x16_bf16, K = 9 x 64
 //   last layer:   64 -> 2 (+ residual), v_mfma_f32_16x16x32_bf16, co padded to 16
@@ -133,25 +134,51 @@ __device__ __forceinline__ void epilogue64(const f32x16 (&acc)[2][4], const floa
 }
 
 // ------------------------------------------------------------- 64 -> 64
-// Each wave computes 4 rows x 32 columns x 64 output channels (8
-// accumulator blocks of 32 x 32).  K runs over 9 taps x 4 chunks of 16 input
-// channels; the weight fragments of the next tap are fetched from L2 while
-// the current tap runs (two register sets used in turn, so the loop carries
-// no register copies).  Bias (forward) or the ReLU mask
-// source (input gradient) is fetched ahead of the epilogue.  Sized for two
-// workgroups per CU (2 x 78 KB of LDS).
-__global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
-  __shared__ uint4 tile[TILE_PX * 8];
+// 16 x 16-pixel tiles (41.5 KB of LDS) so that three workgroups fit on a CU;
+// each wave computes 4 rows x 16 columns x 64 output channels as 2 pixel
+// blocks of 2 rows x 16 columns (4 accumulators of 32 x 32), few enough
+// registers for three waves per SIMD: while one workgroup fills its tile the
+// other two run MFMAs.  K runs over 9 taps x 4 chunks of 16 input channels;
+// the weight fragments of the next tap are fetched from L2 while the
+// current tap runs, in two register sets used in turn (a rolled loop with
+// one set made the compiler wait for the loads at the back edge).
+constexpr int TW16 = 16;
+constexpr int TILE16_PX = (CONV_TH + 2) * (TW16 + 2);
+constexpr int TILE16_CHUNKS = TILE16_PX * 8;
+constexpr int TILE16_PER_THREAD = (TILE16_CHUNKS + 255) / 256;
+
+__device__ __forceinline__ void load_tile64_16(uint4* tile, const uint16_t* in, int H, int W, int ty0, int tx0) {
+  uint4 v[TILE16_PER_THREAD];
+  int slot[TILE16_PER_THREAD];
+#pragma unroll
+  for (int j = 0; j < TILE16_PER_THREAD; ++j) {
+    const int q = threadIdx.x + 256 * j;
+    v[j] = make_uint4(0, 0, 0, 0);
+    slot[j] = -1;
+    if (q < TILE16_CHUNKS) {
+      const int px = q >> 3, ch = q & 7;
+      const int ly = px / (TW16 + 2), lx = px - ly * (TW16 + 2);
+      const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+      slot[j] = px * 8 + (ch ^ swz(px));
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v[j] = ldg16(in + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TILE16_PER_THREAD; ++j)
+    if (slot[j] >= 0) tile[slot[j]] = v[j];
+}
+
+__global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
+  __shared__ uint4 tile[TILE16_PX * 8];
   __shared__ float sbias[CNN_F];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
-  const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
+  const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
   if (tx0 >= W || ty0 >= H) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int hsel = lane >> 5, n = lane & 31;
   const uint16_t* wp = a.wpk + lane * 8;
-  // weight fragments of one tap (4 chunks x 2 output blocks); two sets in
-  // turn: the next tap's fragments load while the current tap runs
   uint4 wa[4][2], wb[4][2];
 #pragma unroll
   for (int kc = 0; kc < 4; ++kc) {
@@ -159,17 +186,17 @@ __global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
     wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
   }
   if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
-  load_tile64(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
+  load_tile64_16(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
   __syncthreads();
-  f32x16 acc[2][4];
+  f32x16 acc[2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[m][n][v] = 0.f;
-  const int pbase = wv * 4 * (CONV_TW + 2) + (lane & 31);
-  const int hsel = lane >> 5;
+      for (int v = 0; v < 16; ++v) acc[m][nb][v] = 0.f;
+  // pixel n of block nb: row wv * 4 + nb * 2 + n / 16, column n % 16
+  const int pbase = (wv * 4 + (n >> 4)) * (TW16 + 2) + (n & 15);
   auto tap_step = [&](int tap, uint4 (&cur)[4][2], uint4 (&nxt)[4][2]) {
     const int dy = tap / 3, dx = tap - 3 * dy;
     if (tap + 1 < 9) {
@@ -179,20 +206,19 @@ __global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
         nxt[kc][1] = ldg16(wp + (((tap + 1) * 4 + kc) * 2 + 1) * 512);
       }
     }
-    // keep the scheduler from sinking these loads next to their use
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
       const bf16x8 w0 = as_bf16x8(cur[kc][0]), w1 = as_bf16x8(cur[kc][1]);
       const int ch = kc * 2 + hsel;
-      bf16x8 bv[4];
+      bf16x8 bv[2];
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int px = pbase + (dy + nb) * (CONV_TW + 2) + dx;
+      for (int nb = 0; nb < 2; ++nb) {
+        const int px = pbase + (dy + nb * 2) * (TW16 + 2) + dx;
         bv[nb] = as_bf16x8(tile[px * 8 + (ch ^ swz(px))]);
       }
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
+      for (int nb = 0; nb < 2; ++nb) {
         acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, bv[nb], acc[0][nb], 0, 0, 0);
         acc[1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bv[nb], acc[1][nb], 0, 0, 0);
       }
@@ -203,7 +229,49 @@ __global__ void __launch_bounds__(256, 2) k_conv_mid(ConvArgs a) {
     tap_step(tap + 1, wb, wa);
   }
   tap_step(8, wa, wb);
-  epilogue64(acc, sbias, a, d, ty0, tx0, wv, lane);
+  // epilogue (as epilogue64, for this pixel mapping)
+  uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
+  const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
+  const int gx = tx0 + (n & 15);
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int gy = ty0 + wv * 4 + nb * 2 + (n >> 4);
+    const bool ok = gy < H && gx < W;
+    const int64_t po = ok ? ((int64_t)gy * W + gx) * CNN_F : 0;
+    uint2 mref[2][4];
+    if (a.mode == CONV_DGRAD) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          mref[m][g] = ok ? *(const uint2*)(rref + po + m * 32 + 8 * g + hsel * 4) : make_uint2(0, 0);
+    }
+    if (!ok) continue;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int co0 = m * 32 + 8 * g + hsel * 4;
+        float hv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v = acc[m][nb][4 * g + j];
+          if (a.mode == CONV_FWD) {
+            v += sbias[co0 + j];
+            v = v > 0.f ? v : 0.f;
+          } else {
+            const uint32_t word = (j < 2) ? mref[m][g].x : mref[m][g].y;
+            const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
+            if (!bf_pos(r)) v = 0.f;
+          }
+          hv[j] = v;
+        }
+        uint2 pk;
+        pk.x = pack_bf16x2(hv[0], hv[1]);
+        pk.y = pack_bf16x2(hv[2], hv[3]);
+        *(uint2*)(out + po + co0) = pk;
+      }
+  }
 }
 
 // ---------------------------------------------------------------- 2 -> 64
@@ -395,7 +463,10 @@ __global__ void k_pack_last(const float* Wm, uint16_t* out, int transpose) {
 hipError_t conv_launch(int kind, const ConvArgs& a, hipStream_t s) {
   dim3 grid(a.tiles_x, a.tiles_y, a.nslices);
   if (kind == 0) hipLaunchKernelGGL(k_conv_first, grid, dim3(256), 0, s, a);
-  else if (kind == 1) hipLaunchKernelGGL(k_conv_mid, grid, dim3(256), 0, s, a);
+  else if (kind == 1) {
+    dim3 g16((a.tiles_x * CONV_TW + TW16 - 1) / TW16, a.tiles_y, a.nslices);
+    hipLaunchKernelGGL(k_conv_mid16, g16, dim3(256), 0, s, a);
+  }
   else hipLaunchKernelGGL(k_conv_last, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -6,7 +6,7 @@ Workload: the MoDL inference batch (8 slices of 320 x 320, 15 coils, R = 4
 variable-density mask with 24 centre lines).  ``normal`` applies the normal
 operator (A^H A + lambda I) once per repetition (one k_normal launch per
 repetition: the kernel whose HBM bytes the benchmark's roofline reports),
-``conv`` one 64 -> 64 denoiser layer (k_conv_mid), ``copy`` a device-to-device
+``conv`` one 64 -> 64 denoiser layer (k_conv_mid16), ``copy`` a device-to-device
 copy of 256 MiB (256 MiB read, 256 MiB written) whose counter readings
 calibrate FETCH_SIZE and WRITE_SIZE.
 """
