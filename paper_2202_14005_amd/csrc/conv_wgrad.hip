@@ -5,6 +5,8 @@
 // so a fragment of 8 consecutive pixels of one channel is one 16-byte read.
 // Every workgroup writes its partial sums to its own slot; a second kernel
 // adds the slots in a fixed order (deterministic, no float atomics).
+#include <type_traits>
+
 #include "conv.h"
 #include "wgrad.h"
 
@@ -94,51 +96,78 @@ __device__ __forceinline__ void cursor_seek(TileCursor& c, const WgradArgs& a, i
   while (c.si < a.nslices && t >= c.base + c.ntiles) cursor_load(c, a, c.si + 1, c.base + c.ntiles);
 }
 
-constexpr int WGM_PER_A = ((RT + 2) * 34 * 8 + 511) / 512;
+// Loads and channel-major stores of one tile, four consecutive pixels of one
+// 8-channel chunk per work item, so that each channel's four values leave as
+// one 8-byte LDS write (instead of four 2-byte ones).
+//   g items:  (chunk, pixel quad) of the RT x 32 tile: 8 x TPX / 4 = 128
+//   a items:  (dx, chunk, row, column quad) of the shifted copies:
+//             3 x 8 x (RT + 2) x 8 = 768; copy dx, columns 4k..4k+3 read the
+//             halo pixels 4k + dx .. 4k + dx + 3
+constexpr int WGM_GITEMS = 8 * TPX / 4;
+constexpr int WGM_AITEMS = 3 * 8 * (RT + 2) * 8;
+constexpr int WGM_PER_A = (WGM_AITEMS + 511) / 512;
 
-__device__ __forceinline__ void wgm_load(uint4& gv, uint4 (&av)[WGM_PER_A], const WgradArgs& a, const TileCursor& c,
-                                         int64_t t) {
+__device__ __forceinline__ void wgm_load(uint4 (&gv)[4], uint4 (&av)[WGM_PER_A][4], const WgradArgs& a,
+                                         const TileCursor& c, int64_t t) {
   const int loc = (int)(t - c.base);
   const int row0 = (loc / c.ntx) * RT, col0 = (loc % c.ntx) * 32;
   const uint16_t* g = a.g + c.xoff * CNN_F;
   const uint16_t* act = a.act + c.xoff * CNN_F;
   {
-    const int q = threadIdx.x, p = q % TPX, ch = q / TPX;
-    const int gy = row0 + p / 32, gx = col0 + p % 32;
-    gv = make_uint4(0, 0, 0, 0);
-    if (gy < c.H && gx < c.W) gv = *(const uint4*)(g + ((int64_t)gy * c.W + gx) * CNN_F + ch * 8);
+    const int q = threadIdx.x;
+    const int quad = q % (TPX / 4), ch = q / (TPX / 4);
+    const int p0 = quad * 4, gy = row0 + p0 / 32, gx0 = col0 + p0 % 32;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      gv[u] = make_uint4(0, 0, 0, 0);
+      if (q < WGM_GITEMS && gy < c.H && gx0 + u < c.W)
+        gv[u] = *(const uint4*)(g + ((int64_t)gy * c.W + gx0 + u) * CNN_F + ch * 8);
+    }
   }
 #pragma unroll
   for (int j = 0; j < WGM_PER_A; ++j) {
     const int q = threadIdx.x + 512 * j;
-    const int hp = q % ((RT + 2) * 34), ch = q / ((RT + 2) * 34);
-    const int gy = row0 - 1 + hp / 34, gx = col0 - 1 + hp % 34;
-    av[j] = make_uint4(0, 0, 0, 0);
-    if (q < (RT + 2) * 34 * 8 && gy >= 0 && gy < c.H && gx >= 0 && gx < c.W)
-      av[j] = *(const uint4*)(act + ((int64_t)gy * c.W + gx) * CNN_F + ch * 8);
+    const int k = q % 8, r = (q / 8) % (RT + 2), ch = (q / (8 * (RT + 2))) % 8, dx = q / (8 * (RT + 2) * 8);
+    const int gy = row0 - 1 + r, gx0 = col0 + 4 * k + dx - 1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[j][u] = make_uint4(0, 0, 0, 0);
+      if (q < WGM_AITEMS && gy >= 0 && gy < c.H && gx0 + u >= 0 && gx0 + u < c.W)
+        av[j][u] = *(const uint4*)(act + ((int64_t)gy * c.W + gx0 + u) * CNN_F + ch * 8);
+    }
   }
 }
 
-__device__ __forceinline__ void wgm_store(uint16_t* gT, uint16_t* aT, const uint4& gv, const uint4 (&av)[WGM_PER_A]) {
+// element e (0..7) of the 8 bf16 channels of a 16-byte chunk
+__device__ __forceinline__ uint32_t chunk_elem(const uint4& v, int e) {
+  const uint32_t w = (e < 2) ? v.x : (e < 4) ? v.y : (e < 6) ? v.z : v.w;
+  return (e & 1) ? (w >> 16) : (w & 0xffffu);
+}
+
+__device__ __forceinline__ void wgm_store(uint16_t* gT, uint16_t* aT, const uint4 (&gv)[4],
+                                          const uint4 (&av)[WGM_PER_A][4]) {
   {
-    const int q = threadIdx.x, p = q % TPX, ch = q / TPX;
-    const uint16_t* h = (const uint16_t*)&gv;
+    const int q = threadIdx.x;
+    if (q < WGM_GITEMS) {
+      const int quad = q % (TPX / 4), ch = q / (TPX / 4);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) gT[(ch * 8 + e) * GROW + p] = h[e];
+      for (int e = 0; e < 8; ++e) {
+        const uint2 w = make_uint2(chunk_elem(gv[0], e) | (chunk_elem(gv[1], e) << 16),
+                                   chunk_elem(gv[2], e) | (chunk_elem(gv[3], e) << 16));
+        *(uint2*)&gT[(ch * 8 + e) * GROW + quad * 4] = w;
+      }
+    }
   }
 #pragma unroll
   for (int j = 0; j < WGM_PER_A; ++j) {
     const int q = threadIdx.x + 512 * j;
-    if (q >= (RT + 2) * 34 * 8) break;
-    const int hp = q % ((RT + 2) * 34), ch = q / ((RT + 2) * 34);
-    const int r = hp / 34, hx = hp % 34;
-    const uint16_t* h = (const uint16_t*)&av[j];
+    if (q >= WGM_AITEMS) break;
+    const int k = q % 8, r = (q / 8) % (RT + 2), ch = (q / (8 * (RT + 2))) % 8, dx = q / (8 * (RT + 2) * 8);
 #pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      const int c = hx - dx;
-      if (c < 0 || c >= 32) continue;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) aT[(dx * 64 + ch * 8 + e) * AROW + r * 32 + c] = h[e];
+    for (int e = 0; e < 8; ++e) {
+      const uint2 w = make_uint2(chunk_elem(av[j][0], e) | (chunk_elem(av[j][1], e) << 16),
+                                 chunk_elem(av[j][2], e) | (chunk_elem(av[j][3], e) << 16));
+      *(uint2*)&aT[(dx * 64 + ch * 8 + e) * AROW + r * 32 + 4 * k] = w;
     }
   }
 }
@@ -147,7 +176,8 @@ __global__ void __launch_bounds__(512) k_wgrad_mid(WgradArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t gT[64 * GROW];
   __shared__ __attribute__((aligned(16))) uint16_t aT[3 * 64 * AROW];
   float* part = a.partial + (int64_t)blockIdx.x * a.nout;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int mb = wv & 1, nb = (wv >> 1) & 1, th = wv >> 2;
   const int tap0 = th ? 5 : 0;
   // this workgroup's tiles [t0, t1) of the batch
@@ -167,7 +197,7 @@ __global__ void __launch_bounds__(512) k_wgrad_mid(WgradArgs a) {
   cursor_load(cur, a, 0, 0);
   cursor_seek(cur, a, t0);
   nxt = cur;
-  uint4 gv, av[WGM_PER_A];
+  uint4 gv[4], av[WGM_PER_A][4];
   if (t0 < t1) wgm_load(gv, av, a, cur, t0);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
@@ -177,21 +207,33 @@ __global__ void __launch_bounds__(512) k_wgrad_mid(WgradArgs a) {
       cursor_seek(nxt, a, t + 1);
       wgm_load(gv, av, a, nxt, t + 1);
     }
+    // one fragment set: the reads of k-step ks + 1 are issued right behind the
+    // MFMAs of k-step ks (which read their operands at issue)
+    auto compute = [&](auto th_c) {
+      constexpr int TAP0 = decltype(th_c)::value ? 5 : 0, NTAP = decltype(th_c)::value ? 4 : 5;
+      uint4 af, bfr[NTAP];
+      auto ld = [&](int ks) {
+        const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
+        af = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * GROW + r * 32 + c];
 #pragma unroll
-    for (int ks = 0; ks < TPX / 16; ++ks) {
-      const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
-      const uint4 araw = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * GROW + r * 32 + c];
-      const bf16x8 avf = as_bf(araw);
-      if (nb == 0 && th == 0) bsum += frag_sum(araw);  // bias gradient, channel mb * 32 + lane % 32
+        for (int k = 0; k < NTAP; ++k) {
+          const int tap = TAP0 + k, dy = tap / 3, dx = tap % 3;
+          bfr[k] = *(const uint4*)&aT[(dx * 64 + nb * 32 + (lane & 31)) * AROW + (r + dy) * 32 + c];
+        }
+      };
+      ld(0);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int tap = tap0 + k;
-        if (tap > 8) break;
-        const int dy = tap / 3, dx = tap % 3;
-        const bf16x8 bv = as_bf(*(const uint4*)&aT[(dx * 64 + nb * 32 + (lane & 31)) * AROW + (r + dy) * 32 + c]);
-        acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(avf, bv, acc[k], 0, 0, 0);
+      for (int ks = 0; ks < TPX / 16; ++ks) {
+        if (nb == 0 && TAP0 == 0) bsum += frag_sum(af);  // bias gradient, channel mb * 32 + lane % 32
+#pragma unroll
+        for (int k = 0; k < NTAP; ++k)
+          acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(af), as_bf(bfr[k]), acc[k], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks + 1 < TPX / 16) ld(ks + 1);
       }
-    }
+    };
+    if (th == 0) compute(std::integral_constant<int, 0>{});
+    else compute(std::integral_constant<int, 1>{});
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -307,12 +349,14 @@ __global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
         gH[(RT + 2) * 34 + p] = f2bf_w(v.y);
       }
       __syncthreads();
-      if (threadIdx.x < TPX) {  // bias gradient from the fp32 output gradient
-        const int gy = row0 + threadIdx.x / 32, gx = col0 + threadIdx.x % 32;
-        if (gy < H && gx < W) {
-          const float2 v = g5[(int64_t)gy * W + gx];
-          bs0 += v.x;
-          bs1 += v.y;
+      if (wv == 0) {  // bias gradient from the fp32 output gradient: wave 0, per lane
+        for (int p = lane; p < TPX; p += 64) {
+          const int gy = row0 + p / 32, gx = col0 + p % 32;
+          if (gy < H && gx < W) {
+            const float2 v = g5[(int64_t)gy * W + gx];
+            bs0 += v.x;
+            bs1 += v.y;
+          }
         }
       }
 #pragma unroll
@@ -335,7 +379,7 @@ __global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
     const int ci = nb * 32 + (lane & 31);
     if (ii < 18) part[((ii & 1) * 64 + ci) * 9 + (ii >> 1)] = acc[v];
   }
-  // threads 0..63 (wave 0: par 0) hold per-position sums; fixed butterfly
+  // wave 0 (par 0) holds per-lane sums; fixed butterfly
   if (wv == 0) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {

@@ -4,7 +4,7 @@
 
 namespace mrx {
 
-constexpr int WG_ROWS = 2;   // rows per LDS tile
+constexpr int WG_ROWS = 4;   // rows per LDS tile
 constexpr int WG_BAND = 4;   // rows per workgroup (a band of tiles), first and last layers
 constexpr int WGM_WGS = 256; // workgroups (and partial slots) of the middle-layer kernel
 

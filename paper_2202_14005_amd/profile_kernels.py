@@ -6,7 +6,9 @@ Workload: the MoDL inference batch (8 slices of 320 x 320, 15 coils, R = 4
 variable-density mask with 24 centre lines).  ``normal`` applies the normal
 operator (A^H A + lambda I) once per repetition (one k_normal launch per
 repetition: the kernel whose HBM bytes the benchmark's roofline reports),
-``conv`` one 64 -> 64 denoiser layer (k_conv_mid16), ``copy`` a device-to-device
+``conv`` one 64 -> 64 denoiser layer (k_conv_mid16), ``backward`` one reverse
+pass of the denoiser (input gradient and weight gradients, all five
+layers), ``copy`` a device-to-device
 copy of 256 MiB (256 MiB read, 256 MiB written) whose counter readings
 calibrate FETCH_SIZE and WRITE_SIZE.
 """
@@ -42,6 +44,10 @@ def main():
     cnn = ops.CNN.init(7, dev)
     a_in = torch.randn(B * H * W * 64, device=dev).to(torch.bfloat16)
     a_out = torch.empty_like(a_in)
+    grads = ops.CNNGrads(cnn)
+    gz = torch.randn_like(x)
+    if "backward" in what:
+        plan.cnn_forward(x, cnn)  # activations for the reverse pass
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -50,6 +56,8 @@ def main():
             plan.sense_normal(x, S, m, lam, out=q)
         if "conv" in what:
             plan.cnn_layer_forward(2, a_in, cnn, out=a_out)
+        if "backward" in what:
+            plan.cnn_backward(x, gz, cnn, grads)
         if "copy" in what:
             dst.copy_(src)
     torch.cuda.synchronize()
