@@ -302,7 +302,9 @@ mrx_status mrx_vn_stage_backward(mrx_plan plan, const float* g, const float* x, 
  * iterations over the plan when its workspace is set (scratch_a is the
  * right-hand side, scratch_b the solution; both image-sized and
  * overwritten), else five normal-operator applications of the group.  The
- * choice is kept in the plan and in an in-process cache keyed by (H, W, C). */
+ * choice is kept in the plan and in an in-process cache keyed by (H, W, C,
+ * number of slices of the group); plans created later with a matching group
+ * start from the cached choice. */
 mrx_status mrx_plan_autotune(mrx_plan plan, const float* S, const float* mask, float* scratch_a,
                              float* scratch_b, void* stream);
 /* Name of the schedule the plan uses for slice b's column transform. */
@@ -311,12 +313,12 @@ const char* mrx_plan_schedule(mrx_plan plan, int32_t b);
 const char* mrx_schedule_name(int32_t n, int32_t idx);
 /* Force the column schedule `name` for the slices of the plan with H = n. */
 mrx_status mrx_plan_set_schedule(mrx_plan plan, int32_t n, const char* name);
-/* Write the in-process tuning cache to a text file, one "H W C name" entry a
- * line.  MRX_EINVAL if the file cannot be written. */
+/* Write the in-process tuning cache to a text file, one "H W C slices name"
+ * entry a line.  MRX_EINVAL if the file cannot be written. */
 mrx_status mrx_tune_cache_save(const char* path);
 /* Merge the entries of a file written by mrx_tune_cache_save into the
  * in-process cache; plans created afterwards use them.  Every entry is checked
- * first (known schedule for its H, positive W and C): on a bad entry nothing is
+ * first (known schedule for its H, positive W, C and slices): on a bad entry nothing is
  * merged and MRX_EINVAL names the line.  n_loaded (nullable) receives the
  * number of entries. */
 mrx_status mrx_tune_cache_load(const char* path, int32_t* n_loaded);

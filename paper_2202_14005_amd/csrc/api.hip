@@ -43,7 +43,7 @@ void register_row_variant(const RowVariant& v) { row_registry().push_back(v); }
 // Default schedule per length: the first registered one unless the tune
 // cache says otherwise.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, std::string> g_tune_cache;  // (H, W, C) -> column schedule name
+std::map<std::tuple<int, int, int, int>, std::string> g_tune_cache;  // (H, W, C, slices) -> column schedule name
 
 const ColVariant* find_col(int N, const char* name) {
   for (auto& v : col_registry())
@@ -133,7 +133,7 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& g : p->groups) {
-      auto it = g_tune_cache.find({g.H, g.W, g.maxC});
+      auto it = g_tune_cache.find({g.H, g.W, g.maxC, (int)g.slices.size()});
       g.col = find_col(g.H, it != g_tune_cache.end() ? it->second.c_str() : nullptr);
       if (!g.col) g.col = find_col(g.H, nullptr);
       g.rowW = find_row(g.W);

@@ -64,7 +64,7 @@ const RowVariant* find_row(int N);
 std::vector<const ColVariant*> col_variants(int N);
 
 extern std::mutex g_tune_mu;
-extern std::map<std::tuple<int, int, int>, std::string> g_tune_cache;
+extern std::map<std::tuple<int, int, int, int>, std::string> g_tune_cache;
 
 size_t extra_workspace_bytes(mrx_plan_s* p);
 // Set desc[b].nq from the column schedule of each slice's group; with

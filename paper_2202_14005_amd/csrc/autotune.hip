@@ -1,6 +1,7 @@
 // Project-written schedule autotuner: times every registered column schedule
-// of each distinct (H, W, C) group of a plan and keeps the fastest, in the
-// plan and in an in-process cache.
+// of each (H, W) group of a plan and keeps the fastest, in the plan and in an
+// in-process cache keyed by the group's size, coil count and slice count (the
+// slice count sets the grid, so the best schedule depends on it).
 #include <cstdio>
 #include <map>
 #include <mutex>
@@ -59,7 +60,7 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
     }
     g.col = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[{g.H, g.W, g.maxC}] = best->name;
+    g_tune_cache[{g.H, g.W, g.maxC, (int)g.slices.size()}] = best->name;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -69,7 +70,7 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
   return refresh_desc(p, true);
 }
 
-// Text form of the cache, one entry a line: "H W C schedule_name".
+// Text form of the cache, one entry a line: "H W C slices schedule_name".
 extern "C" mrx_status mrx_tune_cache_save(const char* path) {
   if (!path) return fail(MRX_EINVAL, "tune_cache_save: null path");
   FILE* f = fopen(path, "w");
@@ -77,8 +78,8 @@ extern "C" mrx_status mrx_tune_cache_save(const char* path) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : g_tune_cache)
-      fprintf(f, "%d %d %d %s\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-              kv.second.c_str());
+      fprintf(f, "%d %d %d %d %s\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+              std::get<3>(kv.first), kv.second.c_str());
   }
   return fclose(f) == 0 ? MRX_OK : fail(MRX_EINVAL, std::string("tune_cache_save: write failed: ") + path);
 }
@@ -87,20 +88,21 @@ extern "C" mrx_status mrx_tune_cache_load(const char* path, int32_t* n_loaded) {
   if (!path) return fail(MRX_EINVAL, "tune_cache_load: null path");
   FILE* f = fopen(path, "r");
   if (!f) return fail(MRX_EINVAL, std::string("tune_cache_load: cannot open ") + path);
-  std::map<std::tuple<int, int, int>, std::string> entries;
+  std::map<std::tuple<int, int, int, int>, std::string> entries;
   char line[512];
   int lineno = 0;
   while (fgets(line, sizeof line, f)) {
     ++lineno;
-    int H = 0, W = 0, C = 0;
+    int H = 0, W = 0, C = 0, n = 0;
     char name[256] = {0};
     if (line[0] == '\n' || line[0] == '#') continue;
-    if (sscanf(line, "%d %d %d %255s", &H, &W, &C, name) != 4 || !find_col(H, name) || W <= 0 || C <= 0) {
+    if (sscanf(line, "%d %d %d %d %255s", &H, &W, &C, &n, name) != 5 || !find_col(H, name) || W <= 0 || C <= 0 ||
+        n <= 0) {
       fclose(f);
       return fail(MRX_EINVAL, std::string("tune_cache_load: bad entry at line ") + std::to_string(lineno) +
                                   " of " + path);
     }
-    entries[{H, W, C}] = name;
+    entries[{H, W, C, n}] = name;
   }
   fclose(f);
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -73,8 +73,9 @@ def nrmse(x, ref):
 
 
 def train(H=320, W=320, C=15, B=4, T=5, n_cg=10, lam=0.05, lr=1e-4, steps=500, n_train=2000,
-          train_base=100000, seed=7, last_scale=0.1, log_every=25, device=None, verbose=True):
-    """Train a MoDL denoiser; returns (cnn, history)."""
+          train_base=100000, seed=7, last_scale=0.1, log_every=25, device=None, verbose=True, tune=True):
+    """Train a MoDL denoiser; returns (cnn, history).  With ``tune`` the
+    normal operator's schedule is chosen by the autotuner on the first batch."""
     dev = torch.device(device) if device else torch.device("cuda", torch.cuda.current_device())
     plan = ops.Plan(H, W, C, B=B, device=dev, network=True)
     src = PhantomSource(plan, H, W, C)
@@ -87,6 +88,8 @@ def train(H=320, W=320, C=15, B=4, T=5, n_cg=10, lam=0.05, lr=1e-4, steps=500, n
     for it in range(steps):
         seeds = [train_base + (it * B + k) % n_train for k in range(B)]
         y, S, m, x = src.batch(seeds)
+        if tune and it == 0:
+            plan.autotune(S, m)
         loss = net.train_step(y, S, m, x, grads, opt)
         if it % log_every == 0 or it == steps - 1:
             lv = float(loss.item())

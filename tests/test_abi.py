@@ -83,13 +83,13 @@ def test_tune_cache_file_roundtrip_and_errors(tmp_path):
     from paper_2202_14005_amd._lib import MrxError
     name = ops.schedules(320)[0]
     good = tmp_path / "good.txt"
-    good.write_text(f"# comment\n320 320 15 {name}\n")
+    good.write_text(f"# comment\n320 320 15 8 {name}\n")
     assert ops.tune_cache_load(str(good)) == 1
     out = tmp_path / "saved.txt"
     ops.tune_cache_save(str(out))
-    assert f"320 320 15 {name}" in out.read_text().splitlines()
+    assert f"320 320 15 8 {name}" in out.read_text().splitlines()
     bad = tmp_path / "bad.txt"
-    bad.write_text(f"320 320 15 {name}\n320 320 15 no_such_schedule\n")
+    bad.write_text(f"320 320 15 8 {name}\n320 320 15 8 no_such_schedule\n")
     with pytest.raises(MrxError, match="line 2"):
         ops.tune_cache_load(str(bad))
     with pytest.raises(MrxError):
