@@ -80,57 +80,83 @@ __device__ __forceinline__ void load_tile64(uint4* tile, const uint16_t* in, int
 
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return (h & 0x8000u) == 0 && h != 0; }
 
-// Epilogue of the 64-channel-output layers: each wave holds 4 rows x 32
-// columns x 64 channels (acc[m][nb], 32 x 32 blocks).  Forward: + bias
-// (from LDS), ReLU; input gradient: zero where the ReLU input was not
-// positive (the mask source is read for all blocks of a row before use).
-// Output: bf16 NHWC.
-__device__ __forceinline__ void epilogue64(const f32x16 (&acc)[2][4], const float* sbias, const ConvArgs& a,
-                                           const SliceDesc& d, int ty0, int tx0, int wv, int lane) {
-  const int H = d.H, W = d.W;
-  const int hsel = lane >> 5;
-  uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
-  const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
-  const int gx = tx0 + (lane & 31);
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int gy = ty0 + wv * 4 + nb;
-    const bool ok = gy < H && gx < W;
-    const int64_t po = ok ? ((int64_t)gy * W + gx) * CNN_F : 0;
-    uint2 mref[2][4];
-    if (a.mode == CONV_DGRAD) {
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-          mref[m][g] = ok ? *(const uint2*)(rref + po + m * 32 + 8 * g + hsel * 4) : make_uint2(0, 0);
-    }
-    if (!ok) continue;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int co0 = m * 32 + 8 * g + hsel * 4;
-        float hv[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          float v = acc[m][nb][4 * g + j];
-          if (a.mode == CONV_FWD) {
-            v += sbias[co0 + j];
-            v = v > 0.f ? v : 0.f;
-          } else {
-            const uint32_t word = (j < 2) ? mref[m][g].x : mref[m][g].y;
-            const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
-            if (!bf_pos(r)) v = 0.f;
-          }
-          hv[j] = v;
-        }
-        uint2 pk;
-        pk.x = pack_bf16x2(hv[0], hv[1]);
-        pk.y = pack_bf16x2(hv[2], hv[3]);
-        *(uint2*)(out + po + co0) = pk;
-      }
+// Coalesced epilogue of one 32-pixel x 64-channel block (the two 32 x 32
+// accumulators a0 = channels 0-31, a1 = 32-63 of one wave).  The MFMA result
+// gives each lane 4 channels of one pixel per register group, so direct
+// stores would touch 32 pixels (32 cache lines) per instruction.  Instead the
+// block goes through the wave's own 4 KB of LDS (stg, 32 pixel rows of 16
+// eight-byte slots; slot s of pixel p sits at s ^ ((p >> 1) & 15), so a
+// 32-lane write phase covers the 64 banks once) and is written back as whole
+// pixels: 8 lanes x 16 bytes per pixel, 1 KB of consecutive pixels per
+// store.  Forward: + bias, ReLU (before staging).  Input gradient: zero where
+// relu_ref (read with the same 16-byte pattern) is not positive.
+// pix(i) is the element offset (pixel x 64) of block pixel i, or -1 if it
+// lies outside the image.
+struct WaveFence {
+  __device__ static __forceinline__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+};
+
+template <class PixFn>
+__device__ __forceinline__ void epi_block64(const f32x16& a0, const f32x16& a1, const float* sbias, int mode,
+                                            uint2* stg, int lane, PixFn pix, uint16_t* out,
+                                            const uint16_t* rref) {
+  const int n = lane & 31, hsel = lane >> 5, kx = (n >> 1) & 15;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int co0 = m * 32 + 8 * g + hsel * 4;
+      float hv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v = m ? a1[4 * g + j] : a0[4 * g + j];
+        if (mode == CONV_FWD) {
+          v += sbias[co0 + j];
+          v = v > 0.f ? v : 0.f;
+        }
+        hv[j] = v;
+      }
+      uint2 pk;
+      pk.x = pack_bf16x2(hv[0], hv[1]);
+      pk.y = pack_bf16x2(hv[2], hv[3]);
+      stg[n * 16 + ((co0 >> 2) ^ kx)] = pk;
+    }
+  WaveFence::sync();
+  const int c = lane & 7;
+  uint4 v[4];
+  int64_t off[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int pi = r * 8 + (lane >> 3), k = (pi >> 1) & 15;
+    uint4 t = *(const uint4*)&stg[pi * 16 + 2 * (c ^ (k >> 1))];
+    if (k & 1) t = make_uint4(t.z, t.w, t.x, t.y);
+    v[r] = t;
+    off[r] = pix(pi);
+  }
+  WaveFence::sync();  // stg is free for the next block
+  if (mode == CONV_DGRAD) {
+    uint4 mr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mr[r] = off[r] >= 0 ? ldg16(rref + off[r] + c * 8) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint32_t* vw = (uint32_t*)&v[r];
+      const uint32_t* mw = (const uint32_t*)&mr[r];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t lo = bf_pos((uint16_t)(mw[e] & 0xffffu)) ? 0xffffu : 0u;
+        const uint32_t hi = bf_pos((uint16_t)(mw[e] >> 16)) ? 0xffff0000u : 0u;
+        vw[e] &= lo | hi;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (off[r] >= 0) *(uint4*)(out + off[r] + c * 8) = v[r];
 }
 
 // ------------------------------------------------------------- 64 -> 64
@@ -229,48 +255,19 @@ __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
     tap_step(tap + 1, wb, wa);
   }
   tap_step(8, wa, wb);
-  // epilogue (as epilogue64, for this pixel mapping)
+  // epilogue: the input tile's LDS is reused as the waves' staging areas
+  __syncthreads();
   uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
   const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
-  const int gx = tx0 + (n & 15);
+  uint2* stg = (uint2*)tile + wv * 512;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
-    const int gy = ty0 + wv * 4 + nb * 2 + (n >> 4);
-    const bool ok = gy < H && gx < W;
-    const int64_t po = ok ? ((int64_t)gy * W + gx) * CNN_F : 0;
-    uint2 mref[2][4];
-    if (a.mode == CONV_DGRAD) {
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-          mref[m][g] = ok ? *(const uint2*)(rref + po + m * 32 + 8 * g + hsel * 4) : make_uint2(0, 0);
-    }
-    if (!ok) continue;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int co0 = m * 32 + 8 * g + hsel * 4;
-        float hv[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          float v = acc[m][nb][4 * g + j];
-          if (a.mode == CONV_FWD) {
-            v += sbias[co0 + j];
-            v = v > 0.f ? v : 0.f;
-          } else {
-            const uint32_t word = (j < 2) ? mref[m][g].x : mref[m][g].y;
-            const uint16_t r = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xffffu));
-            if (!bf_pos(r)) v = 0.f;
-          }
-          hv[j] = v;
-        }
-        uint2 pk;
-        pk.x = pack_bf16x2(hv[0], hv[1]);
-        pk.y = pack_bf16x2(hv[2], hv[3]);
-        *(uint2*)(out + po + co0) = pk;
-      }
+    const int gy0 = ty0 + wv * 4 + nb * 2;
+    auto pix = [&](int i) -> int64_t {
+      const int gy = gy0 + (i >> 4), gx = tx0 + (i & 15);
+      return (gy < H && gx < W) ? ((int64_t)gy * W + gx) * CNN_F : -1;
+    };
+    epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, stg, lane, pix, out, rref);
   }
 }
 
@@ -280,6 +277,7 @@ __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
 __global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
   __shared__ uint32_t tile[TILE_PX];
   __shared__ float sbias[CNN_F];
+  __shared__ uint2 stage[4 * 512];  // 4 KB per wave for the epilogue
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
@@ -345,7 +343,17 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
       acc[1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bv, acc[1][nb], 0, 0, 0);
     }
   }
-  epilogue64(acc, sbias, a, d, ty0, tx0, wv, lane);
+  uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
+  const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int gy = ty0 + wv * 4 + nb;
+    auto pix = [&](int i) -> int64_t {
+      const int gx = tx0 + i;
+      return (gy < H && gx < W) ? ((int64_t)gy * W + gx) * CNN_F : -1;
+    };
+    epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, stage + wv * 512, lane, pix, out, rref);
+  }
 }
 
 // ---------------------------------------------------------------- 64 -> 2
