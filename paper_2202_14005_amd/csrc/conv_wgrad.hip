@@ -96,90 +96,91 @@ __device__ __forceinline__ void cursor_seek(TileCursor& c, const WgradArgs& a, i
   while (c.si < a.nslices && t >= c.base + c.ntiles) cursor_load(c, a, c.si + 1, c.base + c.ntiles);
 }
 
-// Loads and channel-major stores of one tile, four consecutive pixels of one
-// 8-channel chunk per work item, so that each channel's four values leave as
-// one 8-byte LDS write (instead of four 2-byte ones).
-//   g items:  (chunk, pixel quad) of the RT x 32 tile: 8 x TPX / 4 = 128
-//   a items:  (dx, chunk, row, column quad) of the shifted copies:
-//             3 x 8 x (RT + 2) x 8 = 768; copy dx, columns 4k..4k+3 read the
-//             halo pixels 4k + dx .. 4k + dx + 3
-constexpr int WGM_GITEMS = 8 * TPX / 4;
-constexpr int WGM_AITEMS = 3 * 8 * (RT + 2) * 8;
-constexpr int WGM_PER_A = (WGM_AITEMS + 511) / 512;
+// The tiles are kept pixel-major (NHWC, 128 bytes a pixel) in LDS and the
+// MFMA fragments are read with the transposing LDS load ds_read_b64_tr_b16:
+// in each 16-lane group, lane r names the 8 bytes (4 channels of one pixel)
+// of row r of a 16 x 4 matrix and receives the column r % 4 ... of rows
+// 4j + r / 4 (j = 0..3), i.e. one channel at 4 consecutive pixels.  Two such
+// reads give a 32 x 16 operand fragment (8 consecutive K = pixels a lane).
+// Because the layout is pixel-major, the column shift of a tap is only an
+// address offset (no shifted copies of the input tile are needed), and the
+// global data reach LDS as whole 16-byte chunks.
+//   g tile:   RT x 32 pixels
+//   act tile: (RT + 2) rows x 34 columns (halo), row stride W2_AROW = 36 so
+//             that every row starts at a pixel index divisible by 4
+// Bank spread: the 16-byte chunk c of LDS pixel P sits at c ^ (4 * bit 1 of
+// P); a 32-lane phase of a transposing read (4 consecutive pixels x 64 bytes)
+// then covers the 64 banks once.
+constexpr int W2_AROW = 36;
+constexpr int W2_GPX = RT * 32;
+constexpr int W2_APX = (RT + 2) * W2_AROW;
+constexpr int W2_PX = W2_GPX + W2_APX;
+constexpr int W2_THREADS = 768;
+constexpr int W2_PER = (W2_PX * 8 + W2_THREADS - 1) / W2_THREADS;
 
-__device__ __forceinline__ void wgm_load(uint4 (&gv)[4], uint4 (&av)[WGM_PER_A][4], const WgradArgs& a,
-                                         const TileCursor& c, int64_t t) {
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int w2_slot(int P, int c) { return P * 8 + (c ^ (((P >> 1) & 1) << 2)); }
+
+__device__ __forceinline__ void w2_load(uint4 (&v)[W2_PER], const WgradArgs& a, const TileCursor& c, int64_t t) {
   const int loc = (int)(t - c.base);
   const int row0 = (loc / c.ntx) * RT, col0 = (loc % c.ntx) * 32;
   const uint16_t* g = a.g + c.xoff * CNN_F;
   const uint16_t* act = a.act + c.xoff * CNN_F;
-  {
-    const int q = threadIdx.x;
-    const int quad = q % (TPX / 4), ch = q / (TPX / 4);
-    const int p0 = quad * 4, gy = row0 + p0 / 32, gx0 = col0 + p0 % 32;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      gv[u] = make_uint4(0, 0, 0, 0);
-      if (q < WGM_GITEMS && gy < c.H && gx0 + u < c.W)
-        gv[u] = *(const uint4*)(g + ((int64_t)gy * c.W + gx0 + u) * CNN_F + ch * 8);
+  for (int j = 0; j < W2_PER; ++j) {
+    const int q = threadIdx.x + W2_THREADS * j;
+    const int P = q >> 3, ch = q & 7;
+    v[j] = make_uint4(0, 0, 0, 0);
+    if (q >= W2_PX * 8) continue;
+    int gy, gx;
+    const uint16_t* src;
+    if (P < W2_GPX) {
+      gy = row0 + P / 32;
+      gx = col0 + P % 32;
+      src = g;
+    } else {
+      const int pa = P - W2_GPX, x = pa % W2_AROW;
+      gy = x < 34 ? row0 - 1 + pa / W2_AROW : -1;
+      gx = col0 - 1 + x;
+      src = act;
     }
-  }
-#pragma unroll
-  for (int j = 0; j < WGM_PER_A; ++j) {
-    const int q = threadIdx.x + 512 * j;
-    const int k = q % 8, r = (q / 8) % (RT + 2), ch = (q / (8 * (RT + 2))) % 8, dx = q / (8 * (RT + 2) * 8);
-    const int gy = row0 - 1 + r, gx0 = col0 + 4 * k + dx - 1;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      av[j][u] = make_uint4(0, 0, 0, 0);
-      if (q < WGM_AITEMS && gy >= 0 && gy < c.H && gx0 + u >= 0 && gx0 + u < c.W)
-        av[j][u] = *(const uint4*)(act + ((int64_t)gy * c.W + gx0 + u) * CNN_F + ch * 8);
-    }
+    if (gy >= 0 && gy < c.H && gx >= 0 && gx < c.W)
+      v[j] = *(const uint4*)(src + ((int64_t)gy * c.W + gx) * CNN_F + ch * 8);
   }
 }
 
-// element e (0..7) of the 8 bf16 channels of a 16-byte chunk
-__device__ __forceinline__ uint32_t chunk_elem(const uint4& v, int e) {
-  const uint32_t w = (e < 2) ? v.x : (e < 4) ? v.y : (e < 6) ? v.z : v.w;
-  return (e & 1) ? (w >> 16) : (w & 0xffffu);
-}
-
-__device__ __forceinline__ void wgm_store(uint16_t* gT, uint16_t* aT, const uint4 (&gv)[4],
-                                          const uint4 (&av)[WGM_PER_A][4]) {
-  {
-    const int q = threadIdx.x;
-    if (q < WGM_GITEMS) {
-      const int quad = q % (TPX / 4), ch = q / (TPX / 4);
+__device__ __forceinline__ void w2_store(uint4* tile, const uint4 (&v)[W2_PER]) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint2 w = make_uint2(chunk_elem(gv[0], e) | (chunk_elem(gv[1], e) << 16),
-                                   chunk_elem(gv[2], e) | (chunk_elem(gv[3], e) << 16));
-        *(uint2*)&gT[(ch * 8 + e) * GROW + quad * 4] = w;
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < WGM_PER_A; ++j) {
-    const int q = threadIdx.x + 512 * j;
-    if (q >= WGM_AITEMS) break;
-    const int k = q % 8, r = (q / 8) % (RT + 2), ch = (q / (8 * (RT + 2))) % 8, dx = q / (8 * (RT + 2) * 8);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint2 w = make_uint2(chunk_elem(av[j][0], e) | (chunk_elem(av[j][1], e) << 16),
-                                 chunk_elem(av[j][2], e) | (chunk_elem(av[j][3], e) << 16));
-      *(uint2*)&aT[(dx * 64 + ch * 8 + e) * AROW + r * 32 + 4 * k] = w;
-    }
+  for (int j = 0; j < W2_PER; ++j) {
+    const int q = threadIdx.x + W2_THREADS * j;
+    if (q < W2_PX * 8) tile[w2_slot(q >> 3, q & 7)] = v[j];
   }
 }
 
-__global__ void __launch_bounds__(512) k_wgrad_mid(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t gT[64 * GROW];
-  __shared__ __attribute__((aligned(16))) uint16_t aT[3 * 64 * AROW];
+// two transposing reads at byte offsets o0, o1 of the tile: one 32 x 16 fragment
+__device__ __forceinline__ uint4 frag_tr(const char* tile, int o0, int o1) {
+  typedef __attribute__((address_space(3))) v4s lds_v4s;
+  const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(tile + o0));
+  const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(tile + o1));
+  const uint2 l = __builtin_bit_cast(uint2, lo), h = __builtin_bit_cast(uint2, hi);
+  return make_uint4(l.x, l.y, h.x, h.y);
+}
+
+// A fixed grid of WGM_WGS workgroups walks the batch's tiles (RT rows x 32
+// columns, slices in order) in contiguous ranges; each keeps its sums in
+// registers over all its tiles and writes one slot at the end.  12 waves,
+// one per (co block of 32, ci block of 32, column tap dx); a wave walks the
+// rows of each 16-column half of the tile and keeps the act fragments of
+// the last three rows, so that each act fragment serves the three row taps.
+// The global data of the next two tiles are loaded into registers while the
+// current tile's MFMAs run.
+__global__ void __launch_bounds__(W2_THREADS) k_wgrad_mid(WgradArgs a) {
+  __shared__ uint4 tile[W2_PX * 8];
   float* part = a.partial + (int64_t)blockIdx.x * a.nout;
   const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int mb = wv & 1, nb = (wv >> 1) & 1, th = wv >> 2;
-  const int tap0 = th ? 5 : 0;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int mb = wv & 1, nb = (wv >> 1) & 1, dx = wv >> 2;
   // this workgroup's tiles [t0, t1) of the batch
   int64_t total = 0;
   for (int si = 0; si < a.nslices; ++si) {
@@ -187,68 +188,84 @@ __global__ void __launch_bounds__(512) k_wgrad_mid(WgradArgs a) {
     total += (int64_t)((d.H + RT - 1) / RT) * ((d.W + 31) / 32);
   }
   const int64_t t0 = total * blockIdx.x / gridDim.x, t1 = total * (blockIdx.x + 1) / gridDim.x;
-  f32x16 acc[5];
+  // lane-constant byte offsets of the fragment reads (see the layout above)
+  const int grp = lane >> 4, rr = lane & 15;
+  int offA[2], offB[2];
 #pragma unroll
-  for (int t = 0; t < 5; ++t)
+  for (int t = 0; t < 2; ++t) {
+    const int k = 8 * (grp >> 1) + 4 * t + (rr >> 2);
+    const int sA = mb * 8 + 4 * (grp & 1) + (rr & 3), swA = ((k >> 1) & 1) << 3;
+    offA[t] = k * 128 + (sA ^ swA) * 8;
+    const int sB = nb * 8 + 4 * (grp & 1) + (rr & 3), swB = (((k + dx) >> 1) & 1) << 3;
+    offB[t] = W2_GPX * 128 + (k + dx) * 128 + (sB ^ swB) * 8;
+  }
+  const char* tb = (const char*)tile;
+  f32x16 acc[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
   float bsum = 0.f;
-  TileCursor cur, nxt;
-  cursor_load(cur, a, 0, 0);
-  cursor_seek(cur, a, t0);
-  nxt = cur;
-  uint4 gv[4], av[WGM_PER_A][4];
-  if (t0 < t1) wgm_load(gv, av, a, cur, t0);
-  for (int64_t t = t0; t < t1; ++t) {
+  const bool bias_wave = nb == 0 && dx == 0;
+  // two register sets of prefetched tiles (tiles t + 1 and t + 2 are in
+  // flight while tile t is computed)
+  TileCursor nxt;
+  cursor_load(nxt, a, 0, 0);
+  uint4 va[W2_PER], vb[W2_PER];
+  if (t0 < t1) {
+    cursor_seek(nxt, a, t0);
+    w2_load(va, a, nxt, t0);
+  }
+  if (t0 + 1 < t1) {
+    cursor_seek(nxt, a, t0 + 1);
+    w2_load(vb, a, nxt, t0 + 1);
+  }
+  auto step = [&](int64_t t, uint4 (&v)[W2_PER]) {
     __syncthreads();
-    wgm_store(gT, aT, gv, av);
+    w2_store(tile, v);
     __syncthreads();
-    if (t + 1 < t1) {
-      cursor_seek(nxt, a, t + 1);
-      wgm_load(gv, av, a, nxt, t + 1);
+    if (t + 2 < t1) {
+      cursor_seek(nxt, a, t + 2);
+      w2_load(v, a, nxt, t + 2);
     }
-    // one fragment set: the reads of k-step ks + 1 are issued right behind the
-    // MFMAs of k-step ks (which read their operands at issue)
-    auto compute = [&](auto th_c) {
-      constexpr int TAP0 = decltype(th_c)::value ? 5 : 0, NTAP = decltype(th_c)::value ? 4 : 5;
-      uint4 af, bfr[NTAP];
-      auto ld = [&](int ks) {
-        const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
-        af = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * GROW + r * 32 + c];
 #pragma unroll
-        for (int k = 0; k < NTAP; ++k) {
-          const int tap = TAP0 + k, dy = tap / 3, dx = tap % 3;
-          bfr[k] = *(const uint4*)&aT[(dx * 64 + nb * 32 + (lane & 31)) * AROW + (r + dy) * 32 + c];
-        }
+    for (int h = 0; h < 2; ++h) {
+      auto fb = [&](int rho) {
+        const int o = (rho * W2_AROW + 16 * h) * 128;
+        return frag_tr(tb, o + offB[0], o + offB[1]);
       };
-      ld(0);
+      uint4 b0 = fb(0), b1 = fb(1);
 #pragma unroll
-      for (int ks = 0; ks < TPX / 16; ++ks) {
-        if (nb == 0 && TAP0 == 0) bsum += frag_sum(af);  // bias gradient, channel mb * 32 + lane % 32
-#pragma unroll
-        for (int k = 0; k < NTAP; ++k)
-          acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(af), as_bf(bfr[k]), acc[k], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        if (ks + 1 < TPX / 16) ld(ks + 1);
+      for (int r = 0; r < RT; ++r) {
+        const uint4 b2 = fb(r + 2);
+        const int o = (r * 32 + 16 * h) * 128;
+        const uint4 af = frag_tr(tb, o + offA[0], o + offA[1]);
+        if (bias_wave) bsum += frag_sum(af);  // bias gradient, channel mb * 32 + lane % 32
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(af), as_bf(b0), acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(af), as_bf(b1), acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(af), as_bf(b2), acc[2], 0, 0, 0);
+        b0 = b1;
+        b1 = b2;
       }
-    };
-    if (th == 0) compute(std::integral_constant<int, 0>{});
-    else compute(std::integral_constant<int, 1>{});
+    }
+  };
+  for (int64_t t = t0; t < t1; t += 2) {
+    step(t, va);
+    if (t + 1 < t1) step(t + 1, vb);
   }
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const int tap = tap0 + k;
-    if (tap > 8) break;
+  for (int dy = 0; dy < 3; ++dy) {
+    const int tap = dy * 3 + dx;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int co = mb * 32 + 8 * (v >> 2) + (lane >> 5) * 4 + (v & 3);
       const int ci = nb * 32 + (lane & 31);
-      part[(co * 64 + ci) * 9 + tap] = acc[k][v];
+      part[(tap * 64 + co) * 64 + ci] = acc[dy][v];  // tap-major: 128-byte runs of ci
     }
   }
   // lanes l and l + 32 hold the two pixel halves of channel mb * 32 + l % 32
   bsum += __shfl_xor(bsum, 32, 64);
-  if (nb == 0 && th == 0 && lane < 32) part[64 * 64 * 9 + mb * 32 + lane] = bsum;
+  if (bias_wave && lane < 32) part[64 * 64 * 9 + mb * 32 + lane] = bsum;
 }
 
 // ------------------------------------------------------------- 2 -> 64
@@ -400,9 +417,11 @@ __global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
 
 // out[i] (+)= sum_s partial[s][i] over nslots slots in a fixed order: a
 // block takes 64 outputs; its 4 waves sum the slots s = w, w + 4, ... in
-// increasing order, then the 4 wave sums are added in wave order.
+// increasing order, then the 4 wave sums are added in wave order.  With
+// tap_major the weight entries of the slots are ordered [tap][co][ci]
+// (64 x 64 channels) and go to the [co][ci][tap] gradient.
 __global__ void __launch_bounds__(256) k_wgrad_reduce(const float* partial, int nslots, int nout, float* w_out,
-                                                      float* b_out, int nweights, int accumulate) {
+                                                      float* b_out, int nweights, int accumulate, int tap_major) {
   __shared__ float red[4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
@@ -420,7 +439,9 @@ __global__ void __launch_bounds__(256) k_wgrad_reduce(const float* partial, int 
   __syncthreads();
   if (wv == 0 && i < nout) {
     const float t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-    float* dst = i < nweights ? w_out + i : b_out + (i - nweights);
+    int wi = i;
+    if (tap_major && i < nweights) wi = (i % 4096) * 9 + i / 4096;
+    float* dst = i < nweights ? w_out + wi : b_out + (i - nweights);
     *dst = accumulate ? *dst + t : t;
   }
 }
@@ -428,15 +449,16 @@ __global__ void __launch_bounds__(256) k_wgrad_reduce(const float* partial, int 
 hipError_t wgrad_launch(int kind, const WgradArgs& a, int bands, hipStream_t s) {
   dim3 grid(bands, a.nslices);
   if (kind == 0) hipLaunchKernelGGL(k_wgrad_first, grid, dim3(256), 0, s, a);
-  else if (kind == 1) hipLaunchKernelGGL(k_wgrad_mid, dim3(WGM_WGS), dim3(512), 0, s, a);
+  else if (kind == 1) hipLaunchKernelGGL(k_wgrad_mid, dim3(WGM_WGS), dim3(W2_THREADS), 0, s, a);
   else hipLaunchKernelGGL(k_wgrad_last, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t wgrad_reduce(const float* partial, int nslots, int nout, float* w_out, float* b_out, int nweights,
-                        int accumulate, hipStream_t s) {
+                        int accumulate, int tap_major, hipStream_t s) {
+  if (tap_major && nweights != 64 * 64 * 9) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 63) / 64), dim3(256), 0, s, partial, nslots, nout, w_out,
-                     b_out, nweights, accumulate);
+                     b_out, nweights, accumulate, tap_major);
   return hipGetLastError();
 }
 

@@ -138,7 +138,7 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     if (r != hipSuccess) return r;
     const int nslots = kind == 1 ? WGM_WGS : 2 * slots;
     const int nw = w.nout - (kind == 2 ? 2 : 64);
-    return wgrad_reduce(part, nslots, w.nout, g->w[layer], g->b[layer], nw, accumulate, s);
+    return wgrad_reduce(part, nslots, w.nout, g->w[layer], g->b[layer], nw, accumulate, kind == 1, s);
   };
   // layer 5 (64 -> 2)
   e = wg(2, nullptr, act[3], gz, 4);

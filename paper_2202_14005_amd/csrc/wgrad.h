@@ -21,8 +21,9 @@ struct WgradArgs {
 
 // kind: 0 = first (2 -> 64), 1 = middle (64 -> 64), 2 = last (64 -> 2)
 hipError_t wgrad_launch(int kind, const WgradArgs& a, int bands, hipStream_t s);
+// tap_major: the slots hold the 64 x 64 x 9 weight entries as [tap][co][ci]
 hipError_t wgrad_reduce(const float* partial, int nslots, int nout, float* w_out, float* b_out, int nweights,
-                        int accumulate, hipStream_t s);
+                        int accumulate, int tap_major, hipStream_t s);
 // kind: 0 = first, 1 = middle, 2 = last
 hipError_t conv_launch(int kind, const struct ConvArgs& a, hipStream_t s);
 hipError_t pack_weights(int kind, const float* Wm, uint16_t* out, int transpose, hipStream_t s);
