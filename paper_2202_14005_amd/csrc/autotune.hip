@@ -49,13 +49,18 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
         return ok;
       };
       if (!run()) continue;  // warm-up
-      hipEventRecord(e0, s);
+      // the fastest of five timed pairs: robust against a slow outlier
       bool ok = true;
-      for (int rep = 0; rep < 3; ++rep) ok = ok && run();
-      hipEventRecord(e1, s);
-      hipEventSynchronize(e1);
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      float ms = 1e30f;
+      for (int trial = 0; trial < 5 && ok; ++trial) {
+        hipEventRecord(e0, s);
+        for (int rep = 0; rep < 2; ++rep) ok = ok && run();
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float t = 0.f;
+        hipEventElapsedTime(&t, e0, e1);
+        ms = t < ms ? t : ms;
+      }
       if (ok && ms < best_ms) { best_ms = ms; best = v; }
     }
     g.col = best;

@@ -1,10 +1,10 @@
 // Weight and bias gradients of the denoiser's 3x3 convolutions
 //   dW[co][ci][tap] = sum_p g[p][co] * a[p + d(tap)][ci],   db[co] = sum_p g[p][co]
-// as MFMA products with the pixel index as the reduction (K) dimension.  Tiles
-// of WG_ROWS rows x 32 columns are staged in LDS channel-major ([channel][pixel]),
-// so a fragment of 8 consecutive pixels of one channel is one 16-byte read.
-// Every workgroup writes its partial sums to its own slot; a second kernel
-// adds the slots in a fixed order (deterministic, no float atomics).
+// as MFMA products with the pixel index as the reduction (K) dimension.  A
+// fixed grid of WGM_WGS workgroups walks the batch's tiles of WG_ROWS rows x
+// 32 columns; every workgroup writes its partial sums to its own slot and a
+// second kernel adds the slots in a fixed order (deterministic, no float
+// atomics) and scatters them to the [co][ci][tap] gradient layout.
 #include <type_traits>
 
 #include "conv.h"
@@ -24,37 +24,7 @@ __device__ __forceinline__ uint16_t f2bf_w(float f) {
 __device__ __forceinline__ float bf2f_w(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-constexpr int RT = WG_ROWS;             // rows per tile
-constexpr int TPX = RT * 32;            // pixels per tile
-// Row strides of the channel-major LDS tiles, padded by 16 bytes so that the
-// 16-byte fragment reads of 16 consecutive channels start in distinct bank
-// groups (an unpadded 128- or 256-byte stride puts them all in one).
-constexpr int GROW = TPX + 8;
-constexpr int AROW = (RT + 2) * 32 + 8;
-
-// gT[ch][p] = g[tile pixel p][ch] for 64-channel bf16 NHWC g (zero outside).
-// All of a thread's loads are issued before its LDS writes.
-__device__ __forceinline__ void fill_gT(uint16_t* gT, const uint16_t* g, int H, int W, int row0, int col0) {
-  constexpr int PER = (TPX * 8 + 255) / 256;
-  uint4 v[PER];
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int q = threadIdx.x + 256 * j;
-    const int p = q % TPX, ch = q / TPX;
-    const int gy = row0 + p / 32, gx = col0 + p % 32;
-    v[j] = make_uint4(0, 0, 0, 0);
-    if (q < TPX * 8 && gy < H && gx < W) v[j] = *(const uint4*)(g + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
-  }
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int q = threadIdx.x + 256 * j;
-    if (q >= TPX * 8) break;
-    const int p = q % TPX, ch = q / TPX;
-    const uint16_t* h = (const uint16_t*)&v[j];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) gT[(ch * 8 + e) * GROW + p] = h[e];
-  }
-}
+constexpr int RT = WG_ROWS;  // rows per tile (tiles are RT x 32 pixels)
 
 // Sum of the 8 bf16 values of a fragment, in fp32, in index order.
 __device__ __forceinline__ float frag_sum(uint4 v) {
@@ -268,197 +238,254 @@ __global__ void __launch_bounds__(W2_THREADS) k_wgrad_mid(WgradArgs a) {
   if (bias_wave && lane < 32) part[64 * 64 * 9 + mb * 32 + lane] = bsum;
 }
 
-// ------------------------------------------------------------- 2 -> 64
-// dW1[co][ci][tap] with N = (tap, ci) = 18 padded to 32; waves split
-// (co block) x (k-step parity); each parity has its own partial slot.
-__global__ void __launch_bounds__(256) k_wgrad_first(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t gT[64 * GROW];
-  __shared__ uint16_t xT[2 * (RT + 2) * 34];
-  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int mb = wv & 1, par = wv >> 1;
-  float* part = a.partial + (int64_t)(wg * 2 + par) * a.nout;
-  const int b = a.slices[blockIdx.y];
-  const SliceDesc d = a.desc[b];
-  const int H = d.H, W = d.W;
-  f32x16 acc;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  float bsum = 0.f;
-  const uint16_t* g = a.g + d.xoff * CNN_F;
-  const float2* x = a.x + d.xoff;
-  const int j = lane & 31;
-  const int tap = j >> 1, ci = j & 1;
-  const int dy = tap / 3, dx = tap % 3;
-  const int band0 = blockIdx.x * WG_BAND;
-  for (int rt = 0; rt < WG_BAND / RT; ++rt) {
-    const int row0 = band0 + rt * RT;
-    if (row0 >= H) break;
-    for (int col0 = 0; col0 < W; col0 += 32) {
-      __syncthreads();
-      fill_gT(gT, g, H, W, row0, col0);
-      for (int p = threadIdx.x; p < (RT + 2) * 34; p += 256) {
-        const int gy = row0 - 1 + p / 34, gx = col0 - 1 + p % 34;
-        float2 v = make_float2(0.f, 0.f);
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = x[(int64_t)gy * W + gx];
-        xT[p] = f2bf_w(v.x);
-        xT[(RT + 2) * 34 + p] = f2bf_w(v.y);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int ks = par; ks < TPX / 16; ks += 2) {
-        const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
-        const uint4 araw = *(const uint4*)&gT[(mb * 32 + (lane & 31)) * GROW + r * 32 + c];
-        const bf16x8 av = as_bf(araw);
-        bsum += frag_sum(araw);  // bias gradient, this parity's pixels
-        uint4 raw;
-        uint16_t* h = (uint16_t*)&raw;
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          h[e] = (j < 18) ? xT[ci * (RT + 2) * 34 + (r + dy) * 34 + c + e + dx] : (uint16_t)0;
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf(raw), acc, 0, 0, 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int co = mb * 32 + 8 * (v >> 2) + (lane >> 5) * 4 + (v & 3);
-    if (j < 18) part[(co * 2 + ci) * 9 + tap] = acc[v];
-  }
-  bsum += __shfl_xor(bsum, 32, 64);
-  if (lane < 32) part[64 * 2 * 9 + mb * 32 + lane] = bsum;
-}
+// ------------------------------------------------- 2 -> 64 and 64 -> 2
+// One 64-channel operand (the first layer's output gradient g1, the last
+// layer's input activation a4) comes from an RT x 32 NHWC tile read with the
+// transposing loads; the other (the complex input x of the first layer, the
+// complex output gradient g5 of the last) from a bf16 halo tile, re and im
+// planes with row stride 36, gathered per lane.  The 18 (tap, complex
+// component) pairs fill one 32-wide MFMA dimension (padded).  4 waves:
+// (64-channel block of 32, 16-column half of the tile); the two halves'
+// sums are added through LDS at the end.  Tiles t + 1 and t + 2 are
+// prefetched into registers; WGS_WGS workgroups (four a CU) keep enough
+// loads in flight.
+constexpr int WS_THREADS = 256;
+constexpr int WS_CPX = (RT + 2) * 34;          // complex halo pixels
+constexpr int WS_CROW = 36;
 
-// ------------------------------------------------------------- 64 -> 2
-// dW5[co][ci][tap] = sum_q g5[q - d][co] a4[q][ci]; M = (tap, co) = 18 padded
-// to 32, N = ci (two blocks); waves split (ci block) x (k-step parity).
-__global__ void __launch_bounds__(256) k_wgrad_last(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t aT[64 * GROW];
-  __shared__ uint16_t gH[2 * (RT + 2) * 34];
-  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nb = wv & 1, par = wv >> 1;
-  float* part = a.partial + (int64_t)(wg * 2 + par) * a.nout;
-  const int b = a.slices[blockIdx.y];
-  const SliceDesc d = a.desc[b];
-  const int H = d.H, W = d.W;
-  f32x16 acc;
+struct SmallPre {
+  uint4 t[4];  // 64-channel tile: 1024 chunks over 256 threads
+  float2 c;    // complex halo pixel threadIdx.x (if < WS_CPX)
+};
+
+__device__ __forceinline__ void ws_load(SmallPre& v, const uint16_t* t64, const float2* cx, const TileCursor& c,
+                                        int64_t t) {
+  const int loc = (int)(t - c.base);
+  const int row0 = (loc / c.ntx) * RT, col0 = (loc % c.ntx) * 32;
+  const uint16_t* src = t64 + c.xoff * CNN_F;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  float bs0 = 0.f, bs1 = 0.f;
-  const float2* g5 = a.x + d.xoff;  // complex gradient of the network output
-  const uint16_t* act = a.act + d.xoff * CNN_F;
-  const int i = lane & 31;
-  const int tap = i >> 1, co = i & 1;
-  const int dy = tap / 3, dx = tap % 3;
-  const int band0 = blockIdx.x * WG_BAND;
-  for (int rt = 0; rt < WG_BAND / RT; ++rt) {
-    const int row0 = band0 + rt * RT;
-    if (row0 >= H) break;
-    for (int col0 = 0; col0 < W; col0 += 32) {
-      __syncthreads();
-      fill_gT(aT, act, H, W, row0, col0);
-      for (int p = threadIdx.x; p < (RT + 2) * 34; p += 256) {
-        const int gy = row0 - 1 + p / 34, gx = col0 - 1 + p % 34;
-        float2 v = make_float2(0.f, 0.f);
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = g5[(int64_t)gy * W + gx];
-        gH[p] = f2bf_w(v.x);
-        gH[(RT + 2) * 34 + p] = f2bf_w(v.y);
-      }
-      __syncthreads();
-      if (wv == 0) {  // bias gradient from the fp32 output gradient: wave 0, per lane
-        for (int p = lane; p < TPX; p += 64) {
-          const int gy = row0 + p / 32, gx = col0 + p % 32;
-          if (gy < H && gx < W) {
-            const float2 v = g5[(int64_t)gy * W + gx];
-            bs0 += v.x;
-            bs1 += v.y;
-          }
-        }
-      }
-#pragma unroll
-      for (int ks = par; ks < TPX / 16; ks += 2) {
-        const int r = ks >> 1, c = (ks & 1) * 16 + (lane >> 5) * 8;
-        uint4 raw;
-        uint16_t* h = (uint16_t*)&raw;
-        // q - d in halo coordinates: (r + 2 - dy, c + e + 2 - dx)
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          h[e] = (i < 18) ? gH[co * (RT + 2) * 34 + (r + 2 - dy) * 34 + c + e + 2 - dx] : (uint16_t)0;
-        const bf16x8 bv = as_bf(*(const uint4*)&aT[(nb * 32 + (lane & 31)) * GROW + r * 32 + c]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(raw), bv, acc, 0, 0, 0);
-      }
-    }
+  for (int j = 0; j < 4; ++j) {
+    const int q = threadIdx.x + WS_THREADS * j;
+    const int P = q >> 3, ch = q & 7;
+    const int gy = row0 + P / 32, gx = col0 + P % 32;
+    v.t[j] = make_uint4(0, 0, 0, 0);
+    if (gy < c.H && gx < c.W) v.t[j] = *(const uint4*)(src + ((int64_t)gy * c.W + gx) * CNN_F + ch * 8);
   }
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int ii = 8 * (v >> 2) + (lane >> 5) * 4 + (v & 3);
-    const int ci = nb * 32 + (lane & 31);
-    if (ii < 18) part[((ii & 1) * 64 + ci) * 9 + (ii >> 1)] = acc[v];
-  }
-  // wave 0 (par 0) holds per-lane sums; fixed butterfly
-  if (wv == 0) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      bs0 += __shfl_xor(bs0, off, 64);
-      bs1 += __shfl_xor(bs1, off, 64);
-    }
-  }
-  // slot (wg, par 0) carries the bias sums, slot (wg, par 1) zeros
-  if (wv == 0 && lane == 0) {
-    part[2 * 64 * 9 + 0] = bs0;
-    part[2 * 64 * 9 + 1] = bs1;
-  }
-  if (wv == 2 && lane == 0) {
-    part[2 * 64 * 9 + 0] = 0.f;
-    part[2 * 64 * 9 + 1] = 0.f;
+  v.c = make_float2(0.f, 0.f);
+  if (threadIdx.x < WS_CPX) {
+    const int gy = row0 - 1 + threadIdx.x / 34, gx = col0 - 1 + threadIdx.x % 34;
+    if (gy >= 0 && gy < c.H && gx >= 0 && gx < c.W) v.c = cx[c.xoff + (int64_t)gy * c.W + gx];
   }
 }
 
-// out[i] (+)= sum_s partial[s][i] over nslots slots in a fixed order: a
-// block takes 64 outputs; its 4 waves sum the slots s = w, w + 4, ... in
-// increasing order, then the 4 wave sums are added in wave order.  With
-// tap_major the weight entries of the slots are ordered [tap][co][ci]
-// (64 x 64 channels) and go to the [co][ci][tap] gradient.
-__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* partial, int nslots, int nout, float* w_out,
-                                                      float* b_out, int nweights, int accumulate, int tap_major) {
-  __shared__ float red[4][64];
+__device__ __forceinline__ void ws_store(uint4* tile, uint16_t* cs, const SmallPre& v) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int q = threadIdx.x + WS_THREADS * j;
+    tile[w2_slot(q >> 3, q & 7)] = v.t[j];
+  }
+  if (threadIdx.x < WS_CPX) {
+    const int o = (threadIdx.x / 34) * WS_CROW + threadIdx.x % 34;
+    cs[o] = f2bf_w(v.c.x);
+    cs[(RT + 2) * WS_CROW + o] = f2bf_w(v.c.y);
+  }
+}
+
+// LAST = false: dW1 (M = co of g1, N = (tap, ci) of x);
+// LAST = true:  dW5 (M = (tap, co) of g5 shifted, N = ci of a4).
+template <bool LAST>
+__global__ void __launch_bounds__(WS_THREADS) k_wgrad_small(WgradArgs a) {
+  __shared__ uint4 tile[RT * 32 * 8];
+  __shared__ uint16_t cs[2 * (RT + 2) * WS_CROW];
+  __shared__ float comb[2][16][64];
+  float* part = a.partial + (int64_t)blockIdx.x * a.nout;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int blk = wv & 1, h = wv >> 1;
+  int64_t total = 0;
+  for (int si = 0; si < a.nslices; ++si) {
+    const SliceDesc d = a.desc[a.slices[si]];
+    total += (int64_t)((d.H + RT - 1) / RT) * ((d.W + 31) / 32);
+  }
+  const int64_t t0 = total * blockIdx.x / gridDim.x, t1 = total * (blockIdx.x + 1) / gridDim.x;
+  // transposing-read offsets of the 64-channel operand (channel block blk)
+  const int grp = lane >> 4, rr = lane & 15;
+  int off[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int k = 8 * (grp >> 1) + 4 * t + (rr >> 2);
+    off[t] = k * 128 + ((blk * 8 + 4 * (grp & 1) + (rr & 3)) ^ (((k >> 1) & 1) << 3)) * 8;
+  }
+  // gathered operand: index j = lane % 32 = 2 tap + component (j < 18)
+  const int j = lane & 31, tap = j >> 1, comp = j & 1, dy = tap / 3, dx = tap % 3;
+  const int cbase = comp * (RT + 2) * WS_CROW + (LAST ? (2 - dy) * WS_CROW + 2 - dx : dy * WS_CROW + dx) +
+                    16 * h + 8 * (lane >> 5);
+  const char* tb = (const char*)tile;
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  float bsum = 0.f, bs0 = 0.f, bs1 = 0.f;
+  const uint16_t* t64 = LAST ? a.act : a.g;
+  TileCursor nxt;
+  cursor_load(nxt, a, 0, 0);
+  SmallPre va, vb;
+  if (t0 < t1) {
+    cursor_seek(nxt, a, t0);
+    ws_load(va, t64, a.x, nxt, t0);
+  }
+  if (t0 + 1 < t1) {
+    cursor_seek(nxt, a, t0 + 1);
+    ws_load(vb, t64, a.x, nxt, t0 + 1);
+  }
+  auto step = [&](int64_t t, SmallPre& v) {
+    __syncthreads();
+    ws_store(tile, cs, v);
+    if (LAST && threadIdx.x < WS_CPX) {  // bias of the last layer: interior pixels, fp32
+      const int y = threadIdx.x / 34, x = threadIdx.x % 34;
+      if (y >= 1 && y <= RT && x >= 1 && x <= 32) {
+        bs0 += v.c.x;
+        bs1 += v.c.y;
+      }
+    }
+    __syncthreads();
+    if (t + 2 < t1) {
+      cursor_seek(nxt, a, t + 2);
+      ws_load(v, t64, a.x, nxt, t + 2);
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const int o = (r * 32 + 16 * h) * 128;
+      const uint4 f = frag_tr(tb, o + off[0], o + off[1]);
+      uint4 raw;
+      uint16_t* e8 = (uint16_t*)&raw;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) e8[e] = j < 18 ? cs[cbase + r * WS_CROW + e] : (uint16_t)0;
+      if (LAST) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(raw), as_bf(f), acc, 0, 0, 0);
+      } else {
+        bsum += frag_sum(f);  // bias gradient, channel blk * 32 + lane % 32
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(f), as_bf(raw), acc, 0, 0, 0);
+      }
+    }
+  };
+  for (int64_t t = t0; t < t1; t += 2) {
+    step(t, va);
+    if (t + 1 < t1) step(t + 1, vb);
+  }
+  // add the column halves (h = 1 through LDS, in that fixed order)
+  if (h == 1) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) comb[blk][v][lane] = acc[v];
+  }
+  bsum += __shfl_xor(bsum, 32, 64);  // lanes l and l + 32: the two k halves of a channel
+  __syncthreads();
+  if (h == 0) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float s = acc[v] + comb[blk][v][lane];
+      const int m = 8 * (v >> 2) + (lane >> 5) * 4 + (v & 3);  // MFMA row
+      if (LAST) {
+        if (m < 18) part[m * 64 + blk * 32 + (lane & 31)] = s;  // [tap, co][ci]
+      } else {
+        part[(blk * 32 + m) * 32 + j] = s;  // [co][tap, ci] (j >= 18: zero padding)
+      }
+    }
+  }
+  if (!LAST) {
+    // bias: waves (blk, h = 0) and (blk, h = 1) each hold half of the pixels
+    __syncthreads();
+    if (h == 1 && lane < 32) comb[blk][0][lane] = bsum;
+    __syncthreads();
+    if (h == 0 && lane < 32) part[64 * 32 + blk * 32 + lane] = bsum + comb[blk][0][lane];
+  } else {
+    // bias: per-thread sums -> wave butterfly -> the 4 wave sums in order
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      bs0 += __shfl_xor(bs0, o, 64);
+      bs1 += __shfl_xor(bs1, o, 64);
+    }
+    __syncthreads();
+    if (lane == 0) {
+      comb[0][0][wv] = bs0;
+      comb[0][1][wv] = bs1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      part[18 * 64 + 0] = ((comb[0][0][0] + comb[0][0][1]) + comb[0][0][2]) + comb[0][0][3];
+      part[18 * 64 + 1] = ((comb[0][1][0] + comb[0][1][1]) + comb[0][1][2]) + comb[0][1][3];
+    }
+  }
+}
+
+// out (+)= sum_s partial[s] over nslots slots in a fixed order: a block
+// takes 64 partial entries; its 16 waves sum the slots s = w, w + 16, ... in
+// increasing order, then the 16 wave sums are added in wave order.  Entries
+// [0, npw) are weights in the slot layout `layout`, the rest biases:
+//   WG_LAYOUT_MID:   [tap][co][ci], 64 x 64
+//   WG_LAYOUT_FIRST: [co][2 tap + ci], 64 x 32 (entries 18..31 of a row unused)
+//   WG_LAYOUT_LAST:  [2 tap + co][ci], 18 x 64
+// and go to the [co][ci][tap] gradient.
+__device__ __forceinline__ int wg_dst(int layout, int i) {
+  if (layout == WG_LAYOUT_MID) return (i % 4096) * 9 + i / 4096;
+  if (layout == WG_LAYOUT_FIRST) {
+    const int co = i >> 5, jj = i & 31;
+    return jj < 18 ? (co * 2 + (jj & 1)) * 9 + (jj >> 1) : -1;
+  }
+  const int m = i >> 6, ci = i & 63;
+  return ((m & 1) * 64 + ci) * 9 + (m >> 1);
+}
+
+constexpr int WR_WAVES = 16;
+
+__global__ void __launch_bounds__(64 * WR_WAVES) k_wgrad_reduce(const float* partial, int nslots, int nout,
+                                                               float* w_out, float* b_out, int npw, int accumulate,
+                                                               int layout) {
+  __shared__ float red[WR_WAVES][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   float s = 0.f;
   if (i < nout) {
     int k = wv;
-    for (; k + 12 < nslots; k += 16) {
-      const float a0 = partial[(int64_t)k * nout + i], a1 = partial[(int64_t)(k + 4) * nout + i];
-      const float a2 = partial[(int64_t)(k + 8) * nout + i], a3 = partial[(int64_t)(k + 12) * nout + i];
+    for (; k + 3 * WR_WAVES < nslots; k += 4 * WR_WAVES) {
+      const float a0 = partial[(int64_t)k * nout + i];
+      const float a1 = partial[(int64_t)(k + WR_WAVES) * nout + i];
+      const float a2 = partial[(int64_t)(k + 2 * WR_WAVES) * nout + i];
+      const float a3 = partial[(int64_t)(k + 3 * WR_WAVES) * nout + i];
       s += a0; s += a1; s += a2; s += a3;
     }
-    for (; k < nslots; k += 4) s += partial[(int64_t)k * nout + i];
+    for (; k < nslots; k += WR_WAVES) s += partial[(int64_t)k * nout + i];
   }
   red[wv][lane] = s;
   __syncthreads();
   if (wv == 0 && i < nout) {
-    const float t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-    int wi = i;
-    if (tap_major && i < nweights) wi = (i % 4096) * 9 + i / 4096;
-    float* dst = i < nweights ? w_out + wi : b_out + (i - nweights);
-    *dst = accumulate ? *dst + t : t;
+    float t = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < WR_WAVES; ++w) t += red[w][lane];
+    float* dst = nullptr;
+    if (i >= npw) {
+      dst = b_out + (i - npw);
+    } else {
+      const int wi = wg_dst(layout, i);
+      if (wi >= 0) dst = w_out + wi;
+    }
+    if (dst) *dst = accumulate ? *dst + t : t;
   }
 }
 
-hipError_t wgrad_launch(int kind, const WgradArgs& a, int bands, hipStream_t s) {
-  dim3 grid(bands, a.nslices);
-  if (kind == 0) hipLaunchKernelGGL(k_wgrad_first, grid, dim3(256), 0, s, a);
+hipError_t wgrad_launch(int kind, const WgradArgs& a, hipStream_t s) {
+  if (a.nout != wgrad_nout(kind)) return hipErrorInvalidValue;
+  if (kind == 0) hipLaunchKernelGGL(k_wgrad_small<false>, dim3(WGS_WGS), dim3(WS_THREADS), 0, s, a);
   else if (kind == 1) hipLaunchKernelGGL(k_wgrad_mid, dim3(WGM_WGS), dim3(W2_THREADS), 0, s, a);
-  else hipLaunchKernelGGL(k_wgrad_last, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_wgrad_small<true>, dim3(WGS_WGS), dim3(WS_THREADS), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t wgrad_reduce(const float* partial, int nslots, int nout, float* w_out, float* b_out, int nweights,
-                        int accumulate, int tap_major, hipStream_t s) {
-  if (tap_major && nweights != 64 * 64 * 9) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 63) / 64), dim3(256), 0, s, partial, nslots, nout, w_out,
-                     b_out, nweights, accumulate, tap_major);
+hipError_t wgrad_reduce(int kind, const float* partial, float* w_out, float* b_out, int accumulate, hipStream_t s) {
+  const int nout = wgrad_nout(kind);
+  const int npw = kind == 1 ? 64 * 64 * 9 : kind == 0 ? 64 * 32 : 18 * 64;
+  const int layout = kind == 1 ? WG_LAYOUT_MID : kind == 0 ? WG_LAYOUT_FIRST : WG_LAYOUT_LAST;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 63) / 64), dim3(64 * WR_WAVES), 0, s, partial,
+                     wgrad_slots(kind), nout, w_out, b_out, npw, accumulate, layout);
   return hipGetLastError();
 }
 

@@ -14,11 +14,7 @@ static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr int PK_FIRST = 2 * 2 * 64 * 8;
 constexpr int PK_MID = 9 * 4 * 2 * 64 * 8;
 constexpr int PK_LAST = 9 * 2 * 64 * 8;
-constexpr int NOUT_MID = 64 * 64 * 9 + 64;
-constexpr int NOUT_FIRST = 64 * 2 * 9 + 64;
-constexpr int NOUT_LAST = 2 * 64 * 9 + 2;
 
-static int bands_of(mrx_plan_s* p) { return (p->maxH + WG_BAND - 1) / WG_BAND; }
 size_t net_workspace_bytes(mrx_plan_s* p);
 
 // Network workspace layout, appended after the SENSE/CG part (flags bit 0).
@@ -39,8 +35,9 @@ size_t net_workspace_bytes(mrx_plan_s* p) {
   for (int i = 0; i < 2; ++i) p->ws_gimg[i] = take(ni * 8);
   p->ws_vimg = take(ni * 8);
   p->ws_pk = take((size_t)2 * (PK_FIRST + 3 * PK_MID + PK_LAST) * 2);
-  const size_t slots = (size_t)bands_of(p) * p->B;
-  p->ws_wpart = take(std::max<size_t>({(size_t)WGM_WGS * NOUT_MID, 2 * slots * NOUT_FIRST, 2 * slots * NOUT_LAST}) * 4);
+  size_t wpart = 0;
+  for (int k = 0; k < 3; ++k) wpart = std::max(wpart, (size_t)wgrad_slots(k) * wgrad_nout(k));
+  p->ws_wpart = take(wpart * 4);
   p->ws_loss = take((size_t)p->B * p->nrr * 4);
   return w;
 }
@@ -121,8 +118,6 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
   for (int i = 0; i < 4; ++i) act[i] = (uint16_t*)(p->ws + p->ws_act[i]);
   uint16_t* gb[2] = {(uint16_t*)(p->ws + p->ws_gact[0]), (uint16_t*)(p->ws + p->ws_gact[1])};
   float* part = (float*)(p->ws + p->ws_wpart);
-  const int bands = bands_of(p);
-  const int slots = bands * p->B;
   hipError_t e;
   auto wg = [&](int kind, const uint16_t* gin, const uint16_t* ain, const float2* xin, int layer) {
     WgradArgs w{};
@@ -133,12 +128,10 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     w.act = ain;
     w.x = xin;
     w.partial = part;
-    w.nout = kind == 1 ? NOUT_MID : kind == 0 ? NOUT_FIRST : NOUT_LAST;
-    hipError_t r = wgrad_launch(kind, w, bands, s);
+    w.nout = wgrad_nout(kind);
+    hipError_t r = wgrad_launch(kind, w, s);
     if (r != hipSuccess) return r;
-    const int nslots = kind == 1 ? WGM_WGS : 2 * slots;
-    const int nw = w.nout - (kind == 2 ? 2 : 64);
-    return wgrad_reduce(part, nslots, w.nout, g->w[layer], g->b[layer], nw, accumulate, kind == 1, s);
+    return wgrad_reduce(kind, part, g->w[layer], g->b[layer], accumulate, s);
   };
   // layer 5 (64 -> 2)
   e = wg(2, nullptr, act[3], gz, 4);

@@ -4,9 +4,15 @@
 
 namespace mrx {
 
-constexpr int WG_ROWS = 4;   // rows per LDS tile
-constexpr int WG_BAND = 4;   // rows per workgroup (a band of tiles), first and last layers
-constexpr int WGM_WGS = 256; // workgroups (and partial slots) of the middle-layer kernel
+constexpr int WG_ROWS = 4;   // rows per tile (tiles are WG_ROWS x 32 pixels)
+constexpr int WGM_WGS = 256;   // workgroups (and partial slots) of the 64 -> 64 weight gradient
+constexpr int WGS_WGS = 1024;  // the same for the 2 -> 64 and 64 -> 2 layers (small slots)
+constexpr int wgrad_slots(int kind) { return kind == 1 ? WGM_WGS : WGS_WGS; }
+
+// partial-slot layouts of the three kinds (weights, then biases)
+constexpr int WG_LAYOUT_FIRST = 0, WG_LAYOUT_MID = 1, WG_LAYOUT_LAST = 2;
+// floats per partial slot: kind 0 = first (2 -> 64), 1 = middle, 2 = last (64 -> 2)
+constexpr int wgrad_nout(int kind) { return kind == 1 ? 64 * 64 * 9 + 64 : kind == 0 ? 64 * 32 + 64 : 18 * 64 + 2; }
 
 struct WgradArgs {
   const SliceDesc* desc;
@@ -19,11 +25,11 @@ struct WgradArgs {
   int nout;
 };
 
-// kind: 0 = first (2 -> 64), 1 = middle (64 -> 64), 2 = last (64 -> 2)
-hipError_t wgrad_launch(int kind, const WgradArgs& a, int bands, hipStream_t s);
-// tap_major: the slots hold the 64 x 64 x 9 weight entries as [tap][co][ci]
-hipError_t wgrad_reduce(const float* partial, int nslots, int nout, float* w_out, float* b_out, int nweights,
-                        int accumulate, int tap_major, hipStream_t s);
+// kind: 0 = first (2 -> 64), 1 = middle (64 -> 64), 2 = last (64 -> 2); a.partial
+// holds wgrad_slots(kind) slots of wgrad_nout(kind) floats
+hipError_t wgrad_launch(int kind, const WgradArgs& a, hipStream_t s);
+// sums the slots of wgrad_launch into the [co][ci][tap] weight gradient and the bias
+hipError_t wgrad_reduce(int kind, const float* partial, float* w_out, float* b_out, int accumulate, hipStream_t s);
 // kind: 0 = first, 1 = middle, 2 = last
 hipError_t conv_launch(int kind, const struct ConvArgs& a, hipStream_t s);
 hipError_t pack_weights(int kind, const float* Wm, uint16_t* out, int transpose, hipStream_t s);
