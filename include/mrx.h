@@ -307,6 +307,23 @@ mrx_status mrx_vn_stage_backward(mrx_plan plan, const float* g, const float* x, 
  * start from the cached choice. */
 mrx_status mrx_plan_autotune(mrx_plan plan, const float* S, const float* mask, float* scratch_a,
                              float* scratch_b, void* stream);
+/* Kernel timing (measurement aid): with timing on, every launch of the
+ * kernels below made through this plan on a stream that is not being
+ * captured is bracketed by a pair of HIP events on that stream.
+ * mrx_plan_kernel_timing(plan, enable) switches it on or off and drops the
+ * records so far (the events are kept for reuse and freed with the plan).
+ * mrx_plan_kernel_time synchronises with the recorded launches of kernel
+ * `kid` and returns their summed duration in microseconds and their number.
+ * Timing adds two event records to each timed launch. */
+enum {
+  MRX_KERNEL_NORMAL = 0,     /* normal operator (plain and CG-fused) */
+  MRX_KERNEL_CG_UPDATE = 1,  /* CG update of x, r and the residual partials */
+  MRX_KERNEL_CONV_MID = 2,   /* 64 -> 64 denoiser layer (forward and input gradient) */
+  MRX_KERNEL_WGRAD_MID = 3,  /* weight gradient of a 64 -> 64 layer */
+  MRX_KERNEL_COUNT = 4
+};
+mrx_status mrx_plan_kernel_timing(mrx_plan plan, int32_t enable);
+mrx_status mrx_plan_kernel_time(mrx_plan plan, int32_t kid, double* total_us, int32_t* count);
 /* Name of the schedule the plan uses for slice b's column transform. */
 const char* mrx_plan_schedule(mrx_plan plan, int32_t b);
 /* Name of the idx-th registered column schedule for length n, or NULL. */

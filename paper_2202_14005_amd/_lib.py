@@ -49,6 +49,8 @@ SIGNATURES = {
     "mrx_mse_grad": (c_int32, [P, P, P, P, P, P]),
     "mrx_adam_step": (c_int32, [P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "mrx_plan_schedule": (c_char_p, [P, c_int32]),
+    "mrx_plan_kernel_timing": (c_int32, [P, c_int32]),
+    "mrx_plan_kernel_time": (c_int32, [P, c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int32)]),
     "mrx_schedule_name": (c_char_p, [c_int32, c_int32]),
     "mrx_vn_stage": (c_int32, [P, P, P, P, P, P, P, P]),
     "mrx_vn_stage_backward": (c_int32, [P, P, P, P, P, P, P, P, P, P, P, c_int32, P]),

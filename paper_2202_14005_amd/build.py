@@ -93,6 +93,17 @@ SCHEDULES = [
     ("n320_4x4x20_t16_w16_g2_rl_k3", 4, 4, 20, 16, 16, 16, 2, 0, 0, 3),
     ("n320_4x4x20_t16_w8_g2_rl_k2", 4, 4, 20, 16, 8, 16, 2, 0, 0, 2),
     ("n384_4x4x24_t16_w16_k3", 4, 4, 24, 16, 16, 16, 1, 1, 0, 3),
+    ("n320_4x4x20_t16_w16_rl_k2", 4, 4, 20, 16, 16, 16, 1, 0, 0, 2),
+    ("n320_4x4x20_t16_w16_rl_k4", 4, 4, 20, 16, 16, 16, 1, 0, 0, 4),
+    ("n320_4x4x20_t16_w8_rl_k2", 4, 4, 20, 16, 8, 16, 1, 0, 0, 2),
+    ("n320_4x4x20_t16_w8_rl_k3", 4, 4, 20, 16, 8, 16, 1, 0, 0, 3),
+    ("n320_4x4x20_t16_w8_rl_k4", 4, 4, 20, 16, 8, 16, 1, 0, 0, 4),
+    ("n192_4x4x12_t16_w16_rl_k3", 4, 4, 12, 16, 16, 16, 1, 0, 0, 3),
+    ("n192_4x4x12_t16_w8_rl_k3", 4, 4, 12, 16, 8, 16, 1, 0, 0, 3),
+    ("n256_4x4x16_t16_w16_rl_k3", 4, 4, 16, 16, 16, 16, 1, 0, 0, 3),
+    ("n256_4x4x16_t16_w8_rl_k3", 4, 4, 16, 16, 8, 16, 1, 0, 0, 3),
+    ("n384_4x4x24_t16_w16_rl_k3", 4, 4, 24, 16, 16, 16, 1, 0, 0, 3),
+    ("n384_4x4x24_t16_w8_rl_k3", 4, 4, 24, 16, 8, 16, 1, 0, 0, 3),
 ]
 
 COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net.hip", "conv.hip",

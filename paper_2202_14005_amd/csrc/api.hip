@@ -29,6 +29,26 @@ mrx_status hip_fail(hipError_t e, const char* what) {
   return MRX_EHIP;
 }
 
+KernelTimer::KernelTimer(mrx_plan_s* p, int kid, hipStream_t s) : p_(p), s_(s) {
+  if (!p->ktime || kid < 0) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  while (p->kpool.size() < p->kpool_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    p->kpool.push_back(e);
+  }
+  hipEvent_t a = p->kpool[p->kpool_used], b = p->kpool[p->kpool_used + 1];
+  if (hipEventRecord(a, s) != hipSuccess) return;
+  p->kpool_used += 2;
+  p->kev.push_back({a, b, kid});
+  b_ = b;
+}
+
+KernelTimer::~KernelTimer() {
+  if (b_) (void)hipEventRecord(b_, s_);
+}
+
 static std::vector<ColVariant>& col_registry() {
   static std::vector<ColVariant> v;
   return v;
@@ -206,7 +226,34 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
 void mrx_plan_destroy(mrx_plan p) {
   if (!p) return;
   if (p->d_tables) (void)hipFree(p->d_tables);
+  for (hipEvent_t e : p->kpool) (void)hipEventDestroy(e);
   delete p;
+}
+
+mrx_status mrx_plan_kernel_timing(mrx_plan p, int32_t enable) {
+  if (!p) return fail(MRX_EINVAL, "kernel_timing: null plan");
+  p->ktime = enable != 0;
+  p->kev.clear();
+  p->kpool_used = 0;
+  return MRX_OK;
+}
+
+mrx_status mrx_plan_kernel_time(mrx_plan p, int32_t kid, double* total_us, int32_t* count) {
+  if (!p) return fail(MRX_EINVAL, "kernel_time: null plan");
+  if (kid < 0 || kid >= MRX_KERNEL_COUNT) return fail(MRX_EINVAL, "kernel_time: unknown kernel id");
+  double t = 0.0;
+  int32_t n = 0;
+  for (const auto& e : p->kev) {
+    if (e.kid != kid) continue;
+    if (hipEventSynchronize(e.b) != hipSuccess) return fail(MRX_EHIP, "kernel_time: event synchronize");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) return fail(MRX_EHIP, "kernel_time: elapsed time");
+    t += ms * 1e3;
+    ++n;
+  }
+  if (total_us) *total_us = t;
+  if (count) *count = n;
+  return MRX_OK;
 }
 
 mrx_status mrx_plan_sizes(mrx_plan p, int64_t* ni, int64_t* nc, int64_t* nm) {

@@ -53,11 +53,33 @@ struct mrx_plan_s {
   size_t ws_vn_kt = 0, ws_vn_u = 0, ws_vn_e = 0, ws_vn_kg = 0, ws_vn_s = 0, ws_vn_qx = 0, ws_vn_qg = 0;
   size_t ws_vn_plam = 0, ws_vn_pk = 0, ws_vn_pw = 0;
   bool net_ready = false;
+  // optional timing of the hot kernels: a pair of events around each launch
+  struct KEvent {
+    hipEvent_t a, b;
+    int kid;
+  };
+  bool ktime = false;
+  std::vector<hipEvent_t> kpool;  // created on demand, reused after a reset
+  size_t kpool_used = 0;
+  std::vector<KEvent> kev;
 };
 
 namespace mrx {
 
 mrx_status fail(mrx_status st, const std::string& msg);
+
+// Times one launch (constructor before, destructor after) when the plan's
+// kernel timing is on and the stream is not being captured.
+class KernelTimer {
+ public:
+  KernelTimer(mrx_plan_s* p, int kid, hipStream_t s);
+  ~KernelTimer();
+
+ private:
+  mrx_plan_s* p_;
+  hipStream_t s_;
+  hipEvent_t b_ = nullptr;
+};
 mrx_status hip_fail(hipError_t e, const char* what);
 const ColVariant* find_col(int N, const char* name);
 const RowVariant* find_row(int N);

@@ -95,6 +95,7 @@ static mrx_status cnn_fwd(mrx_plan_s* p, const float2* x, float2* z, hipStream_t
     m.out_bf16 = act[l];
     m.wpk = pk_ptr(p, 0, l);
     m.bias = p->net_b[l];
+    KernelTimer kt(p, MRX_KERNEL_CONV_MID, s);
     e = conv_launch(1, m, s);
   }
   if (e == hipSuccess) {
@@ -129,7 +130,11 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     w.x = xin;
     w.partial = part;
     w.nout = wgrad_nout(kind);
-    hipError_t r = wgrad_launch(kind, w, s);
+    hipError_t r;
+    {
+      KernelTimer kt(p, kind == 1 ? MRX_KERNEL_WGRAD_MID : -1, s);
+      r = wgrad_launch(kind, w, s);
+    }
     if (r != hipSuccess) return r;
     return wgrad_reduce(kind, part, g->w[layer], g->b[layer], accumulate, s);
   };
@@ -155,7 +160,10 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     m.out_bf16 = gb[1 - cur];
     m.wpk = pk_ptr(p, 1, l);
     m.relu_ref = act[l - 1];
-    e = conv_launch(1, m, s);
+    {
+      KernelTimer kt(p, MRX_KERNEL_CONV_MID, s);
+      e = conv_launch(1, m, s);
+    }
     cur = 1 - cur;
   }
   // layer 1 (2 -> 64) and the residual
@@ -296,7 +304,11 @@ mrx_status mrx_cnn_layer_forward(mrx_plan p, int32_t layer, const void* in, void
   m.out_bf16 = (uint16_t*)out;
   m.wpk = pk_ptr(p, 0, layer);
   m.bias = p->net_b[layer];
-  hipError_t e = conv_launch(1, m, (hipStream_t)stream);
+  hipError_t e;
+  {
+    KernelTimer kt(p, MRX_KERNEL_CONV_MID, (hipStream_t)stream);
+    e = conv_launch(1, m, (hipStream_t)stream);
+  }
   return e == hipSuccess ? MRX_OK : hip_fail(e, "cnn_layer_forward");
 }
 

@@ -71,6 +71,7 @@ mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const fl
     na.qout = out;
     na.tw = p->tw.at(g.H);
     na.mode = 0;
+    KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
     hipError_t e = g.col->normal(na, g.W, s);
     if (e != hipSuccess) return hip_fail(e, "sense_normal");
   }
@@ -135,13 +136,17 @@ mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const floa
       na.pq_part = pq;
       na.npq = p->npq;
       na.stopped = a.stopped;
+      KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
       e = g.col->normal(na, g.W, s);
       if (e != hipSuccess) return hip_fail(e, "cg: normal operator");
     }
     a.rr_cur = rr_cur;
     a.rr_next = rr_prev;  // rho_{k+1} overwrites rho_{k-1}
     a.p = pb[k & 1];
-    e = cg_update(a, s);
+    {
+      KernelTimer kt(p, MRX_KERNEL_CG_UPDATE, s);
+      e = cg_update(a, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "cg: update");
   }
   if (hist) {

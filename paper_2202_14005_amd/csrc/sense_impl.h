@@ -79,9 +79,20 @@ k_normal(NormalArgs a) {
   // this workgroup's coils: [c_begin, c_end) of the slice's C
   const int c_begin = (ks * d.C) / KSPL, c_end = ((ks + 1) * d.C) / KSPL;
   const int lid = threadIdx.x;
-  const int grp = lid / NT, l2 = lid % NT;
+  static_assert(G == 1 || NT % 64 == 0, "a coil group must be whole wavefronts");
+  const int grp = G > 1 ? __builtin_amdgcn_readfirstlane(lid / NT) : 0;  // wave-uniform
+  const int l2 = lid % NT;
   const int c = l2 % WT, tc = l2 / WT;
   const int col = tile * WT + c;
+  // element (a1(tc, i, r), col) of a plane with row stride W: a per-lane byte
+  // offset plus a wave-uniform part, so that every load and store of the
+  // transform addresses a scalar base with one shared 32-bit vector offset
+  const uint32_t voff = (uint32_t)(tc * W + col) * 8u;
+  auto at = [&](auto* base, int i, int r) {
+    using E = std::remove_pointer_t<decltype(base)>;
+    using B = std::conditional_t<std::is_const_v<E>, const char, char>;
+    return (E*)((B*)(base + (T * i + r * Sd::M1) * W) + voff);
+  };
   const bool valid = col < W;
   const bool cg = a.mode == 1;
   if (cg && a.stopped[b]) return;
@@ -112,9 +123,8 @@ k_normal(NormalArgs a) {
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
-        const int o = Sd::a1(tc, i, r) * W + col;
-        float2 pv = valid ? pbase[o] : make_float2(0.f, 0.f);
-        float2 rv = valid ? rbase[o] : make_float2(0.f, 0.f);
+        float2 pv = valid ? *at(pbase, i, r) : make_float2(0.f, 0.f);
+        float2 rv = valid ? *at(rbase, i, r) : make_float2(0.f, 0.f);
         pv = make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
         p[i * Sd::N1 + r] = pv;
       }
@@ -127,17 +137,17 @@ k_normal(NormalArgs a) {
 #pragma unroll
       for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
-        for (int r = 0; r < Sd::N1; ++r) pobase[Sd::a1(tc, i, r) * W + col] = p[i * Sd::N1 + r];
+        for (int r = 0; r < Sd::N1; ++r) *at(pobase, i, r) = p[i * Sd::N1 + r];
     }
   } else {
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
-        const int o = Sd::a1(tc, i, r) * W + col;
-        p[i * Sd::N1 + r] = valid ? pbase[o] : make_float2(0.f, 0.f);
+        p[i * Sd::N1 + r] = valid ? *at(pbase, i, r) : make_float2(0.f, 0.f);
       }
   }
+
 
   float2 acc[P];
 #pragma unroll
@@ -156,8 +166,7 @@ k_normal(NormalArgs a) {
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
-        const int o = Sd::a1(tc, i, r) * W + col;
-        const float2 s = on ? Sc[o] : make_float2(0.f, 0.f);
+        const float2 s = on ? *at(Sc, i, r) : make_float2(0.f, 0.f);
         if constexpr (KS) sk[i * Sd::N1 + r] = s;
         v[i * Sd::N1 + r] = cmul(s, p[i * Sd::N1 + r]);
       }
@@ -178,7 +187,7 @@ k_normal(NormalArgs a) {
           const int k = i * Sd::N1 + r;
           float2 s;
           if constexpr (KS) s = sk[k];
-          else s = ld_stream(&Sc[Sd::a1(tc, i, r) * W + col]);
+          else s = ld_stream(at(Sc, i, r));
           acc[k] = cadd(acc[k], cmulc(s, v[k]));
         }
     }
@@ -217,7 +226,7 @@ k_normal(NormalArgs a) {
         const int k = i * Sd::N1 + r;
         const float2 q = make_float2(acc[k].x + lam * p[k].x, acc[k].y + lam * p[k].y);
         dot += p[k].x * q.x + p[k].y * q.y;
-        if (valid) qbase[Sd::a1(tc, i, r) * W + col] = q;
+        if (valid) *at(qbase, i, r) = q;
       }
   }
   if (cg) {

@@ -207,6 +207,21 @@ class Plan:
     def schedule(self, b=0):
         return lib().mrx_plan_schedule(self._h, int(b)).decode()
 
+    # kernel ids of kernel_time
+    KERNEL_NORMAL, KERNEL_CG_UPDATE, KERNEL_CONV_MID, KERNEL_WGRAD_MID = 0, 1, 2, 3
+
+    def kernel_timing(self, enable: bool):
+        """Switch per-launch event timing of the hot kernels on or off (and
+        drop the records so far)."""
+        check(lib().mrx_plan_kernel_timing(self._h, int(bool(enable))), "kernel_timing")
+
+    def kernel_time(self, kid: int):
+        """(summed microseconds, launches) of kernel ``kid`` since timing was
+        switched on; synchronises with the recorded launches."""
+        t, n = ctypes.c_double(0.0), ctypes.c_int32(0)
+        check(lib().mrx_plan_kernel_time(self._h, int(kid), ctypes.byref(t), ctypes.byref(n)), "kernel_time")
+        return t.value, n.value
+
     def set_schedule(self, n, name):
         check(lib().mrx_plan_set_schedule(self._h, int(n), name.encode()), "plan_set_schedule")
 

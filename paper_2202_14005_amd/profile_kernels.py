@@ -1,11 +1,14 @@
 """Run the hot kernels alone, for profilers (rocprofv3 --pmc / --kernel-trace).
 
     python -m paper_2202_14005_amd.profile_kernels [--reps 3] [--what normal,conv,copy]
+        [--schedule NAME | --tune]
 
 Workload: the MoDL inference batch (8 slices of 320 x 320, 15 coils, R = 4
-variable-density mask with 24 centre lines).  ``normal`` applies the normal
-operator (A^H A + lambda I) once per repetition (one k_normal launch per
-repetition: the kernel whose HBM bytes the benchmark's roofline reports),
+variable-density mask with 24 centre lines).  ``normal`` runs one CG solve
+of ``reps`` iterations (one CG-fused k_normal launch and one k_cg_update per
+iteration, as in the MoDL step; the kernel whose HBM bytes the benchmark's
+roofline reports) with the given column schedule, or the autotuner's choice
+with --tune, or the default,
 ``conv`` one 64 -> 64 denoiser layer (k_conv_mid16), ``backward`` one reverse
 pass of the denoiser (input gradient and weight gradients, all five
 layers), ``copy`` a device-to-device
@@ -31,6 +34,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--what", default="normal,conv,copy")
+    ap.add_argument("--schedule", default=None)
+    ap.add_argument("--tune", action="store_true")
     a = ap.parse_args()
     what = set(a.what.split(","))
     dev = torch.device("cuda", 0)
@@ -39,8 +44,11 @@ def main():
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     plan = ops.Plan(H, W, C, B=B, device=dev, network=True)
     x, S, m = t(d["x"]), t(d["S"]), t(d["mask"])
+    if a.schedule:
+        plan.set_schedule(H, a.schedule)
+    elif a.tune:
+        plan.autotune(S, m)
     lam = plan.lam(0.05)
-    q = torch.empty_like(x)
     cnn = ops.CNN.init(7, dev)
     a_in = torch.randn(B * H * W * 64, device=dev).to(torch.bfloat16)
     a_out = torch.empty_like(a_in)
@@ -51,9 +59,9 @@ def main():
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
+    if "normal" in what:
+        plan.cg_dc(x, S, m, lam, a.reps)
     for _ in range(a.reps):
-        if "normal" in what:
-            plan.sense_normal(x, S, m, lam, out=q)
         if "conv" in what:
             plan.cnn_layer_forward(2, a_in, cnn, out=a_out)
         if "backward" in what:

@@ -222,3 +222,26 @@ def test_every_schedule_normal_and_cg(H, W, C):
         print(f"{name}: normal {e_q:.2e} cg {e_x:.2e}")
         assert e_q < OP_TOL, name
         assert e_x < CG_TOL, name
+
+
+def test_kernel_timing_records_each_launch():
+    """Per-launch event timing: one record per normal-operator launch and CG
+    update of a solve, none once switched off; the solve's result is the
+    same with timing on."""
+    H, W, C, B, n = 64, 48, 4, 2, 7
+    d = case_inputs(H, W, C, "uniform", B=B, seed=1900)
+    S, m, x = dev(d["S"]), dev(d["mask"]), dev(d["x"])
+    plan = Plan(H, W, C, B=B)
+    ref = plan.cg_dc(x, S, m, 0.05, n)
+    plan.kernel_timing(True)
+    out = plan.cg_dc(x, S, m, 0.05, n)
+    t_n, c_n = plan.kernel_time(plan.KERNEL_NORMAL)
+    t_u, c_u = plan.kernel_time(plan.KERNEL_CG_UPDATE)
+    assert (c_n, c_u) == (n, n) and t_n > 0 and t_u > 0
+    assert torch.equal(out, ref)
+    plan.sense_normal(x, S, m, 0.1)
+    assert plan.kernel_time(plan.KERNEL_NORMAL)[1] == n + 1
+    assert plan.kernel_time(plan.KERNEL_CONV_MID) == (0.0, 0)
+    plan.kernel_timing(False)
+    plan.cg_dc(x, S, m, 0.05, n)
+    assert plan.kernel_time(plan.KERNEL_NORMAL) == (0.0, 0)
