@@ -24,17 +24,20 @@ __device__ __forceinline__ float bsum(float v, float* red) {
 }
 
 __device__ __forceinline__ float psum(const float* a, int n) {
-  // fixed-order sum by every thread of the block (n is small)
-  __shared__ float tmp[CG_THREADS];
+  // fixed-order sum, returned to every thread of the block: thread t adds
+  // a[t], a[t + CG_THREADS], ...; then a fixed butterfly in each wavefront
+  // and the wavefront sums in order
+  __shared__ float tmp[CG_THREADS / 64];
   float s = 0.f;
   for (int i = threadIdx.x; i < n; i += CG_THREADS) s += a[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   __syncthreads();
-  tmp[threadIdx.x] = s;
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = s;
   __syncthreads();
   float t = 0.f;
-  const int m = n < CG_THREADS ? n : CG_THREADS;
-  for (int i = 0; i < m; ++i) t += tmp[i];
-  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < CG_THREADS / 64; ++w) t += tmp[w];
   return t;
 }
 
@@ -71,6 +74,28 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_update(CgElemArgs a) {
   const int b = a.slices[blockIdx.y];
   const SliceDesc d = a.desc[b];
   const int64_t n = (int64_t)d.H * d.W;
+  const int64_t base = (int64_t)blockIdx.x * CG_EPB;
+  // all of a thread's loads are issued first (one memory latency per block,
+  // overlapping the reductions that give alpha)
+  constexpr int PER = CG_EPB / CG_THREADS;
+  float2 rv[PER], pv[PER], qv[PER], xv[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = base + threadIdx.x + j * CG_THREADS;
+    const int64_t o = d.xoff + (i < n ? i : 0);
+    rv[j] = a.r[o];
+    pv[j] = a.p[o];
+    qv[j] = a.q[o];
+    xv[j] = a.x[o];
+  }
+  if (d.nq > 1) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int64_t i = base + threadIdx.x + j * CG_THREADS;
+      const int64_t o = d.xoff + (i < n ? i : 0);
+      for (int k = 1; k < d.nq; ++k) qv[j] = cadd(qv[j], a.q[k * a.qstride + o]);
+    }
+  }
   const float rho = psum(a.rr_cur + (int64_t)b * a.nrr, a.nrr);
   const float pq = psum(a.pq + (int64_t)b * a.npq, a.npq);
   bool stop = a.stopped[b] != 0;
@@ -87,30 +112,6 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_update(CgElemArgs a) {
   }
   const float alpha = stop ? 0.f : rho / pq;
   float rr = 0.f;
-  const int64_t base = (int64_t)blockIdx.x * CG_EPB;
-  // all of a thread's loads are issued before the updates (one memory
-  // latency per block instead of one per element)
-  constexpr int PER = CG_EPB / CG_THREADS;
-  float2 rv[PER], pv[PER], qv[PER], xv[PER];
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int64_t i = base + threadIdx.x + j * CG_THREADS;
-    const int64_t o = d.xoff + (i < n ? i : 0);
-    rv[j] = a.r[o];
-    if (!stop) {
-      pv[j] = a.p[o];
-      qv[j] = a.q[o];
-      xv[j] = a.x[o];
-    }
-  }
-  if (!stop && d.nq > 1) {
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int64_t i = base + threadIdx.x + j * CG_THREADS;
-      const int64_t o = d.xoff + (i < n ? i : 0);
-      for (int k = 1; k < d.nq; ++k) qv[j] = cadd(qv[j], a.q[k * a.qstride + o]);
-    }
-  }
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int64_t i = base + threadIdx.x + j * CG_THREADS;
