@@ -38,45 +38,14 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
 }
 
-// LDS input tile: (16 + 2) x (32 + 2) pixels x 64 channels bf16, as 8 chunks
-// of 16 bytes per pixel (128 bytes = 32 banks).  Chunk c of pixel p sits at
-// slot c ^ ((p >> 1) & 7): 16 consecutive pixels then cover the 64 banks
-// exactly once for a fixed chunk (pixel parity picks the bank half, the slot
-// the 4-bank group), so a 16-lane phase of a 16-byte read is conflict free.
+// Input tile of the first layer: (16 + 2) x (32 + 2) complex pixels.
 constexpr int TILE_PX = (CONV_TH + 2) * (CONV_TW + 2);
 
+// 64-channel LDS tiles: 8 chunks of 16 bytes per pixel (128 bytes = 32
+// banks).  Chunk c of pixel p sits at slot c ^ ((p >> 1) & 7): 16
+// consecutive pixels then cover the 64 banks exactly once for a fixed chunk
+// (pixel parity picks the bank half, the slot the 4-bank group).
 __device__ __forceinline__ int swz(int px) { return (px >> 1) & 7; }
-
-// Fill the LDS tile: every thread owns the chunks q = tid + 256 k; the loads
-// of a batch are all issued before any of them is written to LDS, so the
-// memory latency is paid once per batch rather than once per chunk.
-constexpr int TILE_CHUNKS = TILE_PX * 8;
-constexpr int TILE_PER_THREAD = (TILE_CHUNKS + 255) / 256;
-
-__device__ __forceinline__ void load_tile64(uint4* tile, const uint16_t* in, int H, int W, int ty0, int tx0) {
-  constexpr int BATCH = 10;
-#pragma unroll
-  for (int k0 = 0; k0 < TILE_PER_THREAD; k0 += BATCH) {
-    uint4 v[BATCH];
-    int slot[BATCH];
-#pragma unroll
-    for (int j = 0; j < BATCH; ++j) {
-      const int q = threadIdx.x + 256 * (k0 + j);
-      v[j] = make_uint4(0, 0, 0, 0);
-      slot[j] = -1;
-      if (k0 + j < TILE_PER_THREAD && q < TILE_CHUNKS) {
-        const int px = q >> 3, ch = q & 7;
-        const int ly = px / (CONV_TW + 2), lx = px - ly * (CONV_TW + 2);
-        const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
-        slot[j] = px * 8 + (ch ^ swz(px));
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) v[j] = ldg16(in + ((int64_t)gy * W + gx) * CNN_F + ch * 8);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < BATCH; ++j)
-      if (slot[j] >= 0) tile[slot[j]] = v[j];
-  }
-}
 
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return (h & 0x8000u) == 0 && h != 0; }
 
@@ -358,14 +327,15 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
 
 // ---------------------------------------------------------------- 64 -> 2
 // v_mfma_f32_16x16x32_bf16 with the two output channels padded to 16 rows;
-// each wave covers 4 rows x 32 columns = 8 blocks of 16 pixels.
+// 16 x 16-pixel tiles (41.5 KB of LDS, three workgroups a CU); each wave
+// covers 4 rows x 16 columns = 4 blocks of 16 pixels.
 // Output: out_c = resid + (acc + bias)  (fwd: z = x + N(x); dgrad: g_x).
-__global__ void __launch_bounds__(256, 2) k_conv_last(ConvArgs a) {
-  __shared__ uint4 tile[TILE_PX * 8];
+__global__ void __launch_bounds__(256, 3) k_conv_last(ConvArgs a) {
+  __shared__ uint4 tile[TILE16_PX * 8];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
-  const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
+  const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
   if (tx0 >= W || ty0 >= H) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint16_t* wp = a.wpk + lane * 8;
@@ -375,11 +345,11 @@ __global__ void __launch_bounds__(256, 2) k_conv_last(ConvArgs a) {
     wf[k][0] = ldg16(wp + (k * 2 + 0) * 512);
     wf[k][1] = ldg16(wp + (k * 2 + 1) * 512);
   }
-  load_tile64(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
+  load_tile64_16(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
   __syncthreads();
-  f32x4 acc[8];
+  f32x4 acc[4];
 #pragma unroll
-  for (int n = 0; n < 8; ++n)
+  for (int n = 0; n < 4; ++n)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[n][v] = 0.f;
 #pragma unroll
@@ -390,8 +360,8 @@ __global__ void __launch_bounds__(256, 2) k_conv_last(ConvArgs a) {
       const bf16x8 w = as_bf16x8(wf[tap][cc]);
       const int ch = cc * 4 + (lane >> 4);
 #pragma unroll
-      for (int n = 0; n < 8; ++n) {
-        const int px = (wv * 4 + (n >> 1) + dy) * (CONV_TW + 2) + (n & 1) * 16 + (lane & 15) + dx;
+      for (int n = 0; n < 4; ++n) {
+        const int px = (wv * 4 + n + dy) * (TW16 + 2) + (lane & 15) + dx;
         const bf16x8 bv = as_bf16x8(tile[px * 8 + (ch ^ swz(px))]);
         acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, bv, acc[n], 0, 0, 0);
       }
@@ -402,15 +372,15 @@ __global__ void __launch_bounds__(256, 2) k_conv_last(ConvArgs a) {
   float2* out = a.out_c + d.xoff;
   const float2* res = a.resid ? a.resid + d.xoff : nullptr;
   bool bad = false;
-  float2 rv[8];
+  float2 rv[4];
 #pragma unroll
-  for (int n = 0; n < 8; ++n) {
-    const int gy = ty0 + wv * 4 + (n >> 1), gx = tx0 + (n & 1) * 16 + lane;
+  for (int n = 0; n < 4; ++n) {
+    const int gy = ty0 + wv * 4 + n, gx = tx0 + lane;
     rv[n] = (res && gy < H && gx < W) ? res[(int64_t)gy * W + gx] : make_float2(0.f, 0.f);
   }
 #pragma unroll
-  for (int n = 0; n < 8; ++n) {
-    const int gy = ty0 + wv * 4 + (n >> 1), gx = tx0 + (n & 1) * 16 + lane;
+  for (int n = 0; n < 4; ++n) {
+    const int gy = ty0 + wv * 4 + n, gx = tx0 + lane;
     if (gy >= H || gx >= W) continue;
     const int64_t o = (int64_t)gy * W + gx;
     float2 v = make_float2(rv[n].x + acc[n][0] + b0, rv[n].y + acc[n][1] + b1);
@@ -475,7 +445,10 @@ hipError_t conv_launch(int kind, const ConvArgs& a, hipStream_t s) {
     dim3 g16((a.tiles_x * CONV_TW + TW16 - 1) / TW16, a.tiles_y, a.nslices);
     hipLaunchKernelGGL(k_conv_mid16, g16, dim3(256), 0, s, a);
   }
-  else hipLaunchKernelGGL(k_conv_last, grid, dim3(256), 0, s, a);
+  else {
+    dim3 g16((a.tiles_x * CONV_TW + TW16 - 1) / TW16, a.tiles_y, a.nslices);
+    hipLaunchKernelGGL(k_conv_last, g16, dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
