@@ -8,7 +8,7 @@ namespace mrx {
 
 constexpr int CNN_F = 64;      // feature channels
 constexpr int CNN_L = 5;       // layers
-constexpr int CONV_TW = 32;    // output tile width (pixels)
+constexpr int CONV_TW = 16;    // output tile width (pixels)
 constexpr int CONV_TH = 16;    // output tile height (rows); 4 waves x 4 rows
 
 // Packed bf16 weights of one network (layout chosen for the MFMA operand
@@ -33,7 +33,7 @@ struct ConvArgs {
   const SliceDesc* desc;
   const int* slices;
   int nslices;
-  int tiles_x;               // max over slices of ceil(W / 32)
+  int tiles_x;               // max over slices of ceil(W / 16)
   int tiles_y;               // max over slices of ceil(H / 16)
   const uint16_t* in_bf16;   // NHWC bf16, pixel offset xoff * 64
   const float2* in_c;        // complex image (first layer input / last layer residual)

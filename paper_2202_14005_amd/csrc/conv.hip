@@ -38,8 +38,6 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
 }
 
-// Input tile of the first layer: (16 + 2) x (32 + 2) complex pixels.
-constexpr int TILE_PX = (CONV_TH + 2) * (CONV_TW + 2);
 
 // 64-channel LDS tiles: 8 chunks of 16 bytes per pixel (128 bytes = 32
 // banks).  Chunk c of pixel p sits at slot c ^ ((p >> 1) & 7): 16
@@ -137,8 +135,9 @@ __device__ __forceinline__ void epi_block64(const f32x16& a0, const f32x16& a1, 
 // the weight fragments of the next tap are fetched from L2 while the
 // current tap runs, in two register sets used in turn (a rolled loop with
 // one set made the compiler wait for the loads at the back edge).
-constexpr int TW16 = 16;
+constexpr int TW16 = CONV_TW;
 constexpr int TILE16_PX = (CONV_TH + 2) * (TW16 + 2);
+constexpr int TILE1_PX = TILE16_PX;  // first layer: complex pixels (bf16 re, im in one word)
 constexpr int TILE16_CHUNKS = TILE16_PX * 8;
 constexpr int TILE16_PER_THREAD = (TILE16_CHUNKS + 255) / 256;
 
@@ -242,15 +241,16 @@ __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
 
 // ---------------------------------------------------------------- 2 -> 64
 // Input: complex image (fp32 pairs), rounded to bf16.  K = 9 taps x 2 channels
-// = 18, padded to 32 (two 16-deep MFMA steps).
-__global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
-  __shared__ uint32_t tile[TILE_PX];
+// = 18, padded to 32 (two 16-deep MFMA steps).  16 x 16-pixel tiles; each
+// wave computes 4 rows x 16 columns x 64 channels (2 pixel blocks).
+__global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
+  __shared__ uint32_t tile[TILE1_PX];
   __shared__ float sbias[CNN_F];
   __shared__ uint2 stage[4 * 512];  // 4 KB per wave for the epilogue
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
-  const int tx0 = blockIdx.x * CONV_TW, ty0 = blockIdx.y * CONV_TH;
+  const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
   if (tx0 >= W || ty0 >= H) return;
   const float2* in = a.in_c + d.xoff;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -263,14 +263,14 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
   }
   if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
   {
-    constexpr int PT = (TILE_PX + 255) / 256;
+    constexpr int PT = (TILE1_PX + 255) / 256;
     float2 v[PT];
 #pragma unroll
     for (int j = 0; j < PT; ++j) {
       const int px = threadIdx.x + 256 * j;
       v[j] = make_float2(0.f, 0.f);
-      if (px < TILE_PX) {
-        const int ly = px / (CONV_TW + 2), lx = px - ly * (CONV_TW + 2);
+      if (px < TILE1_PX) {
+        const int ly = px / (TW16 + 2), lx = px - ly * (TW16 + 2);
         const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
         if (gy >= 0 && gy < H && gx >= 0 && gx < W) v[j] = in[(int64_t)gy * W + gx];
       }
@@ -278,23 +278,25 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < PT; ++j) {
       const int px = threadIdx.x + 256 * j;
-      if (px < TILE_PX) tile[px] = (uint32_t)f2bf(v[j].x) | ((uint32_t)f2bf(v[j].y) << 16);
+      if (px < TILE1_PX) tile[px] = (uint32_t)f2bf(v[j].x) | ((uint32_t)f2bf(v[j].y) << 16);
     }
   }
   __syncthreads();
-  f32x16 acc[2][4];
+  f32x16 acc[2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int n = 0; n < 2; ++n)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[m][n][v] = 0.f;
+  // pixel n of block nb: row wv * 4 + nb * 2 + n / 16, column n % 16
+  const int pbase = (wv * 4 + ((lane & 31) >> 4)) * (TW16 + 2) + (lane & 15);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const bf16x8 w0 = as_bf16x8(wf[s][0]);
     const bf16x8 w1 = as_bf16x8(wf[s][1]);
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+    for (int nb = 0; nb < 2; ++nb) {
       uint4 raw;
       uint32_t* rw = (uint32_t*)&raw;
 #pragma unroll
@@ -303,7 +305,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
         uint32_t v = 0;
         if (t < 9) {
           const int dy = t / 3, dx = t % 3;
-          v = tile[(wv * 4 + nb + dy) * (CONV_TW + 2) + (lane & 31) + dx];
+          v = tile[pbase + (nb * 2 + dy) * (TW16 + 2) + dx];
         }
         rw[e] = v;
       }
@@ -315,10 +317,10 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvArgs a) {
   uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
   const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int gy = ty0 + wv * 4 + nb;
+  for (int nb = 0; nb < 2; ++nb) {
+    const int gy0 = ty0 + wv * 4 + nb * 2;
     auto pix = [&](int i) -> int64_t {
-      const int gx = tx0 + i;
+      const int gy = gy0 + (i >> 4), gx = tx0 + (i & 15);
       return (gy < H && gx < W) ? ((int64_t)gy * W + gx) * CNN_F : -1;
     };
     epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, stage + wv * 512, lane, pix, out, rref);
@@ -439,16 +441,10 @@ __global__ void k_pack_last(const float* Wm, uint16_t* out, int transpose) {
 }
 
 hipError_t conv_launch(int kind, const ConvArgs& a, hipStream_t s) {
-  dim3 grid(a.tiles_x, a.tiles_y, a.nslices);
-  if (kind == 0) hipLaunchKernelGGL(k_conv_first, grid, dim3(256), 0, s, a);
-  else if (kind == 1) {
-    dim3 g16((a.tiles_x * CONV_TW + TW16 - 1) / TW16, a.tiles_y, a.nslices);
-    hipLaunchKernelGGL(k_conv_mid16, g16, dim3(256), 0, s, a);
-  }
-  else {
-    dim3 g16((a.tiles_x * CONV_TW + TW16 - 1) / TW16, a.tiles_y, a.nslices);
-    hipLaunchKernelGGL(k_conv_last, g16, dim3(256), 0, s, a);
-  }
+  dim3 g16(a.tiles_x, a.tiles_y, a.nslices);
+  if (kind == 0) hipLaunchKernelGGL(k_conv_first, g16, dim3(256), 0, s, a);
+  else if (kind == 1) hipLaunchKernelGGL(k_conv_mid16, g16, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_conv_last, g16, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
