@@ -28,6 +28,7 @@ struct CgElemArgs {
   const float2* q;       // q = sum of desc[b].nq partial planes, qstride apart
   int64_t qstride;
   const float* pq;       // [B][npq]
+  float* pq_clear;       // cg_init: zero these [B][npq] partials first (or null)
   const float* rr_cur;   // [B][nrr]
   float* rr_next;        // [B][nrr]
   int* stopped;          // [B]

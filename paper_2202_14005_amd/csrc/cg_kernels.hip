@@ -61,6 +61,9 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_init(CgElemArgs a) {
     a.x[o] = make_float2(0.f, 0.f);
     rr += r.x * r.x + r.y * r.y;
   }
+  // the <p, q> partials of tiles that a schedule never writes must read as zero
+  if (a.pq_clear && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < a.npq; i += CG_THREADS) a.pq_clear[(int64_t)b * a.npq + i] = 0.f;
   const float s = bsum(rr, red);
   if (threadIdx.x == 0) {
     a.rr_next[(int64_t)b * a.nrr + blockIdx.x] = s;

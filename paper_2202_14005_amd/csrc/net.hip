@@ -221,12 +221,16 @@ __global__ void __launch_bounds__(256) k_mse(const SliceDesc* desc, const int* s
   __syncthreads();
   if (threadIdx.x == 0) part[(int64_t)b * nrr + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
-__global__ void k_mse_total(const float* part, int total, float scale, float* loss) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    float s = 0.f;
-    for (int i = 0; i < total; ++i) s += part[i];
-    *loss = s * scale;
-  }
+// loss = scale * sum of the partials, in a fixed order: thread t adds
+// part[t], part[t + 256], ...; fixed butterflies; the 4 wave sums in order.
+__global__ void __launch_bounds__(256) k_mse_total(const float* part, int total, float scale, float* loss) {
+  __shared__ float red[4];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < total; i += 256) s += part[i];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *loss = (((red[0] + red[1]) + red[2]) + red[3]) * scale;
 }
 
 __global__ void k_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
@@ -413,7 +417,7 @@ mrx_status mrx_mse_grad(mrx_plan p, const float* x, const float* ref, float* g, 
                      (const float2*)ref, (float2*)g, part, p->nrr, scale);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && loss) {
-    hipLaunchKernelGGL(k_mse_total, dim3(1), dim3(64), 0, s, part, p->B * p->nrr, scale, loss);
+    hipLaunchKernelGGL(k_mse_total, dim3(1), dim3(256), 0, s, part, p->B * p->nrr, scale, loss);
     e = hipGetLastError();
   }
   return e == hipSuccess ? MRX_OK : hip_fail(e, "mse_grad");

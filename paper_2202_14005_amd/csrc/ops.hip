@@ -101,10 +101,9 @@ mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const floa
   a.pq = pq;
   a.hist = hist;
   a.rr_next = rr[0];
-  // tiles that a schedule never writes must read as zero partials
-  hipError_t e = fill_u32((uint32_t*)pq, 0u, (int64_t)p->B * p->npq, s);
-  if (e != hipSuccess) return hip_fail(e, "cg: clear partials");
-  e = cg_init(a, s);
+  a.pq_clear = pq;  // cg_init also clears the <p, q> partials
+  hipError_t e = cg_init(a, s);
+  a.pq_clear = nullptr;
   if (e != hipSuccess) return hip_fail(e, "cg: init");
   for (int k = 0; k < n_iter; ++k) {
     float* rr_cur = rr[k & 1];
