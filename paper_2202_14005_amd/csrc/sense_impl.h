@@ -493,31 +493,48 @@ k_fwd_col(SenseColArgs a) {
 // ------------------------------------------- adjoint column pass (A^H, H)
 // For each coil: gather sampled rows of the row-pass output into frequency
 // order with the centering sign, inverse transform along H, multiply by
-// conj(S_c) and accumulate over coils.
-template <class Sd, int WT>
-__global__ void __launch_bounds__(Sd::T * WT)
+// conj(S_c) and accumulate over coils.  G groups of T x WT threads take
+// every G-th coil (all groups run the same number of transforms, idle ones
+// on zeros, so every barrier is reached by the whole workgroup); their sums
+// are added through LDS in a fixed order.
+template <class Sd, int WT, int G>
+__global__ void __launch_bounds__(Sd::T * WT * G, 2)
 k_adj_col(SenseColArgs a) {
-  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T, NT = T * WT;
   using L = LdsInterleaved<N, WT>;
-  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 lds[G * L::SIZE];
   __shared__ float2 tw[N];
+  __shared__ float mk[N];
   const int b = a.slices[blockIdx.y];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
   const int W = d.W, tile = blockIdx.x;
   if (tile * WT >= W) return;
-  const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
+  const int lid = threadIdx.x, grp = lid / NT, l2 = lid % NT;
+  const int c = l2 % WT, tc = l2 / WT, col = tile * WT + c;
   const bool valid = col < W;
-  for (int i = lid; i < N; i += T * WT) tw[i] = a.tw[i];
+  float2* xl = lds + grp * L::SIZE;
+  for (int i = lid; i < N; i += NT * G) {
+    tw[i] = a.tw[i];
+    mk[i] = a.mask[d.moff + i];
+  }
   __syncthreads();
   const float scale = rsqrtf((float)N);
   const int64_t plane = (int64_t)N * W;
-  const float* mrow = a.mask + d.moff;
+  // coil-map element (a1(tc, i, r), col): per-lane offset + uniform row part
+  const uint32_t voff = (uint32_t)(tc * W + col) * 8u;
+  auto at = [&](const float2* base, int i, int r) {
+    return (const float2*)((const char*)(base + (T * i + r * Sd::M1) * W) + voff);
+  };
   float2 acc[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) acc[k] = make_float2(0.f, 0.f);
-  for (int coil = 0; coil < d.C; ++coil) {
-    const float2* ic = a.in + d.soff + coil * plane;
+  const int iters = (d.C + G - 1) / G;
+  for (int it = 0; it < iters; ++it) {
+    const int coil = it * G + grp;
+    const bool on = valid && coil < d.C;
+    const int cc = coil < d.C ? coil : 0;
+    const float2* ic = a.in + d.soff + cc * plane;
     float2 v[P];
 #pragma unroll
     for (int i = 0; i < Sd::GFIN; ++i)
@@ -527,24 +544,45 @@ k_adj_col(SenseColArgs a) {
         const int k = (j + N / 2) % N;
         const float sg = (j & 1) ? -scale : scale;
         float2 u = make_float2(0.f, 0.f);
-        if (valid && mrow[k] != 0.f) u = cscale(ic[(int64_t)k * W + col], sg);
+        if (on && mk[k] != 0.f) u = cscale(ic[(int64_t)k * W + col], sg);
         v[i * Sd::NFIN + r] = u;
       }
-    fft_inverse<Sd, L>(v, lds, tw, tc, c);
-    const float2* Sc = a.S + d.soff + coil * plane;
+    fft_inverse<Sd, L>(v, xl, tw, tc, c);
+    if (on) {
+      const float2* Sc = a.S + d.soff + cc * plane;
+#pragma unroll
+      for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+        for (int r = 0; r < Sd::N1; ++r)
+          acc[i * Sd::N1 + r] = cadd(acc[i * Sd::N1 + r], cmulc(*at(Sc, i, r), v[i * Sd::N1 + r]));
+    }
+  }
+  if constexpr (G > 1) {
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
-      for (int r = 0; r < Sd::N1; ++r) {
-        const float2 s = valid ? Sc[(int64_t)Sd::a1(tc, i, r) * W + col] : make_float2(0.f, 0.f);
-        acc[i * Sd::N1 + r] = cadd(acc[i * Sd::N1 + r], cmulc(s, v[i * Sd::N1 + r]));
-      }
+      for (int r = 0; r < Sd::N1; ++r) xl[L::idx(Sd::a1(tc, i, r), c)] = acc[i * Sd::N1 + r];
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+      for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+        for (int r = 0; r < Sd::N1; ++r) {
+          const int id = L::idx(Sd::a1(tc, i, r), c);
+          float2 sm = lds[id];
+#pragma unroll
+          for (int g = 1; g < G; ++g) sm = cadd(sm, lds[g * L::SIZE + id]);
+          acc[i * Sd::N1 + r] = sm;
+        }
+    }
   }
+  if (grp == 0 && valid) {
 #pragma unroll
-  for (int i = 0; i < Sd::G1; ++i)
+    for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
-    for (int r = 0; r < Sd::N1; ++r)
-      if (valid) a.out[d.xoff + (int64_t)Sd::a1(tc, i, r) * W + col] = acc[i * Sd::N1 + r];
+      for (int r = 0; r < Sd::N1; ++r) a.out[d.xoff + (int64_t)Sd::a1(tc, i, r) * W + col] = acc[i * Sd::N1 + r];
+  }
 }
 
 // ----------------------------------------------------- row passes (along W)
@@ -673,10 +711,13 @@ hipError_t launch_fwd_col(const SenseColArgs& a, int maxW, hipStream_t s) {
   hipLaunchKernelGGL((k_fwd_col<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
   return hipGetLastError();
 }
+// The adjoint column pass uses its own tile: 8 columns, two coil groups.
+constexpr int ADJ_WT = 8, ADJ_G = 2;
 template <class Sd, int WT>
 hipError_t launch_adj_col(const SenseColArgs& a, int maxW, hipStream_t s) {
-  dim3 grid((maxW + WT - 1) / WT, a.nslices);
-  hipLaunchKernelGGL((k_adj_col<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
+  (void)WT;
+  dim3 grid((maxW + ADJ_WT - 1) / ADJ_WT, a.nslices);
+  hipLaunchKernelGGL((k_adj_col<Sd, ADJ_WT, ADJ_G>), grid, dim3(Sd::T * ADJ_WT * ADJ_G), 0, s, a);
   return hipGetLastError();
 }
 template <class Sd, int WT>
