@@ -301,7 +301,8 @@ mrx_status mrx_vn_stage_backward(mrx_plan plan, const float* g, const float* x, 
  * plan by timing each on the given stream (synchronises the host): four CG
  * iterations over the plan when its workspace is set (scratch_a is the
  * right-hand side, scratch_b the solution; both image-sized and
- * overwritten), else five normal-operator applications of the group.  The
+ * overwritten), else, and for plans created with MRX_PLAN_VN, five
+ * normal-operator applications of the group (scratch_a in, scratch_b out).  The
  * choice is kept in the plan and in an in-process cache keyed by (H, W, C,
  * number of slices of the group); plans created later with a matching group
  * start from the cached choice. */

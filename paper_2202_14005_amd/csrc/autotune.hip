@@ -15,7 +15,8 @@ using namespace mrx;
 // Each candidate is timed on what it runs in practice: four CG iterations
 // over the whole plan (operator plus CG update, with this group's candidate
 // and the other groups' current choices) when the workspace is set, else
-// five operator applications of the group.
+// (and for variational-network plans, whose stages apply the plain
+// operator) five operator applications of the group.
 extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float* mask, float* a, float* b,
                                         void* stream) {
   if (!p) return fail(MRX_EINVAL, "autotune: null plan");
@@ -24,7 +25,8 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(MRX_EHIP, "autotune: event create");
-  const bool use_cg = p->ws != nullptr;
+  // plans for the variational network use the plain operator, the others CG
+  const bool use_cg = p->ws != nullptr && !(p->flags & MRX_PLAN_VN);
   for (auto& g : p->groups) {
     const ColVariant* best = g.col;
     float best_ms = 1e30f;

@@ -168,31 +168,37 @@ __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
 // Filter gradients of one stage (reverse mode):
 //   dkr_i[d] = -sum_p (u_i[p] Re g[p+d] + e_i[p] Re x[p+d])
 //   dki_i[d] = +sum_p (u_i[p] Im g[p+d] + e_i[p] Im x[p+d])
-// One workgroup per (band of VN_BAND rows, slice); thread t < 121 owns tap t
-// and keeps 24 x 2 accumulators; partials per workgroup.
-__global__ void __launch_bounds__(128) k_vn_kgrad(VnArgs a) {
-  constexpr int RW = 256;  // row-buffer width; output chunk RW - 2R columns
+// One workgroup per (band of VN_KBAND rows, slice), 256 threads: thread t
+// owns tap t % 128 (< 121) for the 12 filters of half t / 128, with 24
+// accumulators; 64-column chunks keep the LDS small (25 KB) so that many
+// workgroups share a CU.  Partials per workgroup, summed by k_vn_reduce.
+constexpr int VN_KBAND = 2;
+constexpr int VKC = 64;  // columns per chunk
+__global__ void __launch_bounds__(256) k_vn_kgrad(VnArgs a) {
+  constexpr int RW = VKC + 2 * VN_R;
+  constexpr int NH = VN_NK / 2;
   __shared__ float2 rowg[VN_KS * RW];
   __shared__ float2 rowx[VN_KS * RW];
-  __shared__ float uv[RW * VN_NK];
-  __shared__ float ev[RW * VN_NK];
+  __shared__ __attribute__((aligned(16))) float uv[VKC * VN_NK];
+  __shared__ __attribute__((aligned(16))) float ev[VKC * VN_NK];
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
   float* part = a.part_k + (int64_t)wg * (VN_NK * VN_TAPS * 2);
   const int b = a.slices[blockIdx.y];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
-  const int tap = threadIdx.x, dy = tap / VN_KS, dx = tap % VN_KS;
-  float ar[VN_NK], ai[VN_NK];
+  const int tap = threadIdx.x & 127, fh = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
+  const int dy = tap / VN_KS, dx = tap % VN_KS;
+  float ar[NH], ai[NH];
 #pragma unroll
-  for (int i = 0; i < VN_NK; ++i) { ar[i] = 0.f; ai[i] = 0.f; }
-  for (int rr = 0; rr < VN_BAND; ++rr) {
-    const int row = blockIdx.x * VN_BAND + rr;
+  for (int i = 0; i < NH; ++i) { ar[i] = 0.f; ai[i] = 0.f; }
+  for (int rr = 0; rr < VN_KBAND; ++rr) {
+    const int row = blockIdx.x * VN_KBAND + rr;
     if (row >= H) break;
-    for (int c0 = 0; c0 < W; c0 += RW - 2 * VN_R) {
-      const int cw = min(RW - 2 * VN_R, W - c0);
+    for (int c0 = 0; c0 < W; c0 += VKC) {
+      const int cw = min(VKC, W - c0);
       __syncthreads();
       // rows row-5 .. row+5 of g and x, columns c0-5 .. c0+cw+4
-      for (int q = threadIdx.x; q < VN_KS * RW; q += 128) {
+      for (int q = threadIdx.x; q < VN_KS * RW; q += 256) {
         const int r = q / RW, c = q % RW;
         const int gy = row + r - VN_R, gx = c0 + c - VN_R;
         float2 gv = make_float2(0.f, 0.f), xv = make_float2(0.f, 0.f);
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(128) k_vn_kgrad(VnArgs a) {
         rowg[q] = gv;
         rowx[q] = xv;
       }
-      for (int q = threadIdx.x; q < cw * VN_NK; q += 128) {
+      for (int q = threadIdx.x; q < cw * VN_NK; q += 256) {
         const int64_t o = (d.xoff + (int64_t)row * W + c0) * VN_NK + q;
         uv[q] = a.u[o];
         ev[q] = a.e[o];
@@ -213,11 +219,17 @@ __global__ void __launch_bounds__(128) k_vn_kgrad(VnArgs a) {
         for (int c = 0; c < cw; ++c) {
           const int tp = dy * RW + c + dx;
           const float2 gv = rowg[tp], xv = rowx[tp];
+          const float4* u4 = (const float4*)&uv[c * VN_NK + fh * NH];
+          const float4* e4 = (const float4*)&ev[c * VN_NK + fh * NH];
 #pragma unroll
-          for (int i = 0; i < VN_NK; ++i) {
-            const float u = uv[c * VN_NK + i], e = ev[c * VN_NK + i];
-            ar[i] = fmaf(u, gv.x, fmaf(e, xv.x, ar[i]));
-            ai[i] = fmaf(u, gv.y, fmaf(e, xv.y, ai[i]));
+          for (int k = 0; k < NH / 4; ++k) {
+            const float4 u = u4[k], e = e4[k];
+            const float us[4] = {u.x, u.y, u.z, u.w}, es[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              ar[4 * k + m] = fmaf(us[m], gv.x, fmaf(es[m], xv.x, ar[4 * k + m]));
+              ai[4 * k + m] = fmaf(us[m], gv.y, fmaf(es[m], xv.y, ai[4 * k + m]));
+            }
           }
         }
       }
@@ -225,9 +237,10 @@ __global__ void __launch_bounds__(128) k_vn_kgrad(VnArgs a) {
   }
   if (tap < VN_TAPS) {
 #pragma unroll
-    for (int i = 0; i < VN_NK; ++i) {
-      part[(i * VN_TAPS + tap) * 2 + 0] = -ar[i];
-      part[(i * VN_TAPS + tap) * 2 + 1] = ai[i];
+    for (int k = 0; k < NH; ++k) {
+      const int i = fh * NH + k;
+      part[(i * VN_TAPS + tap) * 2 + 0] = -ar[k];
+      part[(i * VN_TAPS + tap) * 2 + 1] = ai[k];
     }
   }
 }
@@ -268,13 +281,26 @@ __global__ void __launch_bounds__(768) k_vn_wgrad(VnArgs a) {
   if (t < VN_NK * VN_NW) part[t] = -acc;
 }
 
-// out[i] (+)= sum_s part[s][i], fixed order.
-__global__ void k_vn_reduce(const float* part, int nslots, int nout, float* out, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nout) return;
+// out[i] (+)= sum_s part[s][i] in a fixed order: a block takes 64 entries;
+// its 16 waves sum the slots s = w, w + 16, ... in increasing order, then
+// the 16 wave sums are added in wave order.
+constexpr int VR_WAVES = 16;
+__global__ void __launch_bounds__(64 * VR_WAVES) k_vn_reduce(const float* part, int nslots, int nout, float* out,
+                                                            int accumulate) {
+  __shared__ float red[VR_WAVES][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int k = 0; k < nslots; ++k) s += part[(int64_t)k * nout + i];
-  out[i] = accumulate ? out[i] + s : s;
+  if (i < nout)
+    for (int k = wv; k < nslots; k += VR_WAVES) s += part[(int64_t)k * nout + i];
+  red[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && i < nout) {
+    float t = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < VR_WAVES; ++w) t += red[w][lane];
+    out[i] = accumulate ? out[i] + t : t;
+  }
 }
 
 }  // namespace mrx
@@ -327,7 +353,8 @@ size_t vn_workspace_bytes(mrx_plan_s* p, size_t base) {
   const size_t tiles = (size_t)((p->maxW + VT - 1) / VT) * ((p->maxH + VT - 1) / VT) * p->B;
   p->ws_vn_plam = take(tiles * 4);
   const size_t bands = (size_t)((p->maxH + VN_BAND - 1) / VN_BAND) * p->B;
-  p->ws_vn_pk = take(bands * VN_NK * VN_TAPS * 2 * 4);
+  const size_t kbands = (size_t)((p->maxH + VN_KBAND - 1) / VN_KBAND) * p->B;
+  p->ws_vn_pk = take(kbands * VN_NK * VN_TAPS * 2 * 4);
   p->ws_vn_pw = take(bands * VN_NK * VN_NW * 4);
   return w;
 }
@@ -391,14 +418,14 @@ mrx_status mrx_vn_stage_backward(mrx_plan p, const float* g, const float* x, con
   hipLaunchKernelGGL(k_vn_filter<true>, grid, dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_vn_adjoint<true>, grid, dim3(256), 0, s, a);
   const int bands = (p->maxH + VN_BAND - 1) / VN_BAND;
-  hipLaunchKernelGGL(k_vn_kgrad, dim3(bands, p->B), dim3(128), 0, s, a);
+  const int kbands = (p->maxH + VN_KBAND - 1) / VN_KBAND;
+  hipLaunchKernelGGL(k_vn_kgrad, dim3(kbands, p->B), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_vn_wgrad, dim3(bands, p->B), dim3(768), 0, s, a);
   const int nk = VN_NK * VN_TAPS * 2, nw = VN_NK * VN_NW;
-  hipLaunchKernelGGL(k_vn_reduce, dim3((nk + 255) / 256), dim3(256), 0, s, a.part_k, bands * p->B, nk, g_k,
-                     accumulate);
-  hipLaunchKernelGGL(k_vn_reduce, dim3((nw + 255) / 256), dim3(256), 0, s, a.part_w, bands * p->B, nw, g_w,
-                     accumulate);
-  hipLaunchKernelGGL(k_vn_reduce, dim3(1), dim3(64), 0, s, a.part_lam, tiles, 1, g_lam, accumulate);
+  const dim3 rb(64 * VR_WAVES);
+  hipLaunchKernelGGL(k_vn_reduce, dim3((nk + 63) / 64), rb, 0, s, a.part_k, kbands * p->B, nk, g_k, accumulate);
+  hipLaunchKernelGGL(k_vn_reduce, dim3((nw + 63) / 64), rb, 0, s, a.part_w, bands * p->B, nw, g_w, accumulate);
+  hipLaunchKernelGGL(k_vn_reduce, dim3(1), rb, 0, s, a.part_lam, tiles, 1, g_lam, accumulate);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MRX_OK : hip_fail(e, "vn_stage_backward");
 }
