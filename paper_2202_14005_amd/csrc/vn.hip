@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
 // and, in the reverse mode, per-workgroup partials of Re<g, qx - aHy>.
 template <bool REV>
 __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
-  __shared__ float tv[VH * VH * VN_NK];
+  __shared__ __attribute__((aligned(16))) float tv[VH * VH * VN_NK];  // [pixel][24]
   __shared__ float red[4];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
       const int gy = y0 + p / VH - VN_R, gx = x0 + p % VH - VN_R;
       float val = 0.f;
       if (gy >= 0 && gy < H && gx >= 0 && gx < W) val = v[(d.xoff + (int64_t)gy * W + gx) * VN_NK + i];
-      tv[i * VH * VH + p] = val;
+      tv[q] = val;
     }
     __syncthreads();
     const int ly = threadIdx.x / VT, lx = threadIdx.x % VT;
@@ -131,12 +131,17 @@ __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
         const int tap = dy * VN_KS + dx;
         const int tp = (ly + 2 * VN_R - dy) * VH + lx + 2 * VN_R - dx;
         const float2* kt = a.kt + tap * VN_NK;
+        const float4* t4 = (const float4*)&tv[tp * VN_NK];  // the 24 values of pixel tp: 6 reads
 #pragma unroll
-        for (int i = 0; i < VN_NK; ++i) {
-          const float vv = tv[i * VH * VH + tp];
-          const float2 kk = kt[i];
-          rr = fmaf(kk.x, vv, rr);
-          ri = fmaf(-kk.y, vv, ri);
+        for (int k = 0; k < VN_NK / 4; ++k) {
+          const float4 v4 = t4[k];
+          const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const float2 kk = kt[4 * k + m];
+            rr = fmaf(kk.x, vs[m], rr);
+            ri = fmaf(-kk.y, vs[m], ri);
+          }
         }
       }
     }
