@@ -29,7 +29,7 @@ mrx_status hip_fail(hipError_t e, const char* what) {
   return MRX_EHIP;
 }
 
-KernelTimer::KernelTimer(mrx_plan_s* p, int kid, hipStream_t s) : p_(p), s_(s) {
+KernelTimer::KernelTimer(mrx_plan_s* p, int kid, hipStream_t s) : s_(s) {
   if (!p->ktime || kid < 0) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;

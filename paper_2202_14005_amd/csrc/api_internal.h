@@ -76,7 +76,6 @@ class KernelTimer {
   ~KernelTimer();
 
  private:
-  mrx_plan_s* p_;
   hipStream_t s_;
   hipEvent_t b_ = nullptr;
 };

@@ -55,13 +55,12 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
       bool ok = true;
       float ms = 1e30f;
       for (int trial = 0; trial < 5 && ok; ++trial) {
-        hipEventRecord(e0, s);
+        ok = hipEventRecord(e0, s) == hipSuccess;
         for (int rep = 0; rep < 2; ++rep) ok = ok && run();
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
+        ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
         float t = 0.f;
-        hipEventElapsedTime(&t, e0, e1);
-        ms = t < ms ? t : ms;
+        ok = ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+        if (ok) ms = t < ms ? t : ms;
       }
       if (ok && ms < best_ms) { best_ms = ms; best = v; }
     }
@@ -69,8 +68,8 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[{g.H, g.W, g.maxC, (int)g.slices.size()}] = best->name;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   // the timing solves may have raised status bits; they are not the caller's
   if (use_cg && clear_status(p, s) != hipSuccess) return fail(MRX_EHIP, "autotune: status reset");
   if (hipGetLastError() != hipSuccess) return fail(MRX_EHIP, "autotune: launch failed");
