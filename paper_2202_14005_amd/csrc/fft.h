@@ -13,21 +13,107 @@
 // with.  T threads cooperate on one transform; at level j each thread owns
 // (N / N_j) / T complete sub-transforms of length N_j held in registers.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 
 namespace mrx {
 
-// x * exp(-/+ 2 pi i e / R); e is a compile-time constant after unrolling.
-template <int R, bool INV>
-__device__ __forceinline__ float2 twc(float2 x, int e) {
-  e %= R;
-  if (e == 0) return x;
-  if (2 * e == R) return cneg(x);
-  if (4 * e == R) return INV ? cmul_pi(x) : cmul_mi(x);
-  if (4 * e == 3 * R) return INV ? cmul_mi(x) : cmul_pi(x);
-  static constexpr TwTab<R> tab{};
-  const float c = tab.c[e], s = tab.s[e];
-  return cmul(x, make_float2(c, INV ? s : -s));
+template <int I>
+using ic = std::integral_constant<int, I>;
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(ic<B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Input multipliers of the DFT codelets.  A codelet forms m_n * x_n for each
+// input; where such a product meets the first addition of a butterfly it is
+// folded into fused multiply-adds (see bfly).  Cheap kinds (1, -1, +-i) cost
+// no multiplication.
+struct MOne {  // 1
+  static constexpr bool cheap = true;
+  __device__ __forceinline__ float2 mul(float2 x) const { return x; }
+};
+struct MNeg {  // -1
+  static constexpr bool cheap = true;
+  __device__ __forceinline__ float2 mul(float2 x) const { return cneg(x); }
+};
+template <bool POS>
+struct MI {  // +i (POS) or -i
+  static constexpr bool cheap = true;
+  __device__ __forceinline__ float2 mul(float2 x) const { return POS ? cmul_pi(x) : cmul_mi(x); }
+};
+struct MRe {  // real scale
+  static constexpr bool cheap = false;
+  float s;
+  __device__ __forceinline__ float2 mul(float2 x) const { return cscale(x, s); }
+  __device__ __forceinline__ float2 madd(float2 u, float2 z) const {
+    return make_float2(__builtin_fmaf(z.x, s, u.x), __builtin_fmaf(z.y, s, u.y));
+  }
+};
+struct MCw {  // complex w
+  static constexpr bool cheap = false;
+  float2 w;
+  __device__ __forceinline__ float2 mul(float2 x) const { return cmul(x, w); }
+  __device__ __forceinline__ float2 madd(float2 u, float2 z) const {
+    return make_float2(__builtin_fmaf(z.x, w.x, __builtin_fmaf(-z.y, w.y, u.x)),
+                       __builtin_fmaf(z.x, w.y, __builtin_fmaf(z.y, w.x, u.y)));
+  }
+};
+struct MCwc {  // conj(w)
+  static constexpr bool cheap = false;
+  float2 w;
+  __device__ __forceinline__ float2 mul(float2 x) const { return cmulc(w, x); }
+  __device__ __forceinline__ float2 madd(float2 u, float2 z) const {
+    return make_float2(__builtin_fmaf(z.x, w.x, __builtin_fmaf(z.y, w.y, u.x)),
+                       __builtin_fmaf(z.y, w.x, __builtin_fmaf(-z.x, w.y, u.y)));
+  }
+};
+struct OneMul {  // every input multiplier 1
+  template <class I>
+  __device__ __forceinline__ MOne operator()(I) const { return {}; }
+};
+
+// s = a x + b z, d = a x - b z.  With one product a fused chain gives s
+// (u + b z in four multiply-adds on u = a x) and d = 2u - s takes two more,
+// instead of a complex multiply (four) and two complex additions (four).
+template <class A, class B>
+__device__ __forceinline__ void bfly(float2 x, A a, float2 z, B b, float2& s, float2& d) {
+  if constexpr (A::cheap && B::cheap) {
+    const float2 u = a.mul(x), y = b.mul(z);
+    s = cadd(u, y);
+    d = csub(u, y);
+  } else if constexpr (!B::cheap) {
+    const float2 u = a.mul(x);
+    s = b.madd(u, z);
+    d = make_float2(__builtin_fmaf(2.f, u.x, -s.x), __builtin_fmaf(2.f, u.y, -s.y));
+  } else {
+    const float2 y = b.mul(z);
+    s = a.madd(y, x);
+    d = make_float2(__builtin_fmaf(-2.f, y.x, s.x), __builtin_fmaf(-2.f, y.y, s.y));
+  }
+}
+
+// Multiplier exp(-/+ 2 pi i E / R) for a compile-time exponent.
+template <int R, bool INV, int E>
+__device__ __forceinline__ auto twm() {
+  constexpr int e = E % R;
+  if constexpr (e == 0) {
+    return MOne{};
+  } else if constexpr (2 * e == R) {
+    return MNeg{};
+  } else if constexpr (4 * e == R) {
+    return MI<INV>{};
+  } else if constexpr (4 * e == 3 * R) {
+    return MI<!INV>{};
+  } else {
+    constexpr TwTab<R> tab{};
+    return MCw{make_float2(tab.c[e], INV ? tab.s[e] : -tab.s[e])};
+  }
 }
 
 template <int R>
@@ -35,29 +121,36 @@ constexpr int first_factor() {
   return (R % 4 == 0) ? 4 : (R % 2 == 0) ? 2 : (R % 3 == 0) ? 3 : (R % 5 == 0) ? 5 : R;
 }
 
-// In-register DFT of length R on v[0..R-1], natural order in and out.
-// Forward: X[k] = sum_n x[n] exp(-2 pi i n k / R); INV: exp(+...), unscaled.
-template <int R, bool INV>
-__device__ __forceinline__ void dft(float2* v) {
+// In-register DFT of length R of the inputs m(n) * v[n], natural order in
+// and out: X[k] = sum_n m(n) v[n] exp(-/+ 2 pi i n k / R) (INV: +, unscaled).
+// m(ic<n>) gives input n's multiplier.  Composite R = R1 * R2 with
+// n = R2 n1 + n2, k = k1 + R1 k2: R2 DFTs of length R1 over n1, then R1 of
+// length R2 over n2 whose inputs carry the twiddles exp(-/+ 2 pi i n2 k1 / R).
+template <int R, bool INV, class M>
+__device__ __forceinline__ void dft_in(float2* v, const M& m) {
   if constexpr (R == 1) {
-    return;
+    v[0] = m(ic<0>{}).mul(v[0]);
   } else if constexpr (R == 2) {
-    float2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
+    float2 a, b;
+    bfly(v[0], m(ic<0>{}), v[1], m(ic<1>{}), a, b);
+    v[0] = a;
+    v[1] = b;
   } else if constexpr (R == 3) {
     constexpr float s3 = 0.86602540378443864676f;
-    float2 t1 = cadd(v[1], v[2]);
-    float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
-    float2 t3 = cscale(csub(v[1], v[2]), s3);
-    v[0] = cadd(v[0], t1);
-    float2 it3 = INV ? cmul_pi(t3) : cmul_mi(t3);
+    const float2 x0 = m(ic<0>{}).mul(v[0]);
+    float2 t1, d;
+    bfly(v[1], m(ic<1>{}), v[2], m(ic<2>{}), t1, d);
+    const float2 t2 = make_float2(x0.x - 0.5f * t1.x, x0.y - 0.5f * t1.y);
+    const float2 t3 = cscale(d, s3);
+    v[0] = cadd(x0, t1);
+    const float2 it3 = INV ? cmul_pi(t3) : cmul_mi(t3);
     v[1] = cadd(t2, it3);
     v[2] = csub(t2, it3);
   } else if constexpr (R == 4) {
-    float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-    float2 c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
-    float2 id = INV ? cmul_pi(d) : cmul_mi(d);
+    float2 a, b, c, d;
+    bfly(v[0], m(ic<0>{}), v[2], m(ic<2>{}), a, b);
+    bfly(v[1], m(ic<1>{}), v[3], m(ic<3>{}), c, d);
+    const float2 id = INV ? cmul_pi(d) : cmul_mi(d);
     v[0] = cadd(a, c);
     v[2] = csub(a, c);
     v[1] = cadd(b, id);
@@ -67,45 +160,51 @@ __device__ __forceinline__ void dft(float2* v) {
     constexpr float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
     constexpr float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
     constexpr float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
-    float2 x0 = v[0];
-    float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-    float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-    float2 a1 = make_float2(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
-    float2 a2 = make_float2(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
-    float2 b1 = make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y);
-    float2 b2 = make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y);
-    float2 ib1 = INV ? cmul_pi(b1) : cmul_mi(b1);
-    float2 ib2 = INV ? cmul_pi(b2) : cmul_mi(b2);
+    const float2 x0 = m(ic<0>{}).mul(v[0]);
+    float2 t1, t2, t3, t4;
+    bfly(v[1], m(ic<1>{}), v[4], m(ic<4>{}), t1, t3);
+    bfly(v[2], m(ic<2>{}), v[3], m(ic<3>{}), t2, t4);
+    const float2 a1 = make_float2(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+    const float2 a2 = make_float2(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+    const float2 b1 = make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y);
+    const float2 b2 = make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y);
+    const float2 ib1 = INV ? cmul_pi(b1) : cmul_mi(b1);
+    const float2 ib2 = INV ? cmul_pi(b2) : cmul_mi(b2);
     v[0] = cadd(x0, cadd(t1, t2));
     v[1] = cadd(a1, ib1);
     v[4] = csub(a1, ib1);
     v[2] = cadd(a2, ib2);
     v[3] = csub(a2, ib2);
   } else {
-    // R = R1 * R2 with n = R2 n1 + n2, k = k1 + R1 k2.
     constexpr int R1 = first_factor<R>();
     constexpr int R2 = R / R1;
     static_assert(R1 > 1 && R1 < R, "length must factor into 2, 3, 4, 5");
     float2 a[R];
-#pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) {
+    static_for<0, R2>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
       float2 t[R1];
 #pragma unroll
       for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
-      dft<R1, INV>(t);
+      dft_in<R1, INV>(t, [&](auto n1c) { return m(ic<R2 * decltype(n1c)::value + n2>{}); });
 #pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) a[k1 * R2 + n2] = twc<R, INV>(t[k1], n2 * k1);
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) {
+      for (int k1 = 0; k1 < R1; ++k1) a[k1 * R2 + n2] = t[k1];
+    });
+    static_for<0, R1>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
       float2 t[R2];
 #pragma unroll
       for (int n2 = 0; n2 < R2; ++n2) t[n2] = a[k1 * R2 + n2];
-      dft<R2, INV>(t);
+      dft_in<R2, INV>(t, [](auto n2c) { return twm<R, INV, decltype(n2c)::value * k1>(); });
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
-    }
+    });
   }
+}
+
+// In-register DFT of length R on v[0..R-1], natural order in and out.
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* v) {
+  dft_in<R, INV>(v, OneMul{});
 }
 
 // Static description of one decomposition N = N1 * N2 * N3 over T threads.
@@ -233,13 +332,36 @@ __device__ __forceinline__ void fft_forward(float2* v, float2* lds, const float2
   }
 }
 
+// Scale of the final-level slots for fft_inverse: none, or a real factor
+// per frequency read from a table (the sampling mask of the normal
+// operator), applied inside the first codelet.
+struct NoScale {
+  static constexpr bool on = false;
+  const float* tab;
+};
+struct FreqScale {
+  static constexpr bool on = true;
+  const float* tab;
+};
+
 // Exact adjoint of fft_forward (unscaled inverse): final-level layout in,
-// level-1 layout out.
-template <class S, class L, class Sync = BlockSync>
-__device__ __forceinline__ void fft_inverse(float2* v, float2* lds, const float2* tw, int tc, int c) {
+// level-1 layout out.  With FreqScale the input at frequency k is first
+// multiplied by sc.tab[k].
+template <class S, class L, class Sync = BlockSync, class Sc = NoScale>
+__device__ __forceinline__ void fft_inverse(float2* v, float2* lds, const float2* tw, int tc, int c,
+                                            Sc sc = Sc{nullptr}) {
+  // first codelet of the final level, with the per-frequency scale folded in
+  auto fin = [&](int i) {
+    if constexpr (Sc::on) {
+      dft_in<S::NFIN, true>(v + i * S::NFIN,
+                            [&](auto rc) { return MRe{sc.tab[S::freq(tc, i, decltype(rc)::value)]}; });
+    } else {
+      dft<S::NFIN, true>(v + i * S::NFIN);
+    }
+  };
   if constexpr (S::LEVELS == 3) {
 #pragma unroll
-    for (int i = 0; i < S::G3; ++i) dft<S::N3, true>(v + i * S::N3);
+    for (int i = 0; i < S::G3; ++i) fin(i);
     Sync::sync();
 #pragma unroll
     for (int i = 0; i < S::G3; ++i)
@@ -253,12 +375,19 @@ __device__ __forceinline__ void fft_inverse(float2* v, float2* lds, const float2
 #pragma unroll
     for (int i = 0; i < S::G2; ++i) {
       const int n3 = (tc + S::T * i) % S::N3;
+      float2 w[S::N2];
 #pragma unroll
-      for (int r = 1; r < S::N2; ++r) v[i * S::N2 + r] = cmulc(tw[S::N1 * r * n3], v[i * S::N2 + r]);
+      for (int r = 1; r < S::N2; ++r) w[r] = tw[S::N1 * r * n3];
+      dft_in<S::N2, true>(v + i * S::N2, [&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        if constexpr (r == 0) return MOne{};
+        else return MCwc{w[r]};
+      });
     }
-  }
+  } else {
 #pragma unroll
-  for (int i = 0; i < S::G2; ++i) dft<S::N2, true>(v + i * S::N2);
+    for (int i = 0; i < S::G2; ++i) fin(i);
+  }
   Sync::sync();
 #pragma unroll
   for (int i = 0; i < S::G2; ++i)
@@ -272,9 +401,14 @@ __device__ __forceinline__ void fft_inverse(float2* v, float2* lds, const float2
 #pragma unroll
   for (int i = 0; i < S::G1; ++i) {
     const int g = tc + S::T * i;
+    float2 w[S::N1];
 #pragma unroll
-    for (int r = 1; r < S::N1; ++r) v[i * S::N1 + r] = cmulc(tw[g * r], v[i * S::N1 + r]);
-    dft<S::N1, true>(v + i * S::N1);
+    for (int r = 1; r < S::N1; ++r) w[r] = tw[g * r];
+    dft_in<S::N1, true>(v + i * S::N1, [&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      if constexpr (r == 0) return MOne{};
+      else return MCwc{w[r]};
+    });
   }
 }
 

@@ -15,6 +15,27 @@ __device__ __forceinline__ float2 ld_stream(const float2* p) {
   return __builtin_bit_cast(float2, v);
 }
 
+// Raw buffer access to one plane: a scalar descriptor (base and extent in
+// bytes), a per-lane byte offset and a wave-uniform byte offset, so that a
+// load or store costs no vector address arithmetic.  Offsets at or past the
+// extent read zero and drop stores (the hardware's range check).
+struct BufPlane {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ BufPlane(const void* base, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000)) {}
+  __device__ __forceinline__ float2 ld(uint32_t voff, uint32_t soff) const {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  }
+  // non-temporal (second read of a coil map within a workgroup)
+  __device__ __forceinline__ float2 ld_nt(uint32_t voff, uint32_t soff) const {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 2));
+  }
+  __device__ __forceinline__ void st(float2 v, uint32_t voff, uint32_t soff) const {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, 0);
+  }
+};
+
 // Deterministic fixed-order sum of n floats by one wavefront: lane l adds
 // elements l, l+64, ... in order, then a fixed butterfly over lanes.
 __device__ __forceinline__ float wave_sum_fixed(const float* a, int n, int lane) {
@@ -84,16 +105,15 @@ k_normal(NormalArgs a) {
   const int l2 = lid % NT;
   const int c = l2 % WT, tc = l2 / WT;
   const int col = tile * WT + c;
-  // element (a1(tc, i, r), col) of a plane with row stride W: a per-lane byte
-  // offset plus a wave-uniform part, so that every load and store of the
-  // transform addresses a scalar base with one shared 32-bit vector offset
-  const uint32_t voff = (uint32_t)(tc * W + col) * 8u;
-  auto at = [&](auto* base, int i, int r) {
-    using E = std::remove_pointer_t<decltype(base)>;
-    using B = std::conditional_t<std::is_const_v<E>, const char, char>;
-    return (E*)((B*)(base + (T * i + r * Sd::M1) * W) + voff);
-  };
   const bool valid = col < W;
+  // element (a1(tc, i, r), col) of a plane with row stride W: one per-lane
+  // byte offset and a wave-uniform one per (i, r).  Lanes past the last
+  // column (a ragged tile) read column W - 1 instead: columns transform
+  // independently, so their results are only left unstored and out of the
+  // dot product, and every load stays unpredicated.
+  const uint32_t voff = (uint32_t)(tc * W + (valid ? col : W - 1)) * 8u;
+  auto so = [&](int i, int r) { return (uint32_t)((T * i + r * Sd::M1) * W) * 8u; };
+  const uint32_t pbytes = (uint32_t)N * (uint32_t)W * 8u;
   const bool cg = a.mode == 1;
   if (cg && a.stopped[b]) return;
   float2* xl = lds + grp * L::SIZE;
@@ -113,18 +133,17 @@ k_normal(NormalArgs a) {
   }
   __syncthreads();
 
-  const float2* pbase = a.pin + d.xoff;
+  const BufPlane pin(a.pin + d.xoff, pbytes);
   float2 p[P];
   if (cg && a.iter > 0) {
     const float beta = sc[0];
-    const float2* rbase = a.r + d.xoff;
-    float2* pobase = a.pout + d.xoff;
+    const BufPlane rin(a.r + d.xoff, pbytes), pout(a.pout + d.xoff, pbytes);
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
-        float2 pv = valid ? *at(pbase, i, r) : make_float2(0.f, 0.f);
-        float2 rv = valid ? *at(rbase, i, r) : make_float2(0.f, 0.f);
+        float2 pv = pin.ld(voff, so(i, r));
+        const float2 rv = rin.ld(voff, so(i, r));
         pv = make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
         p[i * Sd::N1 + r] = pv;
       }
@@ -137,15 +156,13 @@ k_normal(NormalArgs a) {
 #pragma unroll
       for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
-        for (int r = 0; r < Sd::N1; ++r) *at(pobase, i, r) = p[i * Sd::N1 + r];
+        for (int r = 0; r < Sd::N1; ++r) pout.st(p[i * Sd::N1 + r], voff, so(i, r));
     }
   } else {
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
-      for (int r = 0; r < Sd::N1; ++r) {
-        p[i * Sd::N1 + r] = valid ? *at(pbase, i, r) : make_float2(0.f, 0.f);
-      }
+      for (int r = 0; r < Sd::N1; ++r) p[i * Sd::N1 + r] = pin.ld(voff, so(i, r));
   }
 
 
@@ -158,27 +175,22 @@ k_normal(NormalArgs a) {
   const int iters = (c_end - c_begin + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
     const int coil = c_begin + it * G + grp;
-    const bool on = valid && coil < c_end;
-    const float2* Sc = Sb + (int64_t)(coil < c_end ? coil : c_begin) * plane;
+    const bool on = coil < c_end;  // wave-uniform: idle groups run on a real coil's values
+    const BufPlane Sc(Sb + (int64_t)(on ? coil : c_begin) * plane, pbytes);
     float2 v[P];
     float2 sk[KS ? P : 1];
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
-        const float2 s = on ? *at(Sc, i, r) : make_float2(0.f, 0.f);
+        const float2 s = Sc.ld(voff, so(i, r));
         if constexpr (KS) sk[i * Sd::N1 + r] = s;
         v[i * Sd::N1 + r] = cmul(s, p[i * Sd::N1 + r]);
       }
     fft_forward<Sd, L>(v, xl, tw, tc, c);
-#pragma unroll
-    for (int i = 0; i < Sd::GFIN; ++i)
-#pragma unroll
-      for (int r = 0; r < Sd::NFIN; ++r) {
-        const float m = mk[Sd::freq(tc, i, r)];
-        v[i * Sd::NFIN + r] = cscale(v[i * Sd::NFIN + r], m);
-      }
-    fft_inverse<Sd, L>(v, xl, tw, tc, c);
+    // the mask (with the 1/N of the two unnormalised transforms) scales the
+    // spectrum inside the inverse transform's first codelet
+    fft_inverse<Sd, L, BlockSync, FreqScale>(v, xl, tw, tc, c, FreqScale{mk});
     if (on) {
 #pragma unroll
       for (int i = 0; i < Sd::G1; ++i)
@@ -187,7 +199,7 @@ k_normal(NormalArgs a) {
           const int k = i * Sd::N1 + r;
           float2 s;
           if constexpr (KS) s = sk[k];
-          else s = ld_stream(at(Sc, i, r));
+          else s = Sc.ld_nt(voff, so(i, r));
           acc[k] = cadd(acc[k], cmulc(s, v[k]));
         }
     }
@@ -218,7 +230,7 @@ k_normal(NormalArgs a) {
   const float lam = (a.lam && ks == 0) ? a.lam[b] : 0.f;
   float dot = 0.f;
   if (grp == 0) {
-    float2* qbase = a.qout + (int64_t)ks * a.qstride + d.xoff;
+    const BufPlane qout(a.qout + (int64_t)ks * a.qstride + d.xoff, pbytes);
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
@@ -226,8 +238,9 @@ k_normal(NormalArgs a) {
         const int k = i * Sd::N1 + r;
         const float2 q = make_float2(acc[k].x + lam * p[k].x, acc[k].y + lam * p[k].y);
         dot += p[k].x * q.x + p[k].y * q.y;
-        if (valid) *at(qbase, i, r) = q;
+        if (valid) qout.st(q, voff, so(i, r));
       }
+    if (!valid) dot = 0.f;
   }
   if (cg) {
     const float s = block_sum_fixed(dot, red);
@@ -362,14 +375,9 @@ k_normal_wl(NormalArgs a) {
         v[k] = cmul(sv[k], plt[(T * i + Sd::M1 * r) * CW]);
       }
     fft_forward<Sd, L, WaveSync>(v, xl, tw, tc, c);
-#pragma unroll
-    for (int i = 0; i < Sd::GFIN; ++i)
-#pragma unroll
-      for (int r = 0; r < Sd::NFIN; ++r) {
-        const float m = mk[Sd::freq(tc, i, r)];
-        v[i * Sd::NFIN + r] = cscale(v[i * Sd::NFIN + r], m);
-      }
-    fft_inverse<Sd, L, WaveSync>(v, xl, tw, tc, c);
+    // the mask (with the 1/N of the two unnormalised transforms) scales the
+    // spectrum inside the inverse transform's first codelet
+    fft_inverse<Sd, L, WaveSync, FreqScale>(v, xl, tw, tc, c, FreqScale{mk});
     // the conjugate multiply re-reads this coil's values (non-temporal; an
     // L2 hit)
     const auto rs = plane_rsrc(coil);
