@@ -6,6 +6,7 @@ namespace mrx {
 
 constexpr int CG_THREADS = 256;
 constexpr int CG_EPB = 512;   // elements per block and slice
+constexpr int CG_QPARTS_MAX = 4;  // partial q planes k_cg_update adds (the normal operator's largest coil split)
 
 // per-slice status bits (same values as the public MRX_FLAG_* macros)
 constexpr uint32_t FLAG_NONFINITE = 1u;

@@ -41,6 +41,32 @@ __device__ __forceinline__ float psum(const float* a, int n) {
   return t;
 }
 
+// psum of two arrays at once (one pass of loads and barriers for both).
+__device__ __forceinline__ float2 psum2(const float* a, int na, const float* b, int nb) {
+  __shared__ float tmp[2][CG_THREADS / 64];
+  float s = 0.f, t = 0.f;
+  for (int i = threadIdx.x; i < na; i += CG_THREADS) s += a[i];
+  for (int i = threadIdx.x; i < nb; i += CG_THREADS) t += b[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    t += __shfl_xor(t, off, 64);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    tmp[0][threadIdx.x >> 6] = s;
+    tmp[1][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+  float u = 0.f, v = 0.f;
+#pragma unroll
+  for (int w = 0; w < CG_THREADS / 64; ++w) {
+    u += tmp[0][w];
+    v += tmp[1][w];
+  }
+  return make_float2(u, v);
+}
+
 // r = aHy + lambda z, p = r, x = 0; partials of <r, r>.
 __global__ void __launch_bounds__(CG_THREADS) k_cg_init(CgElemArgs a) {
   __shared__ float red[CG_THREADS / 64];
@@ -80,8 +106,10 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_update(CgElemArgs a) {
   const int64_t base = (int64_t)blockIdx.x * CG_EPB;
   // all of a thread's loads are issued first (one memory latency per block,
   // overlapping the reductions that give alpha)
+  // (the further partial planes of a coil split included: the bound on
+  // their count makes every load a straight-line one)
   constexpr int PER = CG_EPB / CG_THREADS;
-  float2 rv[PER], pv[PER], qv[PER], xv[PER];
+  float2 rv[PER], pv[PER], qv[PER], xv[PER], qe[CG_QPARTS_MAX - 1][PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int64_t i = base + threadIdx.x + j * CG_THREADS;
@@ -90,17 +118,18 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_update(CgElemArgs a) {
     pv[j] = a.p[o];
     qv[j] = a.q[o];
     xv[j] = a.x[o];
-  }
-  if (d.nq > 1) {
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int64_t i = base + threadIdx.x + j * CG_THREADS;
-      const int64_t o = d.xoff + (i < n ? i : 0);
-      for (int k = 1; k < d.nq; ++k) qv[j] = cadd(qv[j], a.q[k * a.qstride + o]);
-    }
+    for (int k = 1; k < CG_QPARTS_MAX; ++k)
+      if (k < d.nq) qe[k - 1][j] = a.q[k * a.qstride + o];
   }
-  const float rho = psum(a.rr_cur + (int64_t)b * a.nrr, a.nrr);
-  const float pq = psum(a.pq + (int64_t)b * a.npq, a.npq);
+#pragma unroll
+  for (int k = 1; k < CG_QPARTS_MAX; ++k)
+    if (k < d.nq) {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) qv[j] = cadd(qv[j], qe[k - 1][j]);
+    }
+  const float2 rp = psum2(a.rr_cur + (int64_t)b * a.nrr, a.nrr, a.pq + (int64_t)b * a.npq, a.npq);
+  const float rho = rp.x, pq = rp.y;
   bool stop = a.stopped[b] != 0;
   const bool bad = !(pq > 0.f) || !(rho > 0.f) || !isfinite(rho / pq);
   if (!stop && bad) {

@@ -6,6 +6,8 @@
 
 namespace mrx {
 
+static_assert(KSPL_MAX <= CG_QPARTS_MAX, "k_cg_update must add every partial plane");
+
 __global__ void k_fill_u32(uint32_t* d, uint32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = v;
