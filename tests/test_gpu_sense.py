@@ -224,6 +224,37 @@ def test_every_schedule_normal_and_cg(H, W, C):
         assert e_x < CG_TOL, name
 
 
+@pytest.mark.parametrize("H,W,C", [(320, 24, 1), (320, 40, 2), (320, 24, 64), (128, 24, 64), (384, 40, 1)])
+def test_every_schedule_coil_count_edges(H, W, C):
+    """The smallest and largest coil counts a plan accepts (1, 2 and 64)
+    under every column schedule of a length: coil splits and coil groups
+    that get no coil at all (C < split count) and splits of 21-22 coils; the
+    forward and adjoint operators at the same counts."""
+    from paper_2202_14005_amd import ops
+    B = 2
+    d = inputs([1800 + i for i in range(B)], H, W, C)
+    y_ref = osense.sense_fwd(d["x"], d["S"], d["mask"])
+    y = osense.measure(d["x"], d["S"], d["mask"], d["noise"])
+    aHy = osense.sense_adj(y, d["S"], d["mask"]).astype(np.complex64)
+    q_ref = osense.sense_normal(d["x"], d["S"], d["mask"], 0.1)
+    x_ref, _ = ocg.cg_dc(aHy, None, d["S"], d["mask"], np.full(B, 0.05), 10)
+    S, m = dev(d["S"]), dev(d["mask"])
+    plan = Plan(H, W, C, B=B)
+    assert rel(host(plan.sense_fwd(dev(d["x"]), S, m)), y_ref) < OP_TOL
+    a_ref = osense.sense_adj(y.astype(np.complex64), d["S"], d["mask"])
+    assert rel(host(plan.sense_adj(dev(y.astype(np.complex64)), S, m)), a_ref) < OP_TOL
+    names = ops.schedules(H)
+    assert names
+    for name in names:
+        plan = Plan(H, W, C, B=B)
+        plan.set_schedule(H, name)
+        e_q = rel(host(plan.sense_normal(dev(d["x"]), S, m, 0.1)), q_ref)
+        e_x = rel(host(plan.cg_dc(dev(aHy), S, m, 0.05, 10)), x_ref)
+        print(f"C={C} {name}: normal {e_q:.2e} cg {e_x:.2e}")
+        assert e_q < OP_TOL, name
+        assert e_x < CG_TOL, name
+
+
 def test_kernel_timing_records_each_launch():
     """Per-launch event timing: one record per normal-operator launch and CG
     update of a solve, none once switched off; the solve's result is the
