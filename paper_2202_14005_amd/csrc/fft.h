@@ -246,11 +246,25 @@ struct Sched {
   static constexpr int NFIN = (LEVELS == 3) ? N3 : N2;
 };
 
-// Synchronisation between the LDS exchanges of a transform.  BlockSync: the T
-// threads of a transform span several wavefronts.  WaveSync: they all belong
-// to one wavefront, whose LDS operations execute in issue order, so only the
-// compiler has to be kept from moving LDS accesses across the exchange.
+// Synchronisation between the LDS exchanges of a transform: pre() before a
+// thread writes its values of an exchange, sync() between those writes and
+// the reads of the next level.  BlockSync: the T threads of a transform span
+// several wavefronts.  WaveSync: they all belong to one wavefront, whose LDS
+// operations execute in issue order, so only the compiler has to be kept
+// from moving LDS accesses across the exchange.  BlockSyncPost: as
+// BlockSync without the barrier before the writes.  Every exchange writes
+// exactly the LDS slots that the same thread read last (level 2 and the
+// final level of one transform, the final level of a forward and the first
+// of the inverse that follows it, the first level of an inverse and of a
+// next forward on the same tile), and each slot is read by one thread only,
+// so no other thread can still need a slot when it is overwritten; valid
+// when the tile region sees nothing but a chain of transforms in between.
 struct BlockSync {
+  __device__ static __forceinline__ void pre() { __syncthreads(); }
+  __device__ static __forceinline__ void sync() { __syncthreads(); }
+};
+struct BlockSyncPost {
+  __device__ static __forceinline__ void pre() {}
   __device__ static __forceinline__ void sync() { __syncthreads(); }
 };
 struct WaveSync {
@@ -259,6 +273,7 @@ struct WaveSync {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  __device__ static __forceinline__ void pre() { sync(); }
 };
 
 // LDS layouts: element (address a, transform c) of a tile of WT transforms.
@@ -296,7 +311,7 @@ __device__ __forceinline__ void fft_forward(float2* v, float2* lds, const float2
 #pragma unroll
     for (int r = 1; r < S::N1; ++r) v[i * S::N1 + r] = cmul(v[i * S::N1 + r], tw[g * r]);
   }
-  Sync::sync();
+  Sync::pre();
 #pragma unroll
   for (int i = 0; i < S::G1; ++i)
 #pragma unroll
@@ -317,7 +332,7 @@ __device__ __forceinline__ void fft_forward(float2* v, float2* lds, const float2
     }
   }
   if constexpr (S::LEVELS == 3) {
-    Sync::sync();
+    Sync::pre();
 #pragma unroll
     for (int i = 0; i < S::G2; ++i)
 #pragma unroll
@@ -362,7 +377,7 @@ __device__ __forceinline__ void fft_inverse(float2* v, float2* lds, const float2
   if constexpr (S::LEVELS == 3) {
 #pragma unroll
     for (int i = 0; i < S::G3; ++i) fin(i);
-    Sync::sync();
+    Sync::pre();
 #pragma unroll
     for (int i = 0; i < S::G3; ++i)
 #pragma unroll
@@ -388,7 +403,7 @@ __device__ __forceinline__ void fft_inverse(float2* v, float2* lds, const float2
 #pragma unroll
     for (int i = 0; i < S::G2; ++i) fin(i);
   }
-  Sync::sync();
+  Sync::pre();
 #pragma unroll
   for (int i = 0; i < S::G2; ++i)
 #pragma unroll

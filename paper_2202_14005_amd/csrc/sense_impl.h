@@ -187,10 +187,12 @@ k_normal(NormalArgs a) {
         if constexpr (KS) sk[i * Sd::N1 + r] = s;
         v[i * Sd::N1 + r] = cmul(s, p[i * Sd::N1 + r]);
       }
-    fft_forward<Sd, L>(v, xl, tw, tc, c);
+    // (the tile region xl sees only this chain of transforms until the coil
+    // loop ends, so the exchanges need no barrier before their writes)
+    fft_forward<Sd, L, BlockSyncPost>(v, xl, tw, tc, c);
     // the mask (with the 1/N of the two unnormalised transforms) scales the
     // spectrum inside the inverse transform's first codelet
-    fft_inverse<Sd, L, BlockSync, FreqScale>(v, xl, tw, tc, c, FreqScale{mk});
+    fft_inverse<Sd, L, BlockSyncPost, FreqScale>(v, xl, tw, tc, c, FreqScale{mk});
     if (on) {
 #pragma unroll
       for (int i = 0; i < Sd::G1; ++i)
