@@ -252,13 +252,16 @@ struct Sched {
 // several wavefronts.  WaveSync: they all belong to one wavefront, whose LDS
 // operations execute in issue order, so only the compiler has to be kept
 // from moving LDS accesses across the exchange.  BlockSyncPost: as
-// BlockSync without the barrier before the writes.  Every exchange writes
-// exactly the LDS slots that the same thread read last (level 2 and the
-// final level of one transform, the final level of a forward and the first
-// of the inverse that follows it, the first level of an inverse and of a
-// next forward on the same tile), and each slot is read by one thread only,
-// so no other thread can still need a slot when it is overwritten; valid
-// when the tile region sees nothing but a chain of transforms in between.
+// BlockSync without the barrier before the writes, for a tile region that
+// sees nothing but alternating transforms (forward, inverse, forward, ...).
+// There every exchange writes exactly the LDS slots that the same thread
+// read in the exchange before it: the second exchange of a transform those
+// of its first, the first exchange of an inverse those of the last exchange
+// of the forward before it, and the first exchange of a forward those of the
+// last exchange of the inverse before it.  Each slot is read by one thread
+// only, so no other thread can still need a slot when it is overwritten.
+// (Two inverses in a row do not qualify: the first exchange of the second
+// writes other slots than the last exchange of the first read.)
 struct BlockSync {
   __device__ static __forceinline__ void pre() { __syncthreads(); }
   __device__ static __forceinline__ void sync() { __syncthreads(); }
