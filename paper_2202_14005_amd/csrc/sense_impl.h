@@ -133,6 +133,21 @@ k_normal(NormalArgs a) {
   }
   __syncthreads();
 
+  // The first coil's values are loaded ahead of the operand (and, in CG
+  // steps, of r), so that the two memory latencies overlap; v holds them
+  // until the first coil iteration.
+  const int64_t plane = (int64_t)N * W;
+  const float2* Sb = a.S + d.soff;
+  const int gc0 = c_begin + grp;  // this group's first coil (or, idle, a real one)
+  float2 v[P];
+  {
+    const BufPlane S0(Sb + (int64_t)(gc0 < c_end ? gc0 : c_begin) * plane, pbytes);
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) v[i * Sd::N1 + r] = S0.ld(voff, so(i, r));
+  }
+
   const BufPlane pin(a.pin + d.xoff, pbytes);
   float2 p[P];
   if (cg && a.iter > 0) {
@@ -170,23 +185,24 @@ k_normal(NormalArgs a) {
 #pragma unroll
   for (int k = 0; k < P; ++k) acc[k] = make_float2(0.f, 0.f);
 
-  const int64_t plane = (int64_t)N * W;
-  const float2* Sb = a.S + d.soff;
   const int iters = (c_end - c_begin + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
     const int coil = c_begin + it * G + grp;
     const bool on = coil < c_end;  // wave-uniform: idle groups run on a real coil's values
     const BufPlane Sc(Sb + (int64_t)(on ? coil : c_begin) * plane, pbytes);
-    float2 v[P];
+    if (it > 0) {
+#pragma unroll
+      for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+        for (int r = 0; r < Sd::N1; ++r) v[i * Sd::N1 + r] = Sc.ld(voff, so(i, r));
+    }
     float2 sk[KS ? P : 1];
 #pragma unroll
-    for (int i = 0; i < Sd::G1; ++i)
-#pragma unroll
-      for (int r = 0; r < Sd::N1; ++r) {
-        const float2 s = Sc.ld(voff, so(i, r));
-        if constexpr (KS) sk[i * Sd::N1 + r] = s;
-        v[i * Sd::N1 + r] = cmul(s, p[i * Sd::N1 + r]);
-      }
+    for (int k = 0; k < P; ++k) {
+      const float2 s = v[k];
+      if constexpr (KS) sk[k] = s;
+      v[k] = cmul(s, p[k]);
+    }
     // (the tile region xl sees only this chain of transforms until the coil
     // loop ends, so the exchanges need no barrier before their writes)
     fft_forward<Sd, L, BlockSyncPost>(v, xl, tw, tc, c);
