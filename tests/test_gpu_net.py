@@ -178,3 +178,34 @@ def test_adam_parity():
     for p, r in zip(cnn.params(), ref):
         assert np.max(np.abs(host(p) - r)) < 1e-6
     assert cnn.version == 3
+
+
+def test_sub_batch_plans_on_two_streams_equal_one_plan():
+    """Slices are independent: the batch run as two sub-batch plans on two
+    concurrent streams (same column schedule) gives the single plan's MoDL
+    output bit for bit -- no state is shared between plans or launches."""
+    B, H, W, C, T = 4, 48, 40, 4, 2
+    d, aHy = modl_case(B, H, W, C)
+    cnn = ops.CNN.from_numpy(weights(last_scale=0.1))
+    lam = 0.05
+    S, m, a = dev(d["S"]), dev(d["mask"]), dev(aHy)
+    sched = ops.schedules(H)[0]
+    plan = ops.Plan(H, W, C, B=B, network=True)
+    plan.set_schedule(H, sched)
+    ref = plan.modl_forward(a, S, m, cnn, plan.lam(lam), T, 10)
+    main = torch.cuda.current_stream()
+    parts = []
+    for j in range(2):
+        sl = slice(2 * j, 2 * j + 2)
+        p = ops.Plan(H, W, C, B=2, network=True)
+        p.set_schedule(H, sched)
+        parts.append((p, a[sl], S[sl], m[sl], torch.cuda.Stream()))
+    for rep in range(3):
+        outs = []
+        for p, a_j, S_j, m_j, s_j in parts:
+            s_j.wait_stream(main)
+            with torch.cuda.stream(s_j):
+                outs.append(p.modl_forward(a_j, S_j, m_j, cnn, p.lam(lam), T, 10))
+        for *_, s_j in parts:
+            main.wait_stream(s_j)
+        assert torch.equal(torch.cat(outs, 0), ref), rep
