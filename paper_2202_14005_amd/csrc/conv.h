@@ -41,6 +41,8 @@ struct ConvArgs {
   float2* out_c;             // complex output (last layer)
   const uint16_t* wpk;       // packed weights
   const float* bias;         // fp32 bias or null
+  const uint16_t* wpk0;      // fused first + second layer: the first layer's packed weights
+  const float* bias0;        //   and bias
   const uint16_t* relu_ref;  // dgrad: activation whose ReLU derivative masks the output
   const float2* resid;       // last layer: residual term added to the output
   int mode;

@@ -162,26 +162,16 @@ __device__ __forceinline__ void load_tile64_16(uint4* tile, const uint16_t* in, 
     if (slot[j] >= 0) tile[slot[j]] = v[j];
 }
 
-__global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
-  __shared__ uint4 tile[TILE16_PX * 8];
-  __shared__ float sbias[CNN_F];
-  const int b = a.slices[blockIdx.z];
-  const SliceDesc d = a.desc[b];
+// The 64 -> 64 layer on a staged input tile (all of its 18 x 18 pixels and
+// 64 channels in LDS, swizzled): MFMA loop and epilogue.  wa holds the
+// first tap's weight fragments on entry.
+__device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, const ConvArgs& a,
+                                              const SliceDesc& d, int ty0, int tx0, uint4 (&wa)[4][2]) {
   const int H = d.H, W = d.W;
-  const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
-  if (tx0 >= W || ty0 >= H) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int hsel = lane >> 5, n = lane & 31;
   const uint16_t* wp = a.wpk + lane * 8;
-  uint4 wa[4][2], wb[4][2];
-#pragma unroll
-  for (int kc = 0; kc < 4; ++kc) {
-    wa[kc][0] = ldg16(wp + (kc * 2 + 0) * 512);
-    wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
-  }
-  if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
-  load_tile64_16(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
-  __syncthreads();
+  uint4 wb[4][2];
   f32x16 acc[2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
@@ -237,6 +227,152 @@ __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
     };
     epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, stg, lane, pix, out, rref);
   }
+}
+
+__global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
+  __shared__ uint4 tile[TILE16_PX * 8];
+  __shared__ float sbias[CNN_F];
+  const int b = a.slices[blockIdx.z];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
+  if (tx0 >= W || ty0 >= H) return;
+  const int lane = threadIdx.x & 63;
+  const uint16_t* wp = a.wpk + lane * 8;
+  uint4 wa[4][2];
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    wa[kc][0] = ldg16(wp + (kc * 2 + 0) * 512);
+    wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
+  }
+  if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
+  load_tile64_16(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
+  __syncthreads();
+  mid16_compute(tile, sbias, a, d, ty0, tx0, wa);
+}
+
+// ------------------------------------------- 2 -> 64 -> 64, fused (forward)
+// The first two layers of the forward pass in one kernel: the first layer's
+// output is computed for the second layer's 18 x 18 input tile (its 16 x 16
+// output tile plus halo) straight into the LDS tile, zero outside the image
+// (the second layer's zero padding), rounded to bf16 as the separate first
+// layer rounds it; the second layer then runs as k_conv_mid16.  The first
+// layer's activation never goes to HBM (inference only: the reverse pass
+// recomputes the activations with the separate kernels).  The first layer
+// reads a 20 x 20 complex tile (two-pixel halo); its 324 output pixels form
+// 11 MFMA blocks of 32 (the last one partly padding), blocks wv, wv + 4, ...
+// to wave wv.  Uses a.in_c (complex input), a.wpk0 / a.bias0 (first layer)
+// and a.wpk / a.bias (second layer).
+constexpr int TWC = TW16 + 4;                // complex tile width (20)
+constexpr int TILEC_PX = (CONV_TH + 4) * TWC;  // 400
+constexpr int FUSE_BLOCKS = (TILE16_PX + 31) / 32;  // 11
+
+__global__ void __launch_bounds__(256, 3) k_conv_first_mid(ConvArgs a) {
+  __shared__ uint4 tile[TILE16_PX * 8];
+  __shared__ uint32_t ctile[TILEC_PX];
+  __shared__ float sbias[CNN_F];
+  __shared__ float sbias0[CNN_F];
+  const int b = a.slices[blockIdx.z];
+  const SliceDesc d = a.desc[b];
+  const int H = d.H, W = d.W;
+  const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
+  if (tx0 >= W || ty0 >= H) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int hsel = lane >> 5, n = lane & 31;
+  uint4 wf[2][2];  // first-layer weight fragments
+  {
+    const uint16_t* wp0 = a.wpk0 + lane * 8;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      wf[k][0] = ldg16(wp0 + (k * 2 + 0) * 512);
+      wf[k][1] = ldg16(wp0 + (k * 2 + 1) * 512);
+    }
+  }
+  if (threadIdx.x < CNN_F) {
+    sbias[threadIdx.x] = a.bias ? a.bias[threadIdx.x] : 0.f;
+    sbias0[threadIdx.x] = a.bias0 ? a.bias0[threadIdx.x] : 0.f;
+  }
+  {
+    const float2* in = a.in_c + d.xoff;
+    constexpr int PT = (TILEC_PX + 255) / 256;
+    float2 v[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int px = threadIdx.x + 256 * j;
+      v[j] = make_float2(0.f, 0.f);
+      if (px < TILEC_PX) {
+        const int ly = px / TWC, lx = px - ly * TWC;
+        const int gy = ty0 + ly - 2, gx = tx0 + lx - 2;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) v[j] = in[(int64_t)gy * W + gx];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int px = threadIdx.x + 256 * j;
+      if (px < TILEC_PX) ctile[px] = (uint32_t)f2bf(v[j].x) | ((uint32_t)f2bf(v[j].y) << 16);
+    }
+  }
+  __syncthreads();
+  // first layer into the LDS tile
+  uint2* t2 = (uint2*)tile;
+  for (int blk = wv; blk < FUSE_BLOCKS; blk += 4) {
+    const int q = blk * 32 + n;  // tile pixel (18 x 18) of this lane
+    const bool qv = q < TILE16_PX;
+    const int ly = qv ? q / (TW16 + 2) : 0, lx = qv ? q - ly * (TW16 + 2) : 0;
+    f32x16 acc[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[m][v] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      uint4 raw;
+      uint32_t* rw = (uint32_t*)&raw;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int t = s * 8 + hsel * 4 + e;  // tap
+        uint32_t v = 0;
+        if (t < 9) {
+          const int dy = t / 3, dx = t % 3;
+          v = ctile[(ly + dy) * TWC + lx + dx];
+        }
+        rw[e] = v;
+      }
+      const bf16x8 bv = as_bf16x8(raw);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(wf[s][0]), bv, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(wf[s][1]), bv, acc[1], 0, 0, 0);
+    }
+    if (qv) {
+      const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+      const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int co0 = m * 32 + 8 * g + hsel * 4;
+          float hv[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float v = acc[m][4 * g + j] + sbias0[co0 + j];
+            hv[j] = (inside && v > 0.f) ? v : 0.f;
+          }
+          uint2 pk;
+          pk.x = pack_bf16x2(hv[0], hv[1]);
+          pk.y = pack_bf16x2(hv[2], hv[3]);
+          const int ch = co0 >> 3;
+          t2[(q * 8 + (ch ^ swz(q))) * 2 + hsel] = pk;
+        }
+    }
+  }
+  const uint16_t* wp = a.wpk + lane * 8;
+  uint4 wa[4][2];
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    wa[kc][0] = ldg16(wp + (kc * 2 + 0) * 512);
+    wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
+  }
+  __syncthreads();
+  mid16_compute(tile, sbias, a, d, ty0, tx0, wa);
 }
 
 // ---------------------------------------------------------------- 2 -> 64
@@ -444,7 +580,8 @@ hipError_t conv_launch(int kind, const ConvArgs& a, hipStream_t s) {
   dim3 g16(a.tiles_x, a.tiles_y, a.nslices);
   if (kind == 0) hipLaunchKernelGGL(k_conv_first, g16, dim3(256), 0, s, a);
   else if (kind == 1) hipLaunchKernelGGL(k_conv_mid16, g16, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_conv_last, g16, dim3(256), 0, s, a);
+  else if (kind == 2) hipLaunchKernelGGL(k_conv_last, g16, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_conv_first_mid, g16, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -77,18 +77,30 @@ static mrx_status net_ready(mrx_plan_s* p, const char* who) {
   return MRX_OK;
 }
 
-// z = x + N(x); activations of layers 1-4 stay in the workspace.
-static mrx_status cnn_fwd(mrx_plan_s* p, const float2* x, float2* z, hipStream_t s) {
+// z = x + N(x); activations of layers 1-4 stay in the workspace, or, with
+// fuse12 (inference), those of layers 2-4 only: the first two layers then
+// run as one kernel and the first layer's activation is never stored.
+static mrx_status cnn_fwd(mrx_plan_s* p, const float2* x, float2* z, hipStream_t s, bool fuse12 = false) {
   uint16_t* act[4];
   for (int i = 0; i < 4; ++i) act[i] = (uint16_t*)(p->ws + p->ws_act[i]);
   ConvArgs a = conv_args(p);
   a.mode = CONV_FWD;
   a.in_c = x;
-  a.out_bf16 = act[0];
-  a.wpk = pk_ptr(p, 0, 0);
-  a.bias = p->net_b[0];
-  hipError_t e = conv_launch(0, a, s);
-  for (int l = 1; l <= 3 && e == hipSuccess; ++l) {
+  hipError_t e;
+  if (fuse12) {
+    a.out_bf16 = act[1];
+    a.wpk0 = pk_ptr(p, 0, 0);
+    a.bias0 = p->net_b[0];
+    a.wpk = pk_ptr(p, 0, 1);
+    a.bias = p->net_b[1];
+    e = conv_launch(3, a, s);
+  } else {
+    a.out_bf16 = act[0];
+    a.wpk = pk_ptr(p, 0, 0);
+    a.bias = p->net_b[0];
+    e = conv_launch(0, a, s);
+  }
+  for (int l = fuse12 ? 2 : 1; l <= 3 && e == hipSuccess; ++l) {
     ConvArgs m = conv_args(p);
     m.mode = CONV_FWD;
     m.in_bf16 = act[l - 1];
@@ -337,7 +349,7 @@ mrx_status mrx_modl_forward(mrx_plan p, const float* aHy, const float* S, const 
     return e == hipSuccess ? MRX_OK : hip_fail(e, "modl_forward: copy");
   }
   for (int t = 0; t < T; ++t) {
-    st = cnn_fwd(p, prev, z, s);
+    st = cnn_fwd(p, prev, z, s, /*fuse12=*/true);
     if (st != MRX_OK) return st;
     float2* next;
     if (t == T - 1) next = (float2*)x_out;

@@ -209,3 +209,21 @@ def test_sub_batch_plans_on_two_streams_equal_one_plan():
         for *_, s_j in parts:
             main.wait_stream(s_j)
         assert torch.equal(torch.cat(outs, 0), ref), rep
+
+
+@pytest.mark.parametrize("B,H,W,C", [(2, 48, 40, 4), (1, 320, 320, 15), (3, 24, 16, 3)])
+def test_modl_fused_first_layers_equal_separate_kernels(B, H, W, C):
+    """MoDL inference runs the first two denoiser layers as one kernel (the
+    first layer's activation stays in LDS); the reverse pass and
+    cnn_forward use the separate kernels.  Both round the first layer's
+    output to bf16 the same way, so one unroll of modl_forward equals
+    cnn_forward followed by cg_dc bit for bit (ragged tiles included)."""
+    d, aHy = modl_case(B, H, W, C)
+    cnn = ops.CNN.from_numpy(weights(last_scale=0.1))
+    plan = ops.Plan(H, W, C, B=B, network=True)
+    S, m, a = dev(d["S"]), dev(d["mask"]), dev(aHy)
+    lam = plan.lam(0.05)
+    fused = plan.modl_forward(a, S, m, cnn, lam, 1, 10)
+    z = plan.cnn_forward(a, cnn)
+    separate = plan.cg_dc(a, S, m, lam, 10, z=z)
+    assert torch.equal(fused, separate)
