@@ -208,6 +208,7 @@ __device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, c
       }
     }
   };
+#pragma unroll
   for (int tap = 0; tap < 8; tap += 2) {
     tap_step(tap, wa, wb);
     tap_step(tap + 1, wb, wa);
