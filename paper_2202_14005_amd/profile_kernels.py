@@ -9,7 +9,9 @@ of ``reps`` iterations (one CG-fused k_normal launch and one k_cg_update per
 iteration, as in the MoDL step; the kernel whose HBM bytes the benchmark's
 roofline reports) with the given column schedule, or the autotuner's choice
 with --tune, or the default,
-``conv`` one 64 -> 64 denoiser layer (k_conv_mid16), ``backward`` one reverse
+``conv`` one 64 -> 64 denoiser layer (k_conv_mid16), ``denoiser`` the
+denoiser as MoDL inference runs it (one unroll without CG steps: the fused
+first two layers k_conv_first_mid, two k_conv_mid16, k_conv_last), ``backward`` one reverse
 pass of the denoiser (input gradient and weight gradients, all five
 layers), ``copy`` a device-to-device
 copy of 256 MiB (256 MiB read, 256 MiB written) whose counter readings
@@ -64,6 +66,10 @@ def main():
     for _ in range(a.reps):
         if "conv" in what:
             plan.cnn_layer_forward(2, a_in, cnn, out=a_out)
+        if "denoiser" in what:
+            # one MoDL unroll with no CG step: the denoiser as inference runs
+            # it (fused first two layers, layers 3 and 4, last layer)
+            plan.modl_forward(x, S, m, cnn, lam, 1, 0)
         if "backward" in what:
             plan.cnn_backward(x, gz, cnn, grads)
         if "copy" in what:
