@@ -1,13 +1,14 @@
 // MFMA 3x3 convolutions for the MoDL denoiser (bf16 operands, fp32
-// accumulation, NHWC activations).  One workgroup (4 waves) computes a tile
-// of 16 rows x 32 columns (first and last layer) or 16 x 16 (middle layers)
-// of one slice; the input tile with its one-pixel halo is staged in LDS,
-// weights stream from L1/L2 as MFMA fragments.
+// accumulation, NHWC activations).  One workgroup (4 waves) computes a
+// 16 x 16-pixel output tile of one slice; the input tile with its one-pixel
+// halo is staged in LDS, weights stream from L1/L2 as MFMA fragments.
 //   first layer:  2 -> 64 channels, v_mfma_f32_32x32x16_bf16, K = 18 -> 32
 //   middle layer: 64 -> 64, v_mfma_f32_32x32x16_bf16, K = 9 x 64
 //   last layer:   64 -> 2 (+ residual), v_mfma_f32_16x16x32_bf16, co padded to 16
-// The same kernels run the input-gradient (dgrad) pass with transposed,
-// flipped weights and a ReLU-derivative mask in the epilogue.
+//   first + second layer fused (inference forward only)
+// The same kernels (the fused one excepted) run the input-gradient (dgrad)
+// pass with transposed, flipped weights and a ReLU-derivative mask in the
+// epilogue.
 #include "conv.h"
 #include "cg_kernels.h"
 
