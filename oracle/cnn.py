@@ -15,16 +15,26 @@ and F = 64 real filters; the configuration built here has no batch norm):
 Gradients follow the DF^H(1) convention of the paper's complex-numbers
 paragraph: for a complex quantity the returned gradient is dL/dRe + i dL/dIm.
 
-Operand precision.  With ``bf16=True`` the convolution operands are rounded
-to bfloat16 (round to nearest even) where a bf16-operand / wide-accumulator
-implementation rounds them: the layer inputs (the complex image, the stored
-activations), the weights, and the gradients entering each convolution of the
-reverse pass; sums stay in float64.  This mode exists because the ReLU
-derivative is a decision taken on a floating-point value: comparing a bf16
-implementation's reverse pass with an fp64 one mixes in sign flips of
-pre-activations that lie within rounding of zero, so the decision has to be
-taken in the same precision on both sides.  ``bf16=False`` (the default) is
-the plain FP64 definition.
+Operand precision.  The configuration built here runs the convolutions with
+bfloat16 operands and wide accumulation.  With ``bf16=True`` the oracle
+computes exactly that definition: every operand of a convolution contraction
+is rounded to bfloat16 (round to nearest even) --
+
+* forward: the layer input (the complex image as two channels, or the
+  previous layer's ReLU output) and the weights;
+* reverse, input gradient: the gradient entering the layer (after the ReLU
+  derivative) and the weights;
+* reverse, weight gradient: the gradient entering the layer and the layer
+  input --
+
+while everything that is not a convolution operand stays float64: the sums,
+biases, ReLU and its derivative (taken on the float64 pre-activation), the
+bias gradients (sums of the unrounded gradient), the residual and the
+network output.  The mode exists because the ReLU derivative is a decision on
+a floating-point value: a bf16-operand network and the fp64 one disagree on
+pre-activations within rounding of zero, so the decision has to be taken on
+the same operands on both sides.  ``bf16=False`` (the default) is the plain
+FP64 definition.
 """
 from __future__ import annotations
 
@@ -44,17 +54,22 @@ def _q(a, on):
     return bf16_round(a) if on else np.asarray(a, dtype=np.float64)
 
 
+def _tap(ap, dy, dx, H, W):
+    """The padded input shifted by tap (dy, dx), as a [pixels, channels] matrix."""
+    return np.ascontiguousarray(ap[:, dy:dy + H, dx:dx + W, :]).reshape(-1, ap.shape[-1])
+
+
 def conv3x3(a, Wt, bias):
     """Same-padded 3x3 cross-correlation. a [B,H,W,Ci], Wt [Co,Ci,3,3]."""
     a = np.asarray(a, dtype=np.float64)
     Wt = np.asarray(Wt, dtype=np.float64)
     B, H, W, _ = a.shape
     ap = np.pad(a, ((0, 0), (1, 1), (1, 1), (0, 0)))
-    out = np.zeros((B, H, W, Wt.shape[0]))
+    out = np.zeros((B * H * W, Wt.shape[0]))
     for dy in range(3):
         for dx in range(3):
-            out += ap[:, dy:dy + H, dx:dx + W, :] @ Wt[:, :, dy, dx].T
-    return out + np.asarray(bias, dtype=np.float64)
+            out += _tap(ap, dy, dx, H, W) @ np.ascontiguousarray(Wt[:, :, dy, dx].T)
+    return out.reshape(B, H, W, -1) + np.asarray(bias, dtype=np.float64)
 
 
 def conv3x3_backward(a, Wt, g):
@@ -62,19 +77,20 @@ def conv3x3_backward(a, Wt, g):
     output gradient g [B,H,W,Co]."""
     a = np.asarray(a, dtype=np.float64)
     Wt = np.asarray(Wt, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
     B, H, W, _ = a.shape
     ap = np.pad(a, ((0, 0), (1, 1), (1, 1), (0, 0)))
     gp = np.pad(g, ((0, 0), (1, 1), (1, 1), (0, 0)))
-    ga = np.zeros_like(a)
+    g2 = g.reshape(-1, g.shape[-1])
+    ga = np.zeros((B * H * W, a.shape[-1]))
     gW = np.zeros_like(Wt)
     for dy in range(3):
         for dx in range(3):
             # out[p] uses in[p + d]  =>  g_in[q] += g[q - d] W_d
-            ga += gp[:, 2 - dy:2 - dy + H, 2 - dx:2 - dx + W, :] @ Wt[:, :, dy, dx]
-            gW[:, :, dy, dx] = np.einsum(
-                "bhwo,bhwi->oi", g, ap[:, dy:dy + H, dx:dx + W, :])
+            ga += _tap(gp, 2 - dy, 2 - dx, H, W) @ np.ascontiguousarray(Wt[:, :, dy, dx])
+            gW[:, :, dy, dx] = g2.T @ _tap(ap, dy, dx, H, W)
     gb = g.sum(axis=(0, 1, 2))
-    return ga, gW, gb
+    return ga.reshape(a.shape), gW, gb
 
 
 def to_channels(x):
@@ -109,23 +125,20 @@ def denoise(x, weights, bf16=False):
 
 def denoise_backward(x, weights, g, bf16=False):
     """Reverse mode of D_W at x with upstream gradient g (complex [B,H,W]).
-    Returns (g_x complex, [(gW, gb), ...]).  With bf16=True the gradient
-    entering each convolution is rounded to bfloat16 as well (the bias
-    gradient of the last layer uses the unrounded upstream gradient)."""
+    Returns (g_x complex, [(gW, gb), ...]).  With bf16=True the operands of
+    the reverse convolutions are rounded to bfloat16 as described in the
+    module docstring; bias gradients sum the unrounded gradient."""
     _, acts, pres = net_forward(x, weights, keep=True, bf16=bf16)
     L = len(weights)
-    ga = to_channels(g)
+    delta = to_channels(g)
     grads = [None] * L
     for l in range(L - 1, -1, -1):
         if l < L - 1:
-            ga = _q(ga * (pres[l] > 0), bf16)
-        gq = _q(ga, bf16)
-        gin, gW, gb = conv3x3_backward(acts[l], _q(weights[l][0], bf16), gq)
-        if l == L - 1:
-            gb = ga.sum(axis=(0, 1, 2))
-        grads[l] = (gW, gb)
-        ga = gin
-    return np.asarray(g, dtype=np.complex128) + from_channels(ga), grads
+            delta = delta * (pres[l] > 0)
+        gin, gW, _ = conv3x3_backward(acts[l], _q(weights[l][0], bf16), _q(delta, bf16))
+        grads[l] = (gW, delta.sum(axis=(0, 1, 2)))
+        delta = gin
+    return np.asarray(g, dtype=np.complex128) + from_channels(delta), grads
 
 
 def n_params(channels, k=3):

@@ -185,6 +185,70 @@ def test_bf16_rounding_matches_torch_and_ties_to_even(rng):
     assert cnn.bf16_round(three_halves) == 1.0 + 2.0 ** -6
 
 
+def hand_net():
+    import json, os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "denoise_hand_worked.json")))
+    weights = []
+    for cw, b in zip(d["centre_weights"], d["biases"]):
+        cw = np.asarray(cw, dtype=np.float64)
+        Wt = np.full(cw.shape + (3, 3), d["other_taps"])
+        Wt[:, :, 1, 1] = cw
+        weights.append((Wt, np.asarray(b, dtype=np.float64)))
+    c = lambda a: np.array([complex(*v) for v in a]).reshape(-1, 1, 1)
+    return d, weights, c
+
+
+def test_denoise_hand_worked_example():
+    """Values worked by hand (tests/golden/denoise_hand_worked.json): fails if
+    the ReLU moves to the last layer, a ReLU, a bias or the residual is
+    dropped, the channel order flips or the padding is not zero."""
+    d, weights, c = hand_net()
+    assert np.array_equal(cnn.denoise(c(d["x"]), weights), c(d["D"]))
+    gx, grads = cnn.denoise_backward(c(d["x"]), weights, c(d["g"]))
+    assert np.array_equal(gx, c(d["g_x"]))
+    for l, (gW, gb) in enumerate(grads):
+        want = np.zeros_like(gW)
+        want[:, :, 1, 1] = d["grad_centre_weights_summed"][l]
+        assert np.array_equal(gW, want), l
+        assert np.array_equal(gb, d["grad_biases_summed"][l]), l
+
+
+def test_bf16_mode_rounds_exactly_the_convolution_operands(rng):
+    """Two-layer net computed independently with scipy's 2-D correlation and
+    convolution: bf16 rounding of every convolution operand (layer inputs,
+    weights, the gradients entering each reverse convolution), float64 for
+    sums, biases, ReLU, bias gradients and the residual."""
+    q = cnn.bf16_round
+    B, H, W = 1, 5, 6
+    x = rand_c(rng, B, H, W)
+    g = rand_c(rng, B, H, W)
+    w = small_weights(rng, (2, 3, 2))
+    gx, grads = cnn.denoise_backward(x, w, g, bf16=True)
+    out = cnn.denoise(x, w, bf16=True)
+    corr = lambda a, k: scipy.signal.correlate2d(a, k, mode="same", boundary="fill")
+    conv = lambda a, k: scipy.signal.convolve2d(a, k, mode="same", boundary="fill")
+    wgrad = lambda d_, a: scipy.signal.correlate2d(np.pad(a, 1), d_, mode="valid")
+    (W0, b0), (W1, b1) = w
+    a0 = [q(x[0].real), q(x[0].imag)]
+    pre0 = [b0[o] + sum(corr(a0[i], q(W0[o, i])) for i in range(2)) for o in range(3)]
+    a1 = [q(np.maximum(p, 0)) for p in pre0]
+    pre1 = [b1[o] + sum(corr(a1[i], q(W1[o, i])) for i in range(3)) for o in range(2)]
+    assert np.max(np.abs(out[0] - (x[0] + pre1[0] + 1j * pre1[1]))) < 1e-12
+    d1 = [g[0].real, g[0].imag]
+    gb1 = [d1[o].sum() for o in range(2)]
+    gW1 = np.array([[wgrad(q(d1[o]), a1[i]) for i in range(3)] for o in range(2)])
+    ga1 = [sum(conv(q(d1[o]), q(W1[o, i])) for o in range(2)) for i in range(3)]
+    d0 = [ga1[i] * (pre0[i] > 0) for i in range(3)]
+    gb0 = [d0[o].sum() for o in range(3)]
+    gW0 = np.array([[wgrad(q(d0[o]), a0[i]) for i in range(2)] for o in range(3)])
+    ga0 = [sum(conv(q(d0[o]), q(W0[o, i])) for o in range(3)) for i in range(2)]
+    assert np.max(np.abs(grads[1][0] - gW1)) < 1e-12
+    assert np.max(np.abs(grads[1][1] - gb1)) < 1e-12
+    assert np.max(np.abs(grads[0][0] - gW0)) < 1e-12
+    assert np.max(np.abs(grads[0][1] - gb0)) < 1e-12
+    assert np.max(np.abs(gx[0] - (g[0] + ga0[0] + 1j * ga0[1]))) < 1e-12
+
+
 def test_bf16_mode_is_close_to_fp64(rng):
     x = rand_c(rng, 1, 12, 10)
     w = small_weights(rng)
