@@ -123,22 +123,26 @@ def denoise(x, weights, bf16=False):
     return np.asarray(x, dtype=np.complex128) + net_forward(x, weights, bf16=bf16)
 
 
-def denoise_backward(x, weights, g, bf16=False):
+def denoise_backward(x, weights, g, bf16=False, keep=False):
     """Reverse mode of D_W at x with upstream gradient g (complex [B,H,W]).
-    Returns (g_x complex, [(gW, gb), ...]).  With bf16=True the operands of
+    Returns (g_x complex, [(gW, gb), ...]), and with keep=True also the
+    gradients with respect to each layer's pre-activation (the bias
+    gradients are their sums over pixels).  With bf16=True the operands of
     the reverse convolutions are rounded to bfloat16 as described in the
     module docstring; bias gradients sum the unrounded gradient."""
     _, acts, pres = net_forward(x, weights, keep=True, bf16=bf16)
     L = len(weights)
     delta = to_channels(g)
-    grads = [None] * L
+    grads, deltas = [None] * L, [None] * L
     for l in range(L - 1, -1, -1):
         if l < L - 1:
             delta = delta * (pres[l] > 0)
+        deltas[l] = delta
         gin, gW, _ = conv3x3_backward(acts[l], _q(weights[l][0], bf16), _q(delta, bf16))
         grads[l] = (gW, delta.sum(axis=(0, 1, 2)))
         delta = gin
-    return np.asarray(g, dtype=np.complex128) + from_channels(delta), grads
+    gx = np.asarray(g, dtype=np.complex128) + from_channels(delta)
+    return (gx, grads, deltas) if keep else (gx, grads)
 
 
 def n_params(channels, k=3):

@@ -47,7 +47,7 @@ struct mrx_plan_s {
   // network workspace (set by extra_workspace_bytes)
   size_t ws_act[4] = {0, 0, 0, 0}, ws_gact[2] = {0, 0};
   size_t ws_z = 0, ws_ximg[2] = {0, 0}, ws_gimg[2] = {0, 0}, ws_vimg = 0;
-  size_t ws_pk = 0, ws_wpart = 0, ws_loss = 0;
+  size_t ws_pk = 0, ws_wpart = 0, ws_bpart = 0, ws_loss = 0;
   const float* net_b[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   // VarNet workspace
   size_t ws_vn_kt = 0, ws_vn_u = 0, ws_vn_e = 0, ws_vn_kg = 0, ws_vn_s = 0, ws_vn_qx = 0, ws_vn_qg = 0;
@@ -92,7 +92,23 @@ size_t extra_workspace_bytes(mrx_plan_s* p);
 // upload, also copy the descriptors to the device (synchronous).
 mrx_status refresh_desc(mrx_plan_s* p, bool upload);
 size_t vn_workspace_bytes(mrx_plan_s* p, size_t base);
+// Device buffers of one CG solve: residual, the two search-direction
+// buffers, the partial planes of the normal operator's output (KSPL_MAX or
+// the plan's largest coil split), the <p, q> and <r, r> partial sums, the
+// per-slice stop words and status words.
+struct CgBufs {
+  float2* r = nullptr;
+  float2* p[2] = {nullptr, nullptr};
+  float2* q = nullptr;
+  float* pq = nullptr;
+  float* rr[2] = {nullptr, nullptr};
+  int* stop = nullptr;
+  uint32_t* status = nullptr;
+};
+// The plan workspace's CG buffers.
+CgBufs cg_bufs_ws(mrx_plan_s* p);
 CgElemArgs elem_args(mrx_plan_s* p, const float* lam);
+CgElemArgs elem_args(mrx_plan_s* p, const float* lam, const CgBufs& b);
 hipError_t clear_status(mrx_plan_s* p, hipStream_t s);
 hipError_t fill_u32(uint32_t* dst, uint32_t value, int64_t n, hipStream_t s);
 
@@ -102,5 +118,7 @@ mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const fl
                        float2* out, hipStream_t s);
 mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,
                    const float* lam, int n_iter, float2* x, float* hist, hipStream_t s);
+mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bufs, const float2* aHy, const float2* z, const float2* S,
+                   const float* mask, const float* lam, int n_iter, float2* x, float* hist, hipStream_t s);
 
 }  // namespace mrx

@@ -47,6 +47,12 @@ struct ConvArgs {
   const float2* resid;       // last layer: residual term added to the output
   int mode;
   uint32_t* status;          // per-slice status (non-finite output flag), may be null
+  // dgrad of the first (2 -> 64 operator) and middle layers: per-workgroup
+  // fp32 sums over pixels of the masked output, [slot][64] with slot =
+  // blockIdx.x + tiles_x (blockIdx.y + tiles_y blockIdx.z) (zero for tiles
+  // outside their slice) -- the bias gradient of the layer whose ReLU masks
+  // the output, before rounding to bf16.  Null: not computed.
+  float* bias_part;
 };
 
 }  // namespace mrx

@@ -127,6 +127,79 @@ __device__ __forceinline__ void epi_block64(const f32x16& a0, const f32x16& a1, 
     if (off[r] >= 0) *(uint4*)(out + off[r] + c * 8) = v[r];
 }
 
+// Input-gradient epilogue that also sums the bias gradient in fp32: the
+// block is staged as fp32 (each wave's 8 KB: 32 pixel rows of 16 quads of 4
+// channels, quad q of pixel n at q ^ (n & 15), conflict-free for both
+// phases), read back as whole pixels, masked by relu_ref on the fp32 values,
+// rounded to bf16 and stored (the stored values equal those of epi_block64:
+// masking commutes with rounding zero).  bs[e] accumulates, per lane, the
+// masked values of channel (lane & 7) * 8 + e over the lane's pixels.
+template <class PixFn>
+__device__ __forceinline__ void epi_block64_bsum(const f32x16& a0, const f32x16& a1, float4* stgf, int lane,
+                                                 PixFn pix, uint16_t* out, const uint16_t* rref, float (&bs)[8]) {
+  const int n = lane & 31, hsel = lane >> 5;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int q = m * 8 + 2 * g + hsel;  // channels 4q .. 4q + 3
+      const f32x16& a = m ? a1 : a0;
+      stgf[n * 16 + (q ^ (n & 15))] = make_float4(a[4 * g], a[4 * g + 1], a[4 * g + 2], a[4 * g + 3]);
+    }
+  const int c = lane & 7;
+  int64_t off[4];
+  uint4 mr[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    off[r] = pix(r * 8 + (lane >> 3));
+    mr[r] = off[r] >= 0 ? ldg16(rref + off[r] + c * 8) : make_uint4(0, 0, 0, 0);
+  }
+  WaveFence::sync();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int pi = r * 8 + (lane >> 3), k = pi & 15;
+    const float4 f0 = stgf[pi * 16 + ((2 * c) ^ k)], f1 = stgf[pi * 16 + ((2 * c + 1) ^ k)];
+    const float fv[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+    const uint32_t* mw = (const uint32_t*)&mr[r];
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint16_t h = (uint16_t)((e & 1) ? (mw[e >> 1] >> 16) : (mw[e >> 1] & 0xffffu));
+      v[e] = bf_pos(h) ? fv[e] : 0.f;
+      bs[e] += v[e];
+    }
+    uint4 pk;
+    pk.x = pack_bf16x2(v[0], v[1]);
+    pk.y = pack_bf16x2(v[2], v[3]);
+    pk.z = pack_bf16x2(v[4], v[5]);
+    pk.w = pack_bf16x2(v[6], v[7]);
+    if (off[r] >= 0) *(uint4*)(out + off[r] + c * 8) = pk;
+  }
+  WaveFence::sync();  // stgf is free for the next block
+}
+
+// The workgroup's bias partial from the lanes' sums bs (see epi_block64_bsum):
+// a butterfly over the 8 lanes that share a channel group, the 4 waves' sums
+// through LDS (wsum, 4 x 64 floats) in wave order, one slot of 64 floats.
+__device__ __forceinline__ void bias_partial_store(float (&bs)[8], float* wsum, float* slot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 8; o <= 32; o <<= 1)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bs[e] += __shfl_xor(bs[e], o, 64);
+  if (lane < 8) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) wsum[wv * 64 + lane * 8 + e] = bs[e];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64)
+    slot[threadIdx.x] = ((wsum[threadIdx.x] + wsum[64 + threadIdx.x]) + wsum[128 + threadIdx.x]) + wsum[192 + threadIdx.x];
+}
+
+__device__ __forceinline__ float* bias_slot(const ConvArgs& a) {
+  return a.bias_part + ((int64_t)blockIdx.x + (int64_t)a.tiles_x * (blockIdx.y + (int64_t)a.tiles_y * blockIdx.z)) * CNN_F;
+}
+
 // ------------------------------------------------------------- 64 -> 64
 // 16 x 16-pixel tiles (41.5 KB of LDS) so that three workgroups fit on a CU;
 // each wave computes 4 rows x 16 columns x 64 output channels as 2 pixel
@@ -166,6 +239,7 @@ __device__ __forceinline__ void load_tile64_16(uint4* tile, const uint16_t* in, 
 // The 64 -> 64 layer on a staged input tile (all of its 18 x 18 pixels and
 // 64 channels in LDS, swizzled): MFMA loop and epilogue.  wa holds the
 // first tap's weight fragments on entry.
+template <bool BSUM>
 __device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, const ConvArgs& a,
                                               const SliceDesc& d, int ty0, int tx0, uint4 (&wa)[4][2]) {
   const int H = d.H, W = d.W;
@@ -219,7 +293,7 @@ __device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, c
   __syncthreads();
   uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
   const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
-  uint2* stg = (uint2*)tile + wv * 512;
+  float bs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int gy0 = ty0 + wv * 4 + nb * 2;
@@ -227,18 +301,29 @@ __device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, c
       const int gy = gy0 + (i >> 4), gx = tx0 + (i & 15);
       return (gy < H && gx < W) ? ((int64_t)gy * W + gx) * CNN_F : -1;
     };
-    epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, stg, lane, pix, out, rref);
+    if constexpr (BSUM)
+      epi_block64_bsum(acc[0][nb], acc[1][nb], (float4*)tile + wv * 512, lane, pix, out, rref, bs);
+    else
+      epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, (uint2*)tile + wv * 512, lane, pix, out, rref);
   }
+  // 4 waves x 8 KB of fp32 staging end at 32 KB of the 41.5 KB tile
+  if constexpr (BSUM) bias_partial_store(bs, (float*)((float4*)tile + 4 * 512), bias_slot(a));
 }
 
+template <bool BSUM>
 __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
+  static_assert(4 * 512 * sizeof(float4) + 4 * CNN_F * sizeof(float) <= TILE16_PX * 8 * sizeof(uint4),
+                "fp32 staging and wave sums must fit in the tile");
   __shared__ uint4 tile[TILE16_PX * 8];
   __shared__ float sbias[CNN_F];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
   const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
-  if (tx0 >= W || ty0 >= H) return;
+  if (tx0 >= W || ty0 >= H) {
+    if (BSUM && threadIdx.x < CNN_F) bias_slot(a)[threadIdx.x] = 0.f;
+    return;
+  }
   const int lane = threadIdx.x & 63;
   const uint16_t* wp = a.wpk + lane * 8;
   uint4 wa[4][2];
@@ -250,7 +335,7 @@ __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
   if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
   load_tile64_16(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
   __syncthreads();
-  mid16_compute(tile, sbias, a, d, ty0, tx0, wa);
+  mid16_compute<BSUM>(tile, sbias, a, d, ty0, tx0, wa);
 }
 
 // ------------------------------------------- 2 -> 64 -> 64, fused (forward)
@@ -374,22 +459,28 @@ __global__ void __launch_bounds__(256, 3) k_conv_first_mid(ConvArgs a) {
     wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
   }
   __syncthreads();
-  mid16_compute(tile, sbias, a, d, ty0, tx0, wa);
+  mid16_compute<false>(tile, sbias, a, d, ty0, tx0, wa);
 }
 
 // ---------------------------------------------------------------- 2 -> 64
 // Input: complex image (fp32 pairs), rounded to bf16.  K = 9 taps x 2 channels
 // = 18, padded to 32 (two 16-deep MFMA steps).  16 x 16-pixel tiles; each
 // wave computes 4 rows x 16 columns x 64 channels (2 pixel blocks).
+template <bool BSUM>
 __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
   __shared__ uint32_t tile[TILE1_PX];
   __shared__ float sbias[CNN_F];
-  __shared__ uint2 stage[4 * 512];  // 4 KB per wave for the epilogue
+  // epilogue staging: 4 KB per wave (bf16), or 8 KB per wave (fp32) and the
+  // waves' bias sums when BSUM
+  __shared__ uint4 stage[BSUM ? 4 * 512 + CNN_F : 4 * 256];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
   const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
-  if (tx0 >= W || ty0 >= H) return;
+  if (tx0 >= W || ty0 >= H) {
+    if (BSUM && threadIdx.x < CNN_F) bias_slot(a)[threadIdx.x] = 0.f;
+    return;
+  }
   const float2* in = a.in_c + d.xoff;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint16_t* wp = a.wpk + lane * 8;
@@ -454,6 +545,7 @@ __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
   }
   uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
   const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
+  float bs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int gy0 = ty0 + wv * 4 + nb * 2;
@@ -461,8 +553,12 @@ __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
       const int gy = gy0 + (i >> 4), gx = tx0 + (i & 15);
       return (gy < H && gx < W) ? ((int64_t)gy * W + gx) * CNN_F : -1;
     };
-    epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, stage + wv * 512, lane, pix, out, rref);
+    if constexpr (BSUM)
+      epi_block64_bsum(acc[0][nb], acc[1][nb], (float4*)stage + wv * 512, lane, pix, out, rref, bs);
+    else
+      epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, (uint2*)stage + wv * 512, lane, pix, out, rref);
   }
+  if constexpr (BSUM) bias_partial_store(bs, (float*)((float4*)stage + 4 * 512), bias_slot(a));
 }
 
 // ---------------------------------------------------------------- 64 -> 2
@@ -580,8 +676,14 @@ __global__ void k_pack_last(const float* Wm, uint16_t* out, int transpose) {
 
 hipError_t conv_launch(int kind, const ConvArgs& a, hipStream_t s) {
   dim3 g16(a.tiles_x, a.tiles_y, a.nslices);
-  if (kind == 0) hipLaunchKernelGGL(k_conv_first, g16, dim3(256), 0, s, a);
-  else if (kind == 1) hipLaunchKernelGGL(k_conv_mid16, g16, dim3(256), 0, s, a);
+  const bool bsum = a.mode == CONV_DGRAD && a.bias_part;
+  if (kind == 0) {
+    if (bsum) hipLaunchKernelGGL(k_conv_first<true>, g16, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_conv_first<false>, g16, dim3(256), 0, s, a);
+  } else if (kind == 1) {
+    if (bsum) hipLaunchKernelGGL(k_conv_mid16<true>, g16, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_conv_mid16<false>, g16, dim3(256), 0, s, a);
+  }
   else if (kind == 2) hipLaunchKernelGGL(k_conv_last, g16, dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_conv_first_mid, g16, dim3(256), 0, s, a);
   return hipGetLastError();

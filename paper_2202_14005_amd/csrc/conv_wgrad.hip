@@ -1,6 +1,9 @@
-// Weight and bias gradients of the denoiser's 3x3 convolutions
-//   dW[co][ci][tap] = sum_p g[p][co] * a[p + d(tap)][ci],   db[co] = sum_p g[p][co]
-// as MFMA products with the pixel index as the reduction (K) dimension.  A
+// Weight gradients of the denoiser's 3x3 convolutions
+//   dW[co][ci][tap] = sum_p g[p][co] * a[p + d(tap)][ci]
+// as MFMA products with the pixel index as the reduction (K) dimension, and
+// the last layer's bias gradient db[co] = sum_p g[p][co] from its fp32
+// gradient (the inner layers' bias gradients are summed in fp32 by the
+// input-gradient convolutions that produce their gradients, conv.hip).  A
 // fixed grid of WGM_WGS workgroups walks the batch's tiles of WG_ROWS rows x
 // 32 columns; every workgroup writes its partial sums to its own slot and a
 // second kernel adds the slots in a fixed order (deterministic, no float
@@ -25,15 +28,6 @@ __device__ __forceinline__ float bf2f_w(uint16_t h) { return __uint_as_float((ui
 __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 constexpr int RT = WG_ROWS;  // rows per tile (tiles are RT x 32 pixels)
-
-// Sum of the 8 bf16 values of a fragment, in fp32, in index order.
-__device__ __forceinline__ float frag_sum(uint4 v) {
-  const uint16_t* h = (const uint16_t*)&v;
-  float s = 0.f;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) s += bf2f_w(h[e]);
-  return s;
-}
 
 // ------------------------------------------------------------ 64 -> 64
 // A fixed grid of WGM_WGS workgroups walks the batch's tiles (RT rows x 32
@@ -175,8 +169,6 @@ __global__ void __launch_bounds__(W2_THREADS) k_wgrad_mid(WgradArgs a) {
   for (int t = 0; t < 3; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
-  float bsum = 0.f;
-  const bool bias_wave = nb == 0 && dx == 0;
   // two register sets of prefetched tiles (tiles t + 1 and t + 2 are in
   // flight while tile t is computed)
   TileCursor nxt;
@@ -210,7 +202,6 @@ __global__ void __launch_bounds__(W2_THREADS) k_wgrad_mid(WgradArgs a) {
         const uint4 b2 = fb(r + 2);
         const int o = (r * 32 + 16 * h) * 128;
         const uint4 af = frag_tr(tb, o + offA[0], o + offA[1]);
-        if (bias_wave) bsum += frag_sum(af);  // bias gradient, channel mb * 32 + lane % 32
         acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(af), as_bf(b0), acc[0], 0, 0, 0);
         acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(af), as_bf(b1), acc[1], 0, 0, 0);
         acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(af), as_bf(b2), acc[2], 0, 0, 0);
@@ -233,9 +224,6 @@ __global__ void __launch_bounds__(W2_THREADS) k_wgrad_mid(WgradArgs a) {
       part[(tap * 64 + co) * 64 + ci] = acc[dy][v];  // tap-major: 128-byte runs of ci
     }
   }
-  // lanes l and l + 32 hold the two pixel halves of channel mb * 32 + l % 32
-  bsum += __shfl_xor(bsum, 32, 64);
-  if (bias_wave && lane < 32) part[64 * 64 * 9 + mb * 32 + lane] = bsum;
 }
 
 // ------------------------------------------------- 2 -> 64 and 64 -> 2
@@ -324,7 +312,7 @@ __global__ void __launch_bounds__(WS_THREADS) k_wgrad_small(WgradArgs a) {
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  float bsum = 0.f, bs0 = 0.f, bs1 = 0.f;
+  float bs0 = 0.f, bs1 = 0.f;  // last layer: bias gradient (fp32 input gradient)
   const uint16_t* t64 = LAST ? a.act : a.g;
   TileCursor nxt;
   cursor_load(nxt, a, 0, 0);
@@ -363,7 +351,6 @@ __global__ void __launch_bounds__(WS_THREADS) k_wgrad_small(WgradArgs a) {
       if (LAST) {
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(raw), as_bf(f), acc, 0, 0, 0);
       } else {
-        bsum += frag_sum(f);  // bias gradient, channel blk * 32 + lane % 32
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(f), as_bf(raw), acc, 0, 0, 0);
       }
     }
@@ -377,7 +364,6 @@ __global__ void __launch_bounds__(WS_THREADS) k_wgrad_small(WgradArgs a) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) comb[blk][v][lane] = acc[v];
   }
-  bsum += __shfl_xor(bsum, 32, 64);  // lanes l and l + 32: the two k halves of a channel
   __syncthreads();
   if (h == 0) {
 #pragma unroll
@@ -391,13 +377,7 @@ __global__ void __launch_bounds__(WS_THREADS) k_wgrad_small(WgradArgs a) {
       }
     }
   }
-  if (!LAST) {
-    // bias: waves (blk, h = 0) and (blk, h = 1) each hold half of the pixels
-    __syncthreads();
-    if (h == 1 && lane < 32) comb[blk][0][lane] = bsum;
-    __syncthreads();
-    if (h == 0 && lane < 32) part[64 * 32 + blk * 32 + lane] = bsum + comb[blk][0][lane];
-  } else {
+  if (LAST) {
     // bias: per-thread sums -> wave butterfly -> the 4 wave sums in order
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -438,13 +418,13 @@ __device__ __forceinline__ int wg_dst(int layout, int i) {
 constexpr int WR_WAVES = 16;
 
 __global__ void __launch_bounds__(64 * WR_WAVES) k_wgrad_reduce(const float* partial, int nslots, int nout,
-                                                               float* w_out, float* b_out, int npw, int accumulate,
-                                                               int layout) {
+                                                               int nred, float* w_out, float* b_out, int npw,
+                                                               int accumulate, int layout) {
   __shared__ float red[WR_WAVES][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   float s = 0.f;
-  if (i < nout) {
+  if (i < nred) {
     int k = wv;
     for (; k + 3 * WR_WAVES < nslots; k += 4 * WR_WAVES) {
       const float a0 = partial[(int64_t)k * nout + i];
@@ -457,7 +437,7 @@ __global__ void __launch_bounds__(64 * WR_WAVES) k_wgrad_reduce(const float* par
   }
   red[wv][lane] = s;
   __syncthreads();
-  if (wv == 0 && i < nout) {
+  if (wv == 0 && i < nred) {
     float t = red[0][lane];
 #pragma unroll
     for (int w = 1; w < WR_WAVES; ++w) t += red[w][lane];
@@ -485,7 +465,13 @@ hipError_t wgrad_reduce(int kind, const float* partial, float* w_out, float* b_o
   const int npw = kind == 1 ? 64 * 64 * 9 : kind == 0 ? 64 * 32 : 18 * 64;
   const int layout = kind == 1 ? WG_LAYOUT_MID : kind == 0 ? WG_LAYOUT_FIRST : WG_LAYOUT_LAST;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 63) / 64), dim3(64 * WR_WAVES), 0, s, partial,
-                     wgrad_slots(kind), nout, w_out, b_out, npw, accumulate, layout);
+                     wgrad_slots(kind), nout, nout, w_out, b_out, npw, accumulate, layout);
+  return hipGetLastError();
+}
+
+hipError_t bias_reduce(const float* partial, int nslots, float* b_out, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(1), dim3(64 * WR_WAVES), 0, s, partial, nslots, 64, 64,
+                     (float*)nullptr, b_out, 0, accumulate, WG_LAYOUT_MID);
   return hipGetLastError();
 }
 

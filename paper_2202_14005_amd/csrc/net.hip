@@ -38,6 +38,10 @@ size_t net_workspace_bytes(mrx_plan_s* p) {
   size_t wpart = 0;
   for (int k = 0; k < 3; ++k) wpart = std::max(wpart, (size_t)wgrad_slots(k) * wgrad_nout(k));
   p->ws_wpart = take(wpart * 4);
+  // per-workgroup bias sums of the input-gradient convolutions (one slot of
+  // 64 floats per 16 x 16 tile of the launch grid)
+  p->ws_bpart = take((size_t)((p->maxW + CONV_TW - 1) / CONV_TW) * ((p->maxH + CONV_TH - 1) / CONV_TH) * p->B *
+                     CNN_F * 4);
   p->ws_loss = take((size_t)p->B * p->nrr * 4);
   return w;
 }
@@ -150,7 +154,10 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     if (r != hipSuccess) return r;
     return wgrad_reduce(kind, part, g->w[layer], g->b[layer], accumulate, s);
   };
-  // layer 5 (64 -> 2)
+  float* bpart = (float*)(p->ws + p->ws_bpart);
+  const int nbslots = ((p->maxW + CONV_TW - 1) / CONV_TW) * ((p->maxH + CONV_TH - 1) / CONV_TH) * p->B;
+  // layer 5 (64 -> 2); its input gradient masked by layer 4's ReLU is layer
+  // 4's pre-activation gradient, whose fp32 sums give layer 4's bias gradient
   e = wg(2, nullptr, act[3], gz, 4);
   if (e == hipSuccess) {
     ConvArgs a = conv_args(p);
@@ -159,8 +166,10 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     a.out_bf16 = gb[0];
     a.wpk = pk_ptr(p, 1, 4);
     a.relu_ref = act[3];
+    a.bias_part = bpart;
     e = conv_launch(0, a, s);
   }
+  if (e == hipSuccess) e = bias_reduce(bpart, nbslots, g->b[3], accumulate, s);
   // layers 4, 3, 2 (64 -> 64)
   int cur = 0;
   for (int l = 3; l >= 1 && e == hipSuccess; --l) {
@@ -172,10 +181,12 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     m.out_bf16 = gb[1 - cur];
     m.wpk = pk_ptr(p, 1, l);
     m.relu_ref = act[l - 1];
+    m.bias_part = bpart;
     {
       KernelTimer kt(p, MRX_KERNEL_CONV_MID, s);
       e = conv_launch(1, m, s);
     }
+    if (e == hipSuccess) e = bias_reduce(bpart, nbslots, g->b[l - 1], accumulate, s);
     cur = 1 - cur;
   }
   // layer 1 (2 -> 64) and the residual

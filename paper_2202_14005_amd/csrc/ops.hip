@@ -32,7 +32,21 @@ mrx_status refresh_desc(mrx_plan_s* p, bool upload) {
   return e == hipSuccess ? MRX_OK : hip_fail(e, "plan: descriptor upload");
 }
 
-CgElemArgs elem_args(mrx_plan_s* p, const float* lam) {
+CgBufs cg_bufs_ws(mrx_plan_s* p) {
+  CgBufs b;
+  b.r = (float2*)(p->ws + p->ws_r);
+  b.p[0] = (float2*)(p->ws + p->ws_p);
+  b.p[1] = (float2*)(p->ws + p->ws_p2);
+  b.q = (float2*)(p->ws + p->ws_q);
+  b.pq = (float*)(p->ws + p->ws_pq);
+  b.rr[0] = (float*)(p->ws + p->ws_rr0);
+  b.rr[1] = (float*)(p->ws + p->ws_rr1);
+  b.stop = (int*)(p->ws + p->ws_stop);
+  b.status = (uint32_t*)(p->ws + p->ws_status);
+  return b;
+}
+
+CgElemArgs elem_args(mrx_plan_s* p, const float* lam, const CgBufs& b) {
   CgElemArgs a{};
   a.desc = p->d_desc;
   a.slices = p->d_all;
@@ -40,10 +54,12 @@ CgElemArgs elem_args(mrx_plan_s* p, const float* lam) {
   a.nrr = p->nrr;
   a.npq = p->npq;
   a.lam = lam;
-  a.stopped = (int*)(p->ws + p->ws_stop);
-  a.status = (uint32_t*)(p->ws + p->ws_status);
+  a.stopped = b.stop;
+  a.status = b.status;
   return a;
 }
+
+CgElemArgs elem_args(mrx_plan_s* p, const float* lam) { return elem_args(p, lam, cg_bufs_ws(p)); }
 
 mrx_status sense_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const float* mask, float2* x,
                           hipStream_t s) {
@@ -80,19 +96,24 @@ mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const fl
   return MRX_OK;
 }
 
-// x = CG_n(A^H A + lam I, aHy + lam z) from x0 = 0.
 mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,
                    const float* lam, int n_iter, float2* x, float* hist, hipStream_t s) {
-  float2* r = (float2*)(p->ws + p->ws_r);
+  return cg_impl(p, cg_bufs_ws(p), aHy, z, S, mask, lam, n_iter, x, hist, s);
+}
+
+// x = CG_n(A^H A + lam I, aHy + lam z) from x0 = 0, on the buffers bb.
+mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const float2* z, const float2* S,
+                   const float* mask, const float* lam, int n_iter, float2* x, float* hist, hipStream_t s) {
+  float2* r = bb.r;
   // p_k lives in pb[k & 1]: the step that forms p_k = r_k + beta p_{k-1}
   // reads the other buffer, so workgroups splitting a tile's coils never
   // see a half-updated p
-  float2* pb[2] = {(float2*)(p->ws + p->ws_p), (float2*)(p->ws + p->ws_p2)};
+  float2* pb[2] = {bb.p[0], bb.p[1]};
   float2* pv = pb[0];
-  float2* q = (float2*)(p->ws + p->ws_q);
-  float* pq = (float*)(p->ws + p->ws_pq);
-  float* rr[2] = {(float*)(p->ws + p->ws_rr0), (float*)(p->ws + p->ws_rr1)};
-  CgElemArgs a = elem_args(p, lam);
+  float2* q = bb.q;
+  float* pq = bb.pq;
+  float* rr[2] = {bb.rr[0], bb.rr[1]};
+  CgElemArgs a = elem_args(p, lam, bb);
   a.aHy = aHy;
   a.z = z;
   a.x = x;

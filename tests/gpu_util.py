@@ -31,3 +31,19 @@ def uneven(shapes, seed0=5000, R=4, kind="vd"):
           for i, (H, W, C) in enumerate(shapes)]
     packed = {k: np.concatenate([s[k].ravel() for s in sl]) for k in sl[0]}
     return sl, packed
+
+
+def maxrel(a, ref):
+    """Largest element error relative to the largest reference magnitude."""
+    a = np.asarray(a).astype(np.complex128).ravel()
+    ref = np.asarray(ref).astype(np.complex128).ravel()
+    return float(np.max(np.abs(a - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def oracle_threads():
+    """Context in which the FP64 oracle's FFTs use every host core (its BLAS
+    calls already do)."""
+    import os
+
+    import scipy.fft
+    return scipy.fft.set_workers(min(16, os.cpu_count() or 1))

@@ -1,9 +1,14 @@
 """Parity of the HIP variational-network stage (fp32) and its reverse pass
 against the FP64 oracle (oracle/vn.py), through the C-ABI.
 
-Tolerances: stage output 1e-4 relative L2 (fp32 filters of 121 taps and a
-31-knot RBF whose width 2/30 amplifies the filter-response rounding by
-~1/sigma); gradients 1e-3.
+Tolerances (fp32 against FP64): the stage output is an operator result,
+bound 1e-5 relative L2 (filter responses are fp32 sums of 242 products,
+~sqrt(242) 2^-24 ~ 1e-6 relative; the RBF's width 2/30 scales that by up to
+~1/sigma = 15 in Phi', and the normal operator adds <= 1e-6).  Gradients
+1e-4: the reverse pass adds Phi'' (another factor ~1/sigma on the rounding of
+the filter responses, ~2e-5) and fixed-order fp32 sums over all pixels for
+the filter and RBF-weight gradients.  Per-pixel errors are bounded relative
+to the largest value at twice the global bounds.
 """
 import numpy as np
 import pytest
@@ -13,12 +18,12 @@ from oracle import sense as osense
 from oracle import vn as ovn
 from paper_2202_14005_amd import ops
 from synthetic import vn_params
-from tests.gpu_util import dev, host, inputs, rel
+from tests.gpu_util import dev, host, inputs, maxrel, oracle_threads, rel
 
 pytestmark = pytest.mark.gpu
 
-OUT_TOL = 1e-4
-GRAD_TOL = 1e-3
+OUT_TOL = 1e-5
+GRAD_TOL = 1e-4
 
 
 def case(B, H, W, C, seed=900, kind="regular", nc=28):
@@ -36,14 +41,17 @@ def test_vn_stage_forward_parity(B, H, W, C):
     t = 0
     xn = plan.vn_stage(dev(aHy), dev(aHy), dev(d["S"]), dev(d["mask"]), dev(p["k"][t]), dev(p["w"][t]),
                        dev(p["lam"][t:t + 1]))
-    ref = ovn.stage(aHy, aHy, d["S"], d["mask"], p["k"][t], p["w"][t], p["lam"][t])
-    e = rel(host(xn), ref)
-    print(f"vn stage {B}x{H}x{W}: rel {e:.2e}")
-    assert e < OUT_TOL
+    with oracle_threads():
+        ref = ovn.stage(aHy, aHy, d["S"], d["mask"], p["k"][t], p["w"][t], p["lam"][t])
+    e, pe = rel(host(xn), ref), maxrel(host(xn), ref)
+    print(f"vn stage {B}x{H}x{W}: rel {e:.2e} per-pixel {pe:.2e}")
+    assert e < OUT_TOL and pe < 2 * OUT_TOL
 
 
-def test_vn_stage_backward_parity():
-    B, H, W, C = 2, 48, 40, 4
+@pytest.mark.parametrize("B,H,W,C", [(2, 48, 40, 4), (1, 384, 320, 15)])
+def test_vn_stage_backward_parity(B, H, W, C):
+    """At 384 x 320 the filter-gradient kernel walks five 64-column chunks
+    and the RBF-weight kernel two 256-column chunks per row band."""
     d, aHy, p = case(B, H, W, C, seed=950)
     t = 1
     rng = np.random.default_rng(4)
@@ -52,12 +60,17 @@ def test_vn_stage_backward_parity():
     plan = ops.Plan(H, W, C, B=B, vn=True)
     gx, (gk, gw, gl) = plan.vn_stage_backward(dev(g), dev(x), dev(aHy), dev(d["S"]), dev(d["mask"]),
                                               dev(p["k"][t]), dev(p["w"][t]), dev(p["lam"][t:t + 1]))
-    rx, rk, rw, rl = ovn.stage_backward(g, x, aHy, d["S"], d["mask"], p["k"][t], p["w"][t], p["lam"][t])
+    with oracle_threads():
+        rx, rk, rw, rl = ovn.stage_backward(g, x, aHy, d["S"], d["mask"], p["k"][t], p["w"][t], p["lam"][t])
     errs = {"g_x": rel(host(gx), rx), "g_k": rel(host(gk), rk), "g_w": rel(host(gw), rw),
             "g_lam": abs(float(host(gl)[0]) - rl) / abs(rl)}
-    print("vn backward", {k: f"{v:.2e}" for k, v in errs.items()})
+    pix = {"g_x": maxrel(host(gx), rx), "g_k": maxrel(host(gk), rk), "g_w": maxrel(host(gw), rw)}
+    print(f"vn backward {B}x{H}x{W}", {k: f"{v:.2e}" for k, v in errs.items()},
+          "per-element", {k: f"{v:.2e}" for k, v in pix.items()})
     for k, v in errs.items():
         assert v < GRAD_TOL, k
+    for k, v in pix.items():
+        assert v < 2 * GRAD_TOL, k
 
 
 def test_vn_stack_forward_backward():
