@@ -163,6 +163,30 @@ mrx_status mrx_cg_dc(mrx_plan plan, const float* aHy, const float* z, const floa
                      float* resid_hist, void* stream);
 
 /*
+ * Allocation-free variant of mrx_cg_dc, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same solve with the same kernels,
+ * bit-identical x and resid_hist, but the CG vectors and partial sums live
+ * in a fixed device array of the library (64 MiB per GPU, held by every GPU
+ * the library runs on until the process ends) instead of the plan's
+ * workspace, which need not be set.  The call allocates nothing.
+ * Requirements: the current device is the plan's device; the plan's CG
+ * buffers, 8 n_image (3 + k) bytes plus per-slice partial sums (k = the
+ * largest coil split of the plan's column schedules, 1..4), fit in 64 MiB
+ * (about 13 slices of 320 x 320 with k = 3), else MRX_EINVAL, nothing
+ * enqueued.  Every call on one GPU shares that GPU's array and overwrites
+ * it: calls that overlap in time on one GPU (different streams, plans or
+ * threads) race.  Status bits of this call (as mrx_status_word's: non-finite
+ * scalar, CG breakdown) start at zero and are copied to dev_flags (device
+ * uint32[B], NULL = skip); the plan's own status word is not touched.
+ * The first call on a device takes the array's device address
+ * (hipGetSymbolAddress), which may load the library's code object there.
+ */
+mrx_status mrx_cg_dc_noalloc(mrx_plan plan, const float* aHy, const float* z, const float* S,
+                             const float* mask, const float* lambda, int32_t n_iter, float* x,
+                             float* resid_hist, uint32_t* dev_flags, void* stream);
+
+/*
  * Reverse-mode pass of mrx_cg_dc (derivatives of the inversion operator
  * S^{-1}: D_y S^{-1} = S^{-1}, D_lambda S^{-1} = -S^{-1} D_lambda S), with the
  * inverse applied by the same CG recipe:

@@ -38,6 +38,7 @@ SIGNATURES = {
     "mrx_sense_normal": (c_int32, [P, P, P, P, P, P, P]),
     "mrx_cg_dc": (c_int32, [P, P, P, P, P, P, c_int32, P, P, P]),
     "mrx_cg_dc_backward": (c_int32, [P, P, P, P, P, P, P, c_int32, P, P, P, c_int32, P]),
+    "mrx_cg_dc_noalloc": (c_int32, [P, P, P, P, P, P, c_int32, P, P, P, P]),
     "mrx_status_word": (c_int32, [P, P, c_int32, P]),
     "mrx_plan_autotune": (c_int32, [P, P, P, P, P, P]),
     "mrx_cnn_set_weights": (c_int32, [P, P, P]),

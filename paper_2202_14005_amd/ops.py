@@ -159,6 +159,20 @@ class Plan:
                               _ptr(x), _ptr(h), _stream(self.device)), "cg_dc")
         return (x, h) if hist else x
 
+    def cg_dc_noalloc(self, aHy, S, mask, lam, n_iter, z=None, out=None, hist=False, flags=None):
+        """cg_dc through the library's allocation-free entry point (fixed
+        device scratch instead of the plan workspace).  ``out``, ``hist`` and
+        ``flags`` (uint32 [B], this call's status bits) may be passed
+        preallocated so that the call itself allocates nothing."""
+        self._img(aHy, "aHy"); self._img(z, "z"); self._coil(S, "S"); self._mask(mask, "mask")
+        lt = self.lam(lam)
+        x = self._img(out, "out") if out is not None else self._empty_img()
+        h = hist if isinstance(hist, torch.Tensor) else (
+            torch.empty((self.B, n_iter + 1), dtype=torch.float32, device=self.device) if hist else None)
+        check(lib().mrx_cg_dc_noalloc(self._h, _ptr(aHy), _ptr(z), _ptr(S), _ptr(mask), _ptr(lt), int(n_iter),
+                                      _ptr(x), _ptr(h), _ptr(flags), _stream(self.device)), "cg_dc_noalloc")
+        return (x, h) if h is not None else x
+
     def cg_dc_backward(self, gx, x, S, mask, lam, n_iter, z=None, need_z=True, need_lam=True):
         """Returns (g_aHy, g_z or None, g_lambda [B] or None)."""
         self._img(gx, "gx"); self._img(x, "x"); self._img(z, "z"); self._coil(S, "S"); self._mask(mask, "mask")
