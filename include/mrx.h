@@ -98,7 +98,11 @@ const char* mrx_last_error(void);
  * each a length the library has a transform schedule for (products of
  * 2, 3 and 5 between 16 and 512 from the built list, see mrx_supported_length),
  * 1 <= C <= 64.  Creates device tables (shape table, twiddles) with hipMalloc
- * on the current device; this is the only allocating call.  Returns
+ * on the current device; this is the only allocating call.  A plan with
+ * several matrix sizes also creates up to three auxiliary streams and their
+ * events: the size groups of one normal-operator application run
+ * concurrently on them, forked from and joined back into the caller's
+ * stream (parallel branches when the stream is being captured).  Returns
  * MRX_EUNSUPPORTED for sizes without a schedule, MRX_EINVAL for bad counts.
  * flags: 0, or MRX_PLAN_NETWORK and/or MRX_PLAN_VN to size the workspace
  * for the MoDL network calls and the VarNet stage calls.
@@ -341,7 +345,8 @@ mrx_status mrx_plan_autotune(mrx_plan plan, const float* S, const float* mask, f
  * `kid` and returns their summed duration in microseconds and their number.
  * Timing adds two event records to each timed launch. */
 enum {
-  MRX_KERNEL_NORMAL = 0,     /* normal operator (plain and CG-fused) */
+  MRX_KERNEL_NORMAL = 0,     /* normal operator (plain and CG-fused): one record per application,
+                                spanning the launches of all size groups */
   MRX_KERNEL_CG_UPDATE = 1,  /* CG update of x, r and the residual partials */
   MRX_KERNEL_CONV_MID = 2,   /* 64 -> 64 denoiser layer (forward and input gradient) */
   MRX_KERNEL_WGRAD_MID = 3,  /* weight gradient of a 64 -> 64 layer */

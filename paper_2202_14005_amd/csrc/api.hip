@@ -219,6 +219,24 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   p->ws_status = take(sizeof(uint32_t) * B);
   p->ws_bytes_base = w;
   p->ws_bytes = w + extra_workspace_bytes(p);
+  // auxiliary streams for concurrent size groups (at most 3: with the
+  // caller's stream that is the four hardware queues a process gets)
+  const size_t naux = std::min<size_t>(p->groups.size() > 1 ? p->groups.size() - 1 : 0, 3);
+  if (naux) {
+    e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    for (size_t j = 0; j < naux && e == hipSuccess; ++j) {
+      hipStream_t st = nullptr;
+      e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e == hipSuccess) p->aux.push_back(st);
+      hipEvent_t ev = nullptr;
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) p->ev_join.push_back(ev);
+    }
+    if (e != hipSuccess) {
+      mrx_plan_destroy(p);
+      return hip_fail(e, "plan_create: auxiliary streams");
+    }
+  }
   *out = p;
   return MRX_OK;
 }
@@ -227,6 +245,9 @@ void mrx_plan_destroy(mrx_plan p) {
   if (!p) return;
   if (p->d_tables) (void)hipFree(p->d_tables);
   for (hipEvent_t e : p->kpool) (void)hipEventDestroy(e);
+  for (hipStream_t st : p->aux) (void)hipStreamDestroy(st);
+  for (hipEvent_t e : p->ev_join) (void)hipEventDestroy(e);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   delete p;
 }
 

@@ -53,6 +53,12 @@ struct mrx_plan_s {
   size_t ws_vn_kt = 0, ws_vn_u = 0, ws_vn_e = 0, ws_vn_kg = 0, ws_vn_s = 0, ws_vn_qx = 0, ws_vn_qg = 0;
   size_t ws_vn_plam = 0, ws_vn_pk = 0, ws_vn_pw = 0;
   bool net_ready = false;
+  // size groups of one operator application run concurrently: groups after
+  // the first on auxiliary streams (default priority) forked from and
+  // joined back to the caller's stream with these events
+  std::vector<hipStream_t> aux;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
   // optional timing of the hot kernels: a pair of events around each launch
   struct KEvent {
     hipEvent_t a, b;
@@ -111,6 +117,41 @@ CgElemArgs elem_args(mrx_plan_s* p, const float* lam);
 CgElemArgs elem_args(mrx_plan_s* p, const float* lam, const CgBufs& b);
 hipError_t clear_status(mrx_plan_s* p, hipStream_t s);
 hipError_t fill_u32(uint32_t* dst, uint32_t value, int64_t n, hipStream_t s);
+
+// Runs fn(group, stream) for every size group of the plan: the first group
+// on s, the others on the plan's auxiliary streams, forked from s before and
+// joined back into s after (parallel branches under graph capture), so that
+// one group's last workgroups overlap the next group's.  With one group (or
+// no auxiliary streams) everything runs on s in order.
+template <class F>
+hipError_t for_groups(mrx_plan_s* p, hipStream_t s, F fn) {
+  const size_t G = p->groups.size();
+  const size_t A = p->aux.size();
+  if (G <= 1 || A == 0) {
+    for (auto& g : p->groups) {
+      hipError_t e = fn(g, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipError_t e = hipEventRecord(p->ev_fork, s);
+  if (e != hipSuccess) return e;
+  for (size_t j = 0; j < A && j + 1 < G; ++j) {
+    e = hipStreamWaitEvent(p->aux[j], p->ev_fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  for (size_t i = 0; i < G; ++i) {
+    e = fn(p->groups[i], i == 0 ? s : p->aux[(i - 1) % A]);
+    if (e != hipSuccess) return e;
+  }
+  for (size_t j = 0; j < A && j + 1 < G; ++j) {
+    e = hipEventRecord(p->ev_join[j], p->aux[j]);
+    if (e != hipSuccess) return e;
+    e = hipStreamWaitEvent(s, p->ev_join[j], 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 mrx_status sense_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const float* mask, float2* x,
                           hipStream_t s);

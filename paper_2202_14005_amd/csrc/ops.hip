@@ -77,7 +77,8 @@ mrx_status sense_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const
 
 mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
                        float2* out, hipStream_t s) {
-  for (auto& g : p->groups) {
+  KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
+  hipError_t e = for_groups(p, s, [&](Group& g, hipStream_t sg) {
     NormalArgs na{};
     na.desc = p->d_desc;
     na.slices = g.d_slices;
@@ -89,11 +90,9 @@ mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const fl
     na.qout = out;
     na.tw = p->tw.at(g.H);
     na.mode = 0;
-    KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
-    hipError_t e = g.col->normal(na, g.W, s);
-    if (e != hipSuccess) return hip_fail(e, "sense_normal");
-  }
-  return MRX_OK;
+    return g.col->normal(na, g.W, sg);
+  });
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "sense_normal");
 }
 
 mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,
@@ -136,32 +135,34 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
       e = cg_hist(a, k, n_iter + 1, s);
       if (e != hipSuccess) return hip_fail(e, "cg: history");
     }
-    for (auto& g : p->groups) {
-      NormalArgs na{};
-      na.desc = p->d_desc;
-      na.slices = g.d_slices;
-      na.nslices = (int)g.slices.size();
-      na.S = S;
-      na.mask = mask;
-      na.lam = lam;
-      na.pin = pb[k == 0 ? 0 : ((k - 1) & 1)];
-      na.qout = q;
-      na.qstride = p->n_image;
-      na.tw = p->tw.at(g.H);
-      na.mode = 1;
-      na.iter = k;
-      na.r = r;
-      na.pout = pb[k & 1];
-      na.rr_cur = rr_cur;
-      na.rr_prev = rr_prev;
-      na.nrr = p->nrr;
-      na.pq_part = pq;
-      na.npq = p->npq;
-      na.stopped = a.stopped;
+    {
       KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
-      e = g.col->normal(na, g.W, s);
-      if (e != hipSuccess) return hip_fail(e, "cg: normal operator");
+      e = for_groups(p, s, [&](Group& g, hipStream_t sg) {
+        NormalArgs na{};
+        na.desc = p->d_desc;
+        na.slices = g.d_slices;
+        na.nslices = (int)g.slices.size();
+        na.S = S;
+        na.mask = mask;
+        na.lam = lam;
+        na.pin = pb[k == 0 ? 0 : ((k - 1) & 1)];
+        na.qout = q;
+        na.qstride = p->n_image;
+        na.tw = p->tw.at(g.H);
+        na.mode = 1;
+        na.iter = k;
+        na.r = r;
+        na.pout = pb[k & 1];
+        na.rr_cur = rr_cur;
+        na.rr_prev = rr_prev;
+        na.nrr = p->nrr;
+        na.pq_part = pq;
+        na.npq = p->npq;
+        na.stopped = a.stopped;
+        return g.col->normal(na, g.W, sg);
+      });
     }
+    if (e != hipSuccess) return hip_fail(e, "cg: normal operator");
     a.rr_cur = rr_cur;
     a.rr_next = rr_prev;  // rho_{k+1} overwrites rho_{k-1}
     a.p = pb[k & 1];

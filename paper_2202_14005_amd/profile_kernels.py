@@ -13,7 +13,12 @@ with --tune, or the default,
 denoiser as MoDL inference runs it (one unroll without CG steps: the fused
 first two layers k_conv_first_mid, two k_conv_mid16, k_conv_last), ``backward`` one reverse
 pass of the denoiser (input gradient and weight gradients, all five
-layers), ``copy`` a device-to-device
+layers), ``uneven`` ``reps`` CG iterations (one CG-fused normal-operator
+launch per matrix size and one CG update each) on the 64-slice uneven batch
+({192^2, 256^2, 320^2, 384 x 320}, 8-20 coils, autotuned schedules; its coil
+maps exceed the MALL), ``uneven_graph`` ``reps`` replays of the captured
+64-slice reconstruction (A^H y, MoDL T = 5, CG-SENSE fallback, judge), for
+kernel traces, ``copy`` a device-to-device
 copy of 256 MiB (256 MiB read, 256 MiB written) whose counter readings
 calibrate FETCH_SIZE and WRITE_SIZE.
 """
@@ -38,6 +43,9 @@ def main():
     ap.add_argument("--what", default="normal,conv,copy")
     ap.add_argument("--schedule", default=None)
     ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--uneven-schedules", default=None,
+                    help="comma-separated column schedules for the uneven batch (one per matrix height), "
+                         "instead of the autotuner's choice")
     a = ap.parse_args()
     what = set(a.what.split(","))
     dev = torch.device("cuda", 0)
@@ -58,6 +66,36 @@ def main():
     gz = torch.randn_like(x)
     if "backward" in what:
         plan.cnn_forward(x, cnn)  # activations for the reverse pass
+    if "uneven" in what or "uneven_graph" in what:
+        from paper_2202_14005_amd.pipeline import Reconstruction
+        from synthetic import uneven_inputs, uneven_specs
+        specs = uneven_specs(5000)
+        _, packed = uneven_inputs(specs, 5000)
+        up = ops.Plan([q[0] for q in specs], [q[1] for q in specs], [q[2] for q in specs], device=dev,
+                      network=True)
+        uS, um = t(packed["S"]), t(packed["mask"])
+        uy = up.sense_fwd(t(packed["x"]), uS, um, noise=t(packed["noise"]))
+        del packed
+        if a.uneven_schedules:
+            for name in a.uneven_schedules.split(","):
+                up.set_schedule(int(name.split("_")[0][1:]), name)
+        else:
+            up.autotune(uS, um)
+        ua = up.sense_adj(uy, uS, um)
+        rec = None
+        if "uneven_graph" in what:
+            rec = Reconstruction(up, ops.CNN.init(7, dev, last_scale=0.1), uy, uS, um, lam=0.05, T=5, n_cg=10,
+                                 ratio=2.0)
+            rec.capture()
+            rec.replay()
+        torch.cuda.synchronize()
+        if "uneven" in what:
+            up.cg_dc(ua, uS, um, up.lam(0.05), a.reps)
+        if rec is not None:
+            for _ in range(a.reps):
+                rec.replay()
+        torch.cuda.synchronize()
+        print("uneven schedules:", sorted({up.schedule(b) for b in range(up.B)}), flush=True)
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
