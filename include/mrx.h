@@ -95,9 +95,10 @@ const char* mrx_last_error(void);
 /*
  * Plan for a batch of B slices with per-slice matrix size H[b] x W[b] and
  * coil count C[b] (host arrays of B entries).  Requirements: H and W even,
- * each a length the library has a transform schedule for (products of
- * 2, 3 and 5 between 16 and 512 from the built list, see mrx_supported_length),
- * 1 <= C <= 64.  Creates device tables (shape table, twiddles) with hipMalloc
+ * each a length the library has a transform schedule for -- every even
+ * length from 8 to 1024 that factors into 2, 3 and 5, except 450, 486, 750,
+ * 810, 900 and 972, whose odd parts no tile of the transform engine fits
+ * (see mrx_supported_length) -- and 1 <= C <= 64.  Creates device tables (shape table, twiddles) with hipMalloc
  * on the current device; this is the only allocating call.  A plan with
  * several matrix sizes also creates up to three auxiliary streams and their
  * events: the size groups of one normal-operator application run

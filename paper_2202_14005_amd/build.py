@@ -106,6 +106,59 @@ SCHEDULES = [
     ("n384_4x4x24_t16_w8_rl_k3", 4, 4, 24, 16, 8, 16, 1, 0, 0, 3),
 ]
 
+
+
+def _smooth235(n: int) -> bool:
+    for f in (2, 3, 5):
+        while n % f == 0:
+            n //= f
+    return n == 1
+
+
+def generic_schedule(N: int):
+    """A default schedule for a length without a tuned one: N = N1 N2 N3
+    (each at most 40, composed from the 2/3/4/5 codelets), T threads per
+    transform dividing every level's transform count, P = N / T <= 64 points
+    per thread, a column tile of WT columns with T WT a whole number of
+    wavefronts (the CG dot products reduce over full wavefronts) and at most
+    1024 threads, and the normal operator's LDS (N WT complex values plus the
+    twiddle and mask tables) within 150 KB.  Preference: fewest points per
+    thread (at least 12), power-of-two T, three levels, narrow tiles.
+    Coil values are re-read for the conjugate multiply (registers go to the
+    points).  None if no decomposition fits."""
+    import math
+    divs = lambda n: [d for d in range(1, n + 1) if n % d == 0]
+    best = None
+    for n1 in divs(N):
+        for n2 in divs(N // n1):
+            n3 = N // n1 // n2
+            if n1 < 2 or n2 < 2 or max(n1, n2, n3) > 40:
+                continue
+            g = math.gcd(math.gcd(N // n1, N // n2), N // n3)
+            for t in divs(g):
+                P = N // t
+                if P > 64 or t > 64:
+                    continue
+                for wt in (8, 16, 32, 64):
+                    if (t * wt) % 64 or t * wt > 1024 or N * wt * 8 + N * 12 > 150 * 1024:
+                        continue
+                    score = (max(P, 12), 0 if t & (t - 1) == 0 else 1, 0 if n3 > 1 else 1, wt)
+                    if best is None or score < best[0]:
+                        best = (score, (n1, n2, n3, t, wt))
+                    break
+    if best is None:
+        return None
+    n1, n2, n3, t, wt = best[1]
+    return (f"n{N}_{n1}x{n2}x{n3}_t{t}_w{wt}_rl_gen", n1, n2, n3, t, wt, wt, 1, 0)
+
+
+# every even length from 8 to 1024 that factors into 2, 3 and 5 and has no
+# tuned schedule above gets a generic one (if a decomposition fits)
+_TUNED = {e[1] * e[2] * e[3] for e in SCHEDULES}
+GENERIC_SCHEDULES = [g for g in (generic_schedule(n) for n in range(8, 1025, 2)
+                                 if _smooth235(n) and n not in _TUNED) if g]
+SCHEDULES = SCHEDULES + GENERIC_SCHEDULES
+
 COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net.hip", "conv.hip",
                   "conv_wgrad.hip", "vn.hip", "judge.hip"]
 

@@ -32,8 +32,9 @@ def test_version_string():
     assert _lib.lib().mrx_version().decode().startswith("mrx")
 
 
-@pytest.mark.parametrize("n,ok", [(128, 1), (320, 1), (384, 1), (192, 1), (256, 1), (16, 1),
-                                  (14, 0), (7, 0), (1024, 0), (330, 0)])
+@pytest.mark.parametrize("n,ok", [(128, 1), (320, 1), (384, 1), (192, 1), (256, 1), (16, 1), (8, 1), (10, 1),
+                                  (240, 1), (288, 1), (640, 1), (1024, 1), (54, 1),
+                                  (14, 0), (7, 0), (1026, 0), (1152, 0), (330, 0), (6, 0), (450, 0), (972, 0)])
 def test_supported_lengths(n, ok):
     assert _lib.lib().mrx_supported_length(n) == ok
 
