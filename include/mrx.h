@@ -106,7 +106,11 @@ const char* mrx_last_error(void);
  * stream (parallel branches when the stream is being captured).  Returns
  * MRX_EUNSUPPORTED for sizes without a schedule, MRX_EINVAL for bad counts.
  * flags: 0, or MRX_PLAN_NETWORK and/or MRX_PLAN_VN to size the workspace
- * for the MoDL network calls and the VarNet stage calls.
+ * for the MoDL network calls and the VarNet stage calls.  The column
+ * schedule of each size group comes from the in-process tuning cache
+ * (filled by mrx_plan_autotune and mrx_tune_cache_load) when it holds an
+ * entry for the group's (H, W, C, slice count), else the length's default;
+ * the cache is process state rather than an argument of this call.
  */
 mrx_status mrx_plan_create(mrx_plan* plan, int32_t B, const int32_t* H, const int32_t* W,
                            const int32_t* C, uint32_t flags);
@@ -238,8 +242,16 @@ mrx_status mrx_status_word(mrx_plan plan, uint32_t* dev_flags, int32_t clear, vo
  * layer activations are stored as bf16.  Needs a plan created with
  * MRX_PLAN_NETWORK.
  *
- * mrx_cnn_set_weights packs bf16 copies of the weights into the workspace;
- * call it again after every weight update.  It keeps the bias pointers.
+ * The weights are plan state, not arguments of the network calls
+ * (mrx_cnn_forward/backward/layer_forward, mrx_modl_forward/backward):
+ * mrx_cnn_set_weights packs bf16 copies of the five weight tensors into the
+ * plan's workspace and keeps the five fp32 bias pointers.  Every later
+ * network call on the plan uses those packed copies, so a weight update is
+ * not seen until mrx_cnn_set_weights is called again (the Python binding
+ * does so whenever the weights' version counter changed); the biases are
+ * read through the kept pointers at each call, so they must stay valid and
+ * in-place updates of them are seen at once.  Packing is enqueued on
+ * `stream`: calls on other streams must be ordered after it.
  */
 mrx_status mrx_cnn_set_weights(mrx_plan plan, const mrx_cnn_params* w, void* stream);
 /* z = x + N(x) (image-sized complex, must not alias). */
