@@ -16,6 +16,8 @@ from .generators import (  # noqa: F401
     vn_params,
     slice_inputs,
     batch_inputs,
+    soft_slice_inputs,
+    soft_batch_inputs,
     uneven_specs,
     uneven_inputs,
     UNEVEN_SHAPES,

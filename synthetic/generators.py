@@ -180,6 +180,39 @@ def slice_inputs(seed: int, H: int, W: int, C: int, R: int, n_center: int,
     }
 
 
+def soft_slice_inputs(seed: int, H: int, W: int, C: int, R: int, n_center: int,
+                      mask_kind: str = "vd", sigma: float = 1e-3):
+    """One slice whose object is larger than the field of view along H (the
+    reduced-FOV setting of the paper's soft-SENSE experiment), laid out for
+    two sets of coil maps: phantom and coil maps are drawn on a 2H x W grid;
+    the field of view is its central H rows and the other H rows are the
+    ones that alias into it.  Returns x [2, H, W] (set 0: the field of view,
+    set 1: the aliasing rows, row i of set 1 being extended row
+    (i + 3H/2) mod 2H), S [2, C, H, W] arranged the same way, mask [H] and
+    noise [C, H, W] for the H-row k-space.  Only draws and index
+    rearrangements (rolls and slices) happen here."""
+    xe = phantom(seed, 2 * H, W)
+    Se = coil_maps(seed + 7919, C, 2 * H, W)
+    xr = np.roll(xe, -(H // 2), axis=0)
+    Sr = np.roll(Se, -(H // 2), axis=1)
+    return {
+        "x": np.ascontiguousarray(np.stack([xr[:H], xr[H:]])),
+        "S": np.ascontiguousarray(np.stack([Sr[:, :H], Sr[:, H:]])),
+        "mask": pe_mask(seed + 15485863, H, R, n_center, mask_kind),
+        "noise": kspace_noise(seed + 32452843, C, H, W, sigma),
+        "x_ext": xe,
+        "S_ext": Se,
+    }
+
+
+def soft_batch_inputs(seeds, H: int, W: int, C: int, R: int, n_center: int,
+                      mask_kind: str = "vd", sigma: float = 1e-3):
+    """Stack ``soft_slice_inputs``: x [B,2,H,W], S [B,2,C,H,W], mask [B,H],
+    noise [B,C,H,W] (and the extended x_ext [B,2H,W], S_ext [B,C,2H,W])."""
+    sl = [soft_slice_inputs(s, H, W, C, R, n_center, mask_kind, sigma) for s in seeds]
+    return {k: np.stack([d[k] for d in sl]) for k in sl[0]}
+
+
 def batch_inputs(seeds, H: int, W: int, C: int, R: int, n_center: int,
                  mask_kind: str = "vd", sigma: float = 1e-3):
     """Stack ``slice_inputs`` over ``seeds``: x [B,H,W], S [B,C,H,W], mask [B,H],
