@@ -60,6 +60,7 @@ typedef struct mrx_plan_s* mrx_plan;
 /* mrx_plan_create flags */
 #define MRX_PLAN_NETWORK 1u /* also reserve workspace for the CNN / MoDL calls */
 #define MRX_PLAN_VN 2u      /* also reserve workspace for the VarNet stage calls */
+#define MRX_PLAN_SOFT_SENSE 4u /* two sets of coil maps (soft-SENSE); see mrx_soft_* */
 
 /*
  * Parameters of one variational-network stage (device pointers): k = 24
@@ -211,6 +212,29 @@ mrx_status mrx_cg_dc_backward(mrx_plan plan, const float* gx, const float* x, co
                               int32_t accumulate, void* stream);
 
 /*
+ * Soft-SENSE: the SENSE model with two sets of coil maps (Extensions to the
+ * SENSE-Model subsection), for objects larger than the field of view:
+ *   y_c = P F (S_{0,c} x_0 + S_{1,c} x_1),  (A^H y)_m = sum_c conj(S_{m,c}) F^H P^H y_c.
+ * Needs a plan created with MRX_PLAN_SOFT_SENSE (not with MRX_PLAN_VN).
+ * Layout per slice b: images [2][H][W] at 2 x (the SENSE image offset),
+ * maps [2][C][H][W] at 2 x (the SENSE coil offset), k-space [C][H][W] and
+ * mask as for SENSE; for an even batch x is [B][2][H][W] and S
+ * [B][2][C][H][W].  The calls mirror mrx_sense_fwd / _adj / _normal and
+ * mrx_cg_dc on these layouts (same arguments, same workspace and status
+ * rules); the CG inner products run over both sets of a slice.  The column
+ * transforms use each length's default decomposition.
+ */
+mrx_status mrx_soft_sense_fwd(mrx_plan plan, const float* x, const float* S, const float* mask,
+                              const float* noise, float* y, void* stream);
+mrx_status mrx_soft_sense_adj(mrx_plan plan, const float* y, const float* S, const float* mask,
+                              float* x, void* stream);
+mrx_status mrx_soft_sense_normal(mrx_plan plan, const float* x, const float* S, const float* mask,
+                                 const float* lambda, float* out, void* stream);
+mrx_status mrx_soft_cg_dc(mrx_plan plan, const float* aHy, const float* z, const float* S,
+                          const float* mask, const float* lambda, int32_t n_iter, float* x,
+                          float* resid_hist, void* stream);
+
+/*
  * Fallback and judge for a learned reconstruction.  x_cg is the plain
  * Tikhonov CG-SENSE solution (mrx_cg_dc with z = NULL), the reconstruction
  * MoDL reduces to without its denoiser (eq. update_modl with lambda z = 0).
@@ -297,6 +321,35 @@ mrx_status mrx_modl_backward(mrx_plan plan, const float* g_out, const float* sta
                              const float* S, const float* mask, const float* lambda, int32_t T,
                              int32_t n_cg, const mrx_cnn_grads* g, float* g_lambda, float* g_aHy,
                              int32_t accumulate, void* stream);
+
+/*
+ * MoDL with the soft-SENSE operator (two map sets, plan created with
+ * MRX_PLAN_SOFT_SENSE | MRX_PLAN_NETWORK): as mrx_modl_forward/backward, but
+ * the network block updates the first set's image only,
+ *   z^t = (D(x_0^t), x_1^t),  x^{t+1} = (A^H A + lambda I)^{-1} (aHy + lambda z^t),
+ * with images in the soft layout ([2][H][W] per slice) and the CG over both
+ * sets; the reverse pass differentiates the soft CG blocks by a second soft
+ * CG solve and the denoiser on the first set.  states: (T + 1) soft images.
+ * Same weight, workspace and error rules as the SENSE calls.
+ */
+mrx_status mrx_soft_modl_forward(mrx_plan plan, const float* aHy, const float* S, const float* mask,
+                                 const float* lambda, int32_t T, int32_t n_cg, float* x_out,
+                                 float* states, void* stream);
+mrx_status mrx_soft_modl_backward(mrx_plan plan, const float* g_out, const float* states,
+                                  const float* aHy, const float* S, const float* mask,
+                                  const float* lambda, int32_t T, int32_t n_cg,
+                                  const mrx_cnn_grads* g, float* g_lambda, float* g_aHy,
+                                  int32_t accumulate, void* stream);
+/*
+ * The training loss of the soft-SENSE networks: the MSE on the coil images
+ * (they do not depend on how the map sets split the object),
+ *   loss = mean over all coil pixels |S_{0,c} x_0 + S_{1,c} x_1 - ref_c|^2,
+ *   g_m = sum_c conj(S_{m,c}) 2 (S_{0,c} x_0 + S_{1,c} x_1 - ref_c) / n_coil_pixels.
+ * x, g: soft images; S: soft maps; ref: coil images (coil sized, the SENSE
+ * k-space layout).  g and loss (device float[1]) may be NULL.
+ */
+mrx_status mrx_soft_coil_mse_grad(mrx_plan plan, const float* x, const float* S, const float* ref,
+                                  float* g, float* loss, void* stream);
 
 /*
  * MSE loss of eq. network_optimize over all packed pixels:

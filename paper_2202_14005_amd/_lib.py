@@ -39,6 +39,13 @@ SIGNATURES = {
     "mrx_cg_dc": (c_int32, [P, P, P, P, P, P, c_int32, P, P, P]),
     "mrx_cg_dc_backward": (c_int32, [P, P, P, P, P, P, P, c_int32, P, P, P, c_int32, P]),
     "mrx_cg_dc_noalloc": (c_int32, [P, P, P, P, P, P, c_int32, P, P, P, P]),
+    "mrx_soft_sense_fwd": (c_int32, [P, P, P, P, P, P, P]),
+    "mrx_soft_sense_adj": (c_int32, [P, P, P, P, P, P]),
+    "mrx_soft_sense_normal": (c_int32, [P, P, P, P, P, P, P]),
+    "mrx_soft_cg_dc": (c_int32, [P, P, P, P, P, P, c_int32, P, P, P]),
+    "mrx_soft_modl_forward": (c_int32, [P, P, P, P, P, c_int32, c_int32, P, P, P]),
+    "mrx_soft_modl_backward": (c_int32, [P, P, P, P, P, P, P, c_int32, c_int32, P, P, P, c_int32, P]),
+    "mrx_soft_coil_mse_grad": (c_int32, [P, P, P, P, P, P, P]),
     "mrx_status_word": (c_int32, [P, P, c_int32, P]),
     "mrx_plan_autotune": (c_int32, [P, P, P, P, P, P]),
     "mrx_cnn_set_weights": (c_int32, [P, P, P]),

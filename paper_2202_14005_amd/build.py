@@ -180,13 +180,20 @@ def _jobs():
     jobs = []
     for s in srcs:
         jobs.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".hip", ".o")), []))
+    soft_done = set()
     for entry in SCHEDULES:
         name, n1, n2, n3, t, wtc, wtr, g, ks = entry[:9]
         wl = entry[9] if len(entry) > 9 else 0
         kspl = entry[10] if len(entry) > 10 else 1
+        # the first column-tiled schedule of each length also carries the
+        # length's soft-SENSE kernels
+        n = n1 * n2 * n3
+        soft = int(not wl and n not in soft_done)
+        if soft:
+            soft_done.add(n)
         defs = [f"-DMRX_N1={n1}", f"-DMRX_N2={n2}", f"-DMRX_N3={n3}", f"-DMRX_T={t}",
                 f"-DMRX_WTC={wtc}", f"-DMRX_WTR={wtr}", f"-DMRX_G={g}", f"-DMRX_KS={ks}",
-                f"-DMRX_WL={wl}", f"-DMRX_KSPL={kspl}", f'-DMRX_NAME="{name}"']
+                f"-DMRX_WL={wl}", f"-DMRX_KSPL={kspl}", f"-DMRX_SOFT={soft}", f'-DMRX_NAME="{name}"']
         jobs.append((os.path.join(CSRC, "sense_inst.hip"), os.path.join(BUILD, f"sched_{name}.o"), defs))
     return jobs
 

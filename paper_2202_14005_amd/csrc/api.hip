@@ -57,6 +57,16 @@ static std::vector<RowVariant>& row_registry() {
   static std::vector<RowVariant> v;
   return v;
 }
+static std::vector<SoftVariant>& soft_registry() {
+  static std::vector<SoftVariant> v;
+  return v;
+}
+void register_soft_variant(const SoftVariant& v) { soft_registry().push_back(v); }
+const SoftVariant* find_soft(int N) {
+  for (auto& v : soft_registry())
+    if (v.N == N) return &v;
+  return nullptr;
+}
 void register_col_variant(const ColVariant& v) { col_registry().push_back(v); }
 void register_row_variant(const RowVariant& v) { row_registry().push_back(v); }
 
@@ -103,10 +113,14 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   *out = nullptr;
   if (B <= 0 || B > (1 << 20)) return fail(MRX_EINVAL, "plan_create: batch size must be in [1, 2^20]");
   if (!H || !W || !C) return fail(MRX_EINVAL, "plan_create: null shape array");
-  if (flags & ~(MRX_PLAN_NETWORK | MRX_PLAN_VN)) return fail(MRX_EINVAL, "plan_create: unknown flags");
+  if (flags & ~(MRX_PLAN_NETWORK | MRX_PLAN_VN | MRX_PLAN_SOFT_SENSE))
+    return fail(MRX_EINVAL, "plan_create: unknown flags");
+  if ((flags & MRX_PLAN_SOFT_SENSE) && (flags & MRX_PLAN_VN))
+    return fail(MRX_EINVAL, "plan_create: soft-SENSE plans have no VarNet workspace");
   auto* p = new mrx_plan_s();
   p->B = B;
   p->flags = flags;
+  p->sets = (flags & MRX_PLAN_SOFT_SENSE) ? 2 : 1;
   int64_t xo = 0, so = 0, mo = 0;
   for (int b = 0; b < B; ++b) {
     const int h = H[b], w = W[b], c = C[b];
@@ -158,15 +172,22 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
       if (!g.col) g.col = find_col(g.H, nullptr);
       g.rowW = find_row(g.W);
       g.rowH = find_row(g.H);
+      g.soft = find_soft(g.H);
     }
   }
+  if (p->sets > 1)
+    for (auto& g : p->groups)
+      if (!g.soft) {
+        delete p;
+        return fail(MRX_EUNSUPPORTED, "plan_create: no soft-SENSE kernels for H = " + std::to_string(g.H));
+      }
   refresh_desc(p, false);
   p->npq = (p->maxW + 1) / 2;  // upper bound on column tiles x coil split (tile width >= 8)
-  p->nrr = (int)((p->maxHW + CG_EPB - 1) / CG_EPB);
+  p->nrr = (int)((p->sets * p->maxHW + CG_EPB - 1) / CG_EPB);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { delete p; return hip_fail(e, "plan_create: hipGetDevice"); }
   // device tables
-  size_t tb = align256(sizeof(SliceDesc) * B) + align256(sizeof(int) * B) * (p->groups.size() + 1);
+  size_t tb = 2 * align256(sizeof(SliceDesc) * B) + align256(sizeof(int) * B) * (p->groups.size() + 1);
   std::vector<int> lens;
   for (auto& g : p->groups) {
     if (std::find(lens.begin(), lens.end(), g.H) == lens.end()) lens.push_back(g.H);
@@ -180,6 +201,19 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   std::memcpy(host.data() + off, p->desc.data(), sizeof(SliceDesc) * B);
   p->d_desc = (SliceDesc*)((char*)p->d_tables + off);
   off += align256(sizeof(SliceDesc) * B);
+  {
+    // the CG element kernels' view of a slice: sets x H x W entries at
+    // sets x xoff, no partial planes
+    std::vector<SliceDesc> dv(p->desc);
+    for (auto& d : dv) {
+      d.H *= p->sets;
+      d.xoff *= p->sets;
+      d.nq = 1;
+    }
+    std::memcpy(host.data() + off, dv.data(), sizeof(SliceDesc) * B);
+    p->d_desc_soft = (SliceDesc*)((char*)p->d_tables + off);
+    off += align256(sizeof(SliceDesc) * B);
+  }
   std::vector<int> all(B);
   for (int b = 0; b < B; ++b) all[b] = b;
   std::memcpy(host.data() + off, all.data(), sizeof(int) * B);
@@ -206,11 +240,12 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   size_t w = 0;
   auto take = [&](size_t bytes) { size_t o = w; w += align256(bytes); return o; };
   p->ws_tmp = take(sizeof(float2) * p->n_coil);
-  p->ws_r = take(sizeof(float2) * p->n_image);
-  p->ws_p = take(sizeof(float2) * p->n_image);
-  p->ws_p2 = take(sizeof(float2) * p->n_image);
-  p->ws_q = take(sizeof(float2) * p->n_image * KSPL_MAX);
-  p->ws_v = take(sizeof(float2) * p->n_image);
+  const int64_t nimg = p->n_image * p->sets;  // CG vectors hold every set
+  p->ws_r = take(sizeof(float2) * nimg);
+  p->ws_p = take(sizeof(float2) * nimg);
+  p->ws_p2 = take(sizeof(float2) * nimg);
+  p->ws_q = take(sizeof(float2) * nimg * KSPL_MAX);
+  p->ws_v = take(sizeof(float2) * nimg);
   p->ws_pq = take(sizeof(float) * B * p->npq);
   p->ws_rr0 = take(sizeof(float) * B * p->nrr);
   p->ws_rr1 = take(sizeof(float) * B * p->nrr);
@@ -374,6 +409,50 @@ mrx_status mrx_cg_dc_backward(mrx_plan p, const float* gx, const float* x, const
     }
   }
   return MRX_OK;
+}
+
+static mrx_status soft_ready(mrx_plan p, const char* who) {
+  if (!p) return fail(MRX_EINVAL, std::string(who) + ": null plan");
+  if (p->sets < 2) return fail(MRX_EINVAL, std::string(who) + ": plan was created without MRX_PLAN_SOFT_SENSE");
+  return MRX_OK;
+}
+
+mrx_status mrx_soft_sense_fwd(mrx_plan p, const float* x, const float* S, const float* mask, const float* noise,
+                              float* y, void* stream) {
+  mrx_status st = soft_ready(p, "soft_sense_fwd");
+  if (st != MRX_OK) return st;
+  if (!x || !S || !mask || !y) return fail(MRX_EINVAL, "soft_sense_fwd: null data pointer");
+  return soft_fwd_impl(p, (const float2*)x, (const float2*)S, mask, (const float2*)noise, (float2*)y,
+                       (hipStream_t)stream);
+}
+
+mrx_status mrx_soft_sense_adj(mrx_plan p, const float* y, const float* S, const float* mask, float* x,
+                              void* stream) {
+  mrx_status st = soft_ready(p, "soft_sense_adj");
+  if (st != MRX_OK) return st;
+  if (!y || !S || !mask || !x) return fail(MRX_EINVAL, "soft_sense_adj: null data pointer");
+  if (!p->ws) return fail(MRX_ENOWORKSPACE, "soft_sense_adj: workspace not set");
+  return soft_adj_impl(p, (const float2*)y, (const float2*)S, mask, (float2*)x, (hipStream_t)stream);
+}
+
+mrx_status mrx_soft_sense_normal(mrx_plan p, const float* x, const float* S, const float* mask,
+                                 const float* lambda, float* out, void* stream) {
+  mrx_status st = soft_ready(p, "soft_sense_normal");
+  if (st != MRX_OK) return st;
+  if (!x || !S || !mask || !out) return fail(MRX_EINVAL, "soft_sense_normal: null data pointer");
+  if (x == out) return fail(MRX_EINVAL, "soft_sense_normal: input and output must not alias");
+  return soft_normal_impl(p, (const float2*)x, (const float2*)S, mask, lambda, (float2*)out, (hipStream_t)stream);
+}
+
+mrx_status mrx_soft_cg_dc(mrx_plan p, const float* aHy, const float* z, const float* S, const float* mask,
+                          const float* lambda, int32_t n_iter, float* x, float* hist, void* stream) {
+  mrx_status st = soft_ready(p, "soft_cg_dc");
+  if (st != MRX_OK) return st;
+  if (!aHy || !S || !mask || !lambda || !x) return fail(MRX_EINVAL, "soft_cg_dc: null data pointer");
+  if (n_iter < 0 || n_iter > 100000) return fail(MRX_EINVAL, "soft_cg_dc: n_iter out of range");
+  if (!p->ws) return fail(MRX_ENOWORKSPACE, "soft_cg_dc: workspace not set");
+  return cg_impl(p, cg_bufs_ws(p), (const float2*)aHy, (const float2*)z, (const float2*)S, mask, lambda, n_iter,
+                 (float2*)x, hist, (hipStream_t)stream, /*soft=*/true);
 }
 
 mrx_status mrx_status_word(mrx_plan p, uint32_t* dev_flags, int32_t clear, void* stream) {

@@ -20,6 +20,7 @@ struct Group {
   const ColVariant* col = nullptr;   // transform along H (column pass)
   const RowVariant* rowW = nullptr;  // transform along W (row pass)
   const RowVariant* rowH = nullptr;
+  const SoftVariant* soft = nullptr;  // soft-SENSE kernels (plans with two map sets)
 };
 
 }  // namespace mrx
@@ -33,6 +34,12 @@ struct mrx_plan_s {
   int64_t maxHW = 0;
   int64_t n_image = 0, n_coil = 0, n_mask = 0;
   int npq = 0, nrr = 0;
+  // coil-map sets: 1 (SENSE) or 2 (soft-SENSE, MRX_PLAN_SOFT_SENSE); image
+  // vectors of the CG and of the networks then hold sets x H x W per slice,
+  // described by d_desc_soft (H x sets rows, offset sets x xoff) for the
+  // CG element kernels
+  int sets = 1;
+  mrx::SliceDesc* d_desc_soft = nullptr;
   // device tables (plan owned)
   void* d_tables = nullptr;
   mrx::SliceDesc* d_desc = nullptr;
@@ -48,6 +55,7 @@ struct mrx_plan_s {
   size_t ws_act[4] = {0, 0, 0, 0}, ws_gact[2] = {0, 0};
   size_t ws_z = 0, ws_ximg[2] = {0, 0}, ws_gimg[2] = {0, 0}, ws_vimg = 0;
   size_t ws_pk = 0, ws_wpart = 0, ws_bpart = 0, ws_loss = 0;
+  size_t ws_s1[3] = {0, 0, 0};  // soft-SENSE: first-set images in the SENSE layout (denoiser in/out)
   const float* net_b[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   // VarNet workspace
   size_t ws_vn_kt = 0, ws_vn_u = 0, ws_vn_e = 0, ws_vn_kg = 0, ws_vn_s = 0, ws_vn_qx = 0, ws_vn_qg = 0;
@@ -88,6 +96,7 @@ class KernelTimer {
 mrx_status hip_fail(hipError_t e, const char* what);
 const ColVariant* find_col(int N, const char* name);
 const RowVariant* find_row(int N);
+const SoftVariant* find_soft(int N);
 std::vector<const ColVariant*> col_variants(int N);
 
 extern std::mutex g_tune_mu;
@@ -114,7 +123,7 @@ struct CgBufs {
 // The plan workspace's CG buffers.
 CgBufs cg_bufs_ws(mrx_plan_s* p);
 CgElemArgs elem_args(mrx_plan_s* p, const float* lam);
-CgElemArgs elem_args(mrx_plan_s* p, const float* lam, const CgBufs& b);
+CgElemArgs elem_args(mrx_plan_s* p, const float* lam, const CgBufs& b, bool soft = false);
 hipError_t clear_status(mrx_plan_s* p, hipStream_t s);
 hipError_t fill_u32(uint32_t* dst, uint32_t value, int64_t n, hipStream_t s);
 
@@ -160,6 +169,15 @@ mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const fl
 mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,
                    const float* lam, int n_iter, float2* x, float* hist, hipStream_t s);
 mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bufs, const float2* aHy, const float2* z, const float2* S,
-                   const float* mask, const float* lam, int n_iter, float2* x, float* hist, hipStream_t s);
+                   const float* mask, const float* lam, int n_iter, float2* x, float* hist, hipStream_t s,
+                   bool soft = false);
+// soft-SENSE (two map sets): forward, adjoint and normal operators, CG on the
+// plan workspace
+mrx_status soft_fwd_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float2* noise,
+                         float2* y, hipStream_t s);
+mrx_status soft_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const float* mask, float2* x,
+                         hipStream_t s);
+mrx_status soft_normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
+                            float2* out, hipStream_t s);
 
 }  // namespace mrx

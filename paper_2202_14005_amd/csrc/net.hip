@@ -30,10 +30,13 @@ size_t net_workspace_bytes(mrx_plan_s* p) {
   auto take = [&](size_t bytes) { size_t o = p->ws_bytes_base + w; w += al(bytes); return o; };
   for (int i = 0; i < 4; ++i) p->ws_act[i] = take(ni * CNN_F * 2);
   for (int i = 0; i < 2; ++i) p->ws_gact[i] = take(ni * CNN_F * 2);
-  p->ws_z = take(ni * 8);
-  for (int i = 0; i < 2; ++i) p->ws_ximg[i] = take(ni * 8);
-  for (int i = 0; i < 2; ++i) p->ws_gimg[i] = take(ni * 8);
-  p->ws_vimg = take(ni * 8);
+  const size_t ns = ni * (size_t)p->sets;  // network images of soft-SENSE plans hold every set
+  p->ws_z = take(ns * 8);
+  for (int i = 0; i < 2; ++i) p->ws_ximg[i] = take(ns * 8);
+  for (int i = 0; i < 2; ++i) p->ws_gimg[i] = take(ns * 8);
+  p->ws_vimg = take(ns * 8);
+  if (p->sets > 1)
+    for (int i = 0; i < 3; ++i) p->ws_s1[i] = take(ni * 8);
   p->ws_pk = take((size_t)2 * (PK_FIRST + 3 * PK_MID + PK_LAST) * 2);
   size_t wpart = 0;
   for (int k = 0; k < 3; ++k) wpart = std::max(wpart, (size_t)wgrad_slots(k) * wgrad_nout(k));
@@ -428,6 +431,78 @@ mrx_status mrx_modl_backward(mrx_plan p, const float* g_out, const float* states
   return MRX_OK;
 }
 
+// ------------------------------------------------------------ soft-SENSE
+// Images of soft-SENSE plans hold [2][H][W] per slice at 2 xoff.  The
+// network block updates the first set's image only: it is taken out into the
+// SENSE layout, denoised, and put back beside the unchanged second set.
+
+// dst[xoff + i] = src[2 xoff + i]: the first set's image of every slice.
+__global__ void k_soft_take(const SliceDesc* desc, int B, const float2* src, float2* dst) {
+  const int b = blockIdx.y;
+  if (b >= B) return;
+  const SliceDesc d = desc[b];
+  const int64_t n = (int64_t)d.H * d.W;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[d.xoff + i] = src[2 * d.xoff + i];
+}
+// out = (first, second's second set): out[2 xoff + i] = first[xoff + i],
+// out[2 xoff + n + i] = second[2 xoff + n + i].
+__global__ void k_soft_merge(const SliceDesc* desc, int B, const float2* first, const float2* second, float2* out) {
+  const int b = blockIdx.y;
+  if (b >= B) return;
+  const SliceDesc d = desc[b];
+  const int64_t n = (int64_t)d.H * d.W;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    out[2 * d.xoff + i] = first[d.xoff + i];
+    out[2 * d.xoff + n + i] = second[2 * d.xoff + n + i];
+  }
+}
+static hipError_t soft_take(mrx_plan_s* p, const float2* src, float2* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_soft_take, dim3(64, p->B), dim3(256), 0, s, p->d_desc, p->B, src, dst);
+  return hipGetLastError();
+}
+static hipError_t soft_merge(mrx_plan_s* p, const float2* first, const float2* second, float2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_soft_merge, dim3(64, p->B), dim3(256), 0, s, p->d_desc, p->B, first, second, out);
+  return hipGetLastError();
+}
+
+// MSE on the coil images sum_m S_{m,c} x_m against ref (coil sized), its
+// gradient g_m = sum_c conj(S_{m,c}) 2 (coil_c - ref_c) scale, and per-block
+// partial sums of the squared error (block = CG_EPB pixels of a slice).
+__global__ void __launch_bounds__(256) k_soft_coil_mse(const SliceDesc* desc, const float2* x, const float2* S,
+                                                       const float2* ref, float2* g, float* part, int nrr,
+                                                       float scale) {
+  __shared__ float red[4];
+  const int b = blockIdx.y;
+  const SliceDesc d = desc[b];
+  const int64_t n = (int64_t)d.H * d.W;
+  float acc = 0.f;
+  const int64_t base = (int64_t)blockIdx.x * CG_EPB;
+  for (int k = threadIdx.x; k < CG_EPB; k += 256) {
+    const int64_t i = base + k;
+    if (i >= n) break;
+    const float2 x0 = x[2 * d.xoff + i], x1 = x[2 * d.xoff + n + i];
+    float2 g0 = make_float2(0.f, 0.f), g1 = make_float2(0.f, 0.f);
+    for (int c = 0; c < d.C; ++c) {
+      const float2 s0 = S[2 * d.soff + (int64_t)c * n + i], s1 = S[2 * d.soff + (int64_t)(d.C + c) * n + i];
+      const float2 r = ref[d.soff + (int64_t)c * n + i];
+      const float2 u = csub(cadd(cmul(s0, x0), cmul(s1, x1)), r);
+      acc += u.x * u.x + u.y * u.y;
+      g0 = cadd(g0, cmulc(s0, u));
+      g1 = cadd(g1, cmulc(s1, u));
+    }
+    if (g) {
+      g[2 * d.xoff + i] = cscale(g0, 2.f * scale);
+      g[2 * d.xoff + n + i] = cscale(g1, 2.f * scale);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)b * nrr + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 mrx_status mrx_mse_grad(mrx_plan p, const float* x, const float* ref, float* g, float* loss, void* stream) {
   if (!p) return fail(MRX_EINVAL, "mse_grad: null plan");
   if (!x || !ref) return fail(MRX_EINVAL, "mse_grad: null data pointer");
@@ -444,6 +519,138 @@ mrx_status mrx_mse_grad(mrx_plan p, const float* x, const float* ref, float* g, 
     e = hipGetLastError();
   }
   return e == hipSuccess ? MRX_OK : hip_fail(e, "mse_grad");
+}
+
+mrx_status mrx_soft_modl_forward(mrx_plan p, const float* aHy, const float* S, const float* mask,
+                                 const float* lambda, int32_t T, int32_t n_cg, float* x_out, float* states,
+                                 void* stream) {
+  if (!p) return fail(MRX_EINVAL, "soft_modl_forward: null plan");
+  if (p->sets < 2) return fail(MRX_EINVAL, "soft_modl_forward: plan was created without MRX_PLAN_SOFT_SENSE");
+  if (!aHy || !S || !mask || !lambda || !x_out) return fail(MRX_EINVAL, "soft_modl_forward: null data pointer");
+  if (T < 0 || T > 1000 || n_cg < 0 || n_cg > 100000)
+    return fail(MRX_EINVAL, "soft_modl_forward: T or n_cg out of range");
+  mrx_status st = net_ready(p, "soft_modl_forward");
+  if (st != MRX_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ns = p->n_image * p->sets;
+  float2* z = (float2*)(p->ws + p->ws_z);
+  float2* x1 = (float2*)(p->ws + p->ws_s1[0]);
+  float2* z1 = (float2*)(p->ws + p->ws_s1[1]);
+  float2* st2 = (float2*)states;
+  const float2* prev = (const float2*)aHy;
+  hipError_t e = hipSuccess;
+  if (st2) e = copy_c((const float2*)aHy, st2, ns, s);
+  if (e == hipSuccess && T == 0) e = copy_c((const float2*)aHy, (float2*)x_out, ns, s);
+  if (e != hipSuccess) return hip_fail(e, "soft_modl_forward: copy");
+  for (int t = 0; t < T; ++t) {
+    e = soft_take(p, prev, x1, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_forward: take");
+    st = cnn_fwd(p, x1, z1, s, /*fuse12=*/true);
+    if (st != MRX_OK) return st;
+    e = soft_merge(p, z1, prev, z, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_forward: merge");
+    float2* next;
+    if (t == T - 1) next = (float2*)x_out;
+    else if (st2) next = st2 + (int64_t)(t + 1) * ns;
+    else next = (float2*)(p->ws + p->ws_ximg[t & 1]);
+    st = cg_impl(p, cg_bufs_ws(p), (const float2*)aHy, z, (const float2*)S, mask, lambda, n_cg, next, nullptr, s,
+                 /*soft=*/true);
+    if (st != MRX_OK) return st;
+    prev = next;
+  }
+  if (st2 && T > 0) {
+    e = copy_c((const float2*)x_out, st2 + (int64_t)T * ns, ns, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_forward: copy");
+  }
+  return MRX_OK;
+}
+
+mrx_status mrx_soft_modl_backward(mrx_plan p, const float* g_out, const float* states, const float* aHy,
+                                  const float* S, const float* mask, const float* lambda, int32_t T, int32_t n_cg,
+                                  const mrx_cnn_grads* g, float* g_lambda, float* g_aHy, int32_t accumulate,
+                                  void* stream) {
+  if (!p) return fail(MRX_EINVAL, "soft_modl_backward: null plan");
+  if (p->sets < 2) return fail(MRX_EINVAL, "soft_modl_backward: plan was created without MRX_PLAN_SOFT_SENSE");
+  if (!g_out || !states || !aHy || !S || !mask || !lambda || !g)
+    return fail(MRX_EINVAL, "soft_modl_backward: null data pointer");
+  for (int l = 0; l < 5; ++l)
+    if (!g->w[l] || !g->b[l]) return fail(MRX_EINVAL, "soft_modl_backward: null gradient buffer");
+  if (T < 1 || T > 1000 || n_cg < 0 || n_cg > 100000)
+    return fail(MRX_EINVAL, "soft_modl_backward: T or n_cg out of range");
+  mrx_status st = net_ready(p, "soft_modl_backward");
+  if (st != MRX_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ns = p->n_image * p->sets;
+  const float2* X = (const float2*)states;
+  float2* z = (float2*)(p->ws + p->ws_z);
+  float2* gcur = (float2*)(p->ws + p->ws_gimg[0]);
+  float2* gz = (float2*)(p->ws + p->ws_gimg[1]);
+  float2* v = (float2*)(p->ws + p->ws_vimg);
+  float2* x1 = (float2*)(p->ws + p->ws_s1[0]);
+  float2* z1 = (float2*)(p->ws + p->ws_s1[1]);
+  float2* gx1 = (float2*)(p->ws + p->ws_s1[2]);
+  float* part = (float*)(p->ws + p->ws_part);
+  hipError_t e = copy_c((const float2*)g_out, gcur, ns, s);
+  if (e != hipSuccess) return hip_fail(e, "soft_modl_backward: copy");
+  if (g_aHy && !accumulate) {
+    e = fill_u32((uint32_t*)g_aHy, 0u, 2 * ns, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_backward: clear");
+  }
+  for (int t = T - 1; t >= 0; --t) {
+    const float2* xt = X + (int64_t)t * ns;
+    const float2* xn = X + (int64_t)(t + 1) * ns;
+    // z^t = (D(x_1^t), x_2^t), with the activations at x_1^t for the reverse pass
+    e = soft_take(p, xt, x1, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_backward: take");
+    st = cnn_fwd(p, x1, z1, s);
+    if (st != MRX_OK) return st;
+    e = soft_merge(p, z1, xt, z, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_backward: merge");
+    st = cg_impl(p, cg_bufs_ws(p), gcur, nullptr, (const float2*)S, mask, lambda, n_cg, v, nullptr, s, true);
+    if (st != MRX_OK) return st;
+    CgElemArgs a = elem_args(p, lambda, cg_bufs_ws(p), /*soft=*/true);
+    a.aHy = xn;
+    a.z = z;
+    a.x = v;
+    e = cg_bwd_tail(a, gz, g_lambda ? part : nullptr, s);
+    if (e == hipSuccess && g_lambda) e = slice_sum(a, part, g_lambda, (accumulate || t < T - 1) ? 1 : 0, s);
+    if (e == hipSuccess && g_aHy) e = axpy_c(v, (float2*)g_aHy, ns, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_backward: dc tail");
+    // the denoiser's reverse pass on the first set; the second set's
+    // gradient passes unchanged
+    e = soft_take(p, gz, z1, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_backward: take");
+    st = cnn_bwd(p, x1, z1, gx1, g, (accumulate || t < T - 1) ? 1 : 0, s);
+    if (st != MRX_OK) return st;
+    e = soft_merge(p, gx1, gz, gcur, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_backward: merge");
+  }
+  if (g_aHy) {
+    e = axpy_c(gcur, (float2*)g_aHy, ns, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_modl_backward: tail");
+  }
+  return MRX_OK;
+}
+
+mrx_status mrx_soft_coil_mse_grad(mrx_plan p, const float* x, const float* S, const float* ref, float* g,
+                                  float* loss, void* stream) {
+  if (!p) return fail(MRX_EINVAL, "soft_coil_mse_grad: null plan");
+  if (p->sets < 2) return fail(MRX_EINVAL, "soft_coil_mse_grad: plan was created without MRX_PLAN_SOFT_SENSE");
+  if (!x || !S || !ref) return fail(MRX_EINVAL, "soft_coil_mse_grad: null data pointer");
+  if (!p->ws) return fail(MRX_ENOWORKSPACE, "soft_coil_mse_grad: workspace not set");
+  if (!(p->flags & MRX_PLAN_NETWORK))
+    return fail(MRX_ENOWORKSPACE, "soft_coil_mse_grad: plan needs MRX_PLAN_NETWORK");
+  hipStream_t s = (hipStream_t)stream;
+  float* part = (float*)(p->ws + p->ws_loss);
+  const float scale = 1.0f / (float)p->n_coil;
+  hipLaunchKernelGGL(k_soft_coil_mse, dim3(p->nrr, p->B), dim3(256), 0, s, p->d_desc, (const float2*)x,
+                     (const float2*)S, (const float2*)ref, (float2*)g, part, p->nrr, scale);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && loss) {
+    hipLaunchKernelGGL(k_mse_total, dim3(1), dim3(256), 0, s, part, p->B * p->nrr, scale, loss);
+    e = hipGetLastError();
+  }
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "soft_coil_mse_grad");
 }
 
 mrx_status mrx_adam_step(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,

@@ -46,9 +46,9 @@ CgBufs cg_bufs_ws(mrx_plan_s* p) {
   return b;
 }
 
-CgElemArgs elem_args(mrx_plan_s* p, const float* lam, const CgBufs& b) {
+CgElemArgs elem_args(mrx_plan_s* p, const float* lam, const CgBufs& b, bool soft) {
   CgElemArgs a{};
-  a.desc = p->d_desc;
+  a.desc = soft ? p->d_desc_soft : p->d_desc;
   a.slices = p->d_all;
   a.nslices = p->B;
   a.nrr = p->nrr;
@@ -95,6 +95,54 @@ mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const fl
   return e == hipSuccess ? MRX_OK : hip_fail(e, "sense_normal");
 }
 
+// Soft-SENSE operators: the soft column passes and the SENSE row passes.
+mrx_status soft_fwd_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float2* noise,
+                         float2* y, hipStream_t s) {
+  for (auto& g : p->groups) {
+    SenseColArgs ca{p->d_desc, g.d_slices, (int)g.slices.size(), S, mask, x, y, p->tw.at(g.H)};
+    hipError_t e = g.soft->fwd_col(ca, g.W, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_sense_fwd: column pass");
+    SenseRowArgs ra{p->d_desc, g.d_slices, (int)g.slices.size(), mask, y, y, noise, p->tw.at(g.W)};
+    e = g.rowW->fwd_row(ra, g.H, g.maxC, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_sense_fwd: row pass");
+  }
+  return MRX_OK;
+}
+
+mrx_status soft_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const float* mask, float2* x,
+                         hipStream_t s) {
+  float2* tmp = (float2*)(p->ws + p->ws_tmp);
+  for (auto& g : p->groups) {
+    SenseRowArgs ra{p->d_desc, g.d_slices, (int)g.slices.size(), mask, y, tmp, nullptr, p->tw.at(g.W)};
+    hipError_t e = g.rowW->adj_row(ra, g.H, g.maxC, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_sense_adj: row pass");
+    SenseColArgs ca{p->d_desc, g.d_slices, (int)g.slices.size(), S, mask, tmp, x, p->tw.at(g.H)};
+    e = g.soft->adj_col(ca, g.W, s);
+    if (e != hipSuccess) return hip_fail(e, "soft_sense_adj: column pass");
+  }
+  return MRX_OK;
+}
+
+mrx_status soft_normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
+                            float2* out, hipStream_t s) {
+  KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
+  hipError_t e = for_groups(p, s, [&](Group& g, hipStream_t sg) {
+    NormalArgs na{};
+    na.desc = p->d_desc;
+    na.slices = g.d_slices;
+    na.nslices = (int)g.slices.size();
+    na.S = S;
+    na.mask = mask;
+    na.lam = lam;
+    na.pin = x;
+    na.qout = out;
+    na.tw = p->tw.at(g.H);
+    na.mode = 0;
+    return g.soft->normal(na, g.W, sg);
+  });
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "soft_sense_normal");
+}
+
 mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,
                    const float* lam, int n_iter, float2* x, float* hist, hipStream_t s) {
   return cg_impl(p, cg_bufs_ws(p), aHy, z, S, mask, lam, n_iter, x, hist, s);
@@ -102,7 +150,8 @@ mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const floa
 
 // x = CG_n(A^H A + lam I, aHy + lam z) from x0 = 0, on the buffers bb.
 mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const float2* z, const float2* S,
-                   const float* mask, const float* lam, int n_iter, float2* x, float* hist, hipStream_t s) {
+                   const float* mask, const float* lam, int n_iter, float2* x, float* hist, hipStream_t s,
+                   bool soft) {
   float2* r = bb.r;
   // p_k lives in pb[k & 1]: the step that forms p_k = r_k + beta p_{k-1}
   // reads the other buffer, so workgroups splitting a tile's coils never
@@ -112,7 +161,7 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
   float2* q = bb.q;
   float* pq = bb.pq;
   float* rr[2] = {bb.rr[0], bb.rr[1]};
-  CgElemArgs a = elem_args(p, lam, bb);
+  CgElemArgs a = elem_args(p, lam, bb, soft);
   a.aHy = aHy;
   a.z = z;
   a.x = x;
@@ -159,7 +208,7 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
         na.pq_part = pq;
         na.npq = p->npq;
         na.stopped = a.stopped;
-        return g.col->normal(na, g.W, sg);
+        return soft ? g.soft->normal(na, g.W, sg) : g.col->normal(na, g.W, sg);
       });
     }
     if (e != hipSuccess) return hip_fail(e, "cg: normal operator");

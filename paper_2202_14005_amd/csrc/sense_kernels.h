@@ -82,7 +82,18 @@ struct RowVariant {
   const char* name;
 };
 
+// Soft-SENSE (two coil-map sets) kernels of one length: the fused normal
+// operator and the column passes; the row passes are the SENSE ones.
+struct SoftVariant {
+  int N;
+  NormalFn normal;
+  ColFn fwd_col;
+  ColFn adj_col;
+  const char* name;
+};
+
 void register_col_variant(const ColVariant& v);
 void register_row_variant(const RowVariant& v);
+void register_soft_variant(const SoftVariant& v);
 
 }  // namespace mrx

@@ -1,0 +1,295 @@
+// Soft-SENSE operator kernels: the SENSE model with two sets of coil maps
+// (Extensions to the SENSE-Model subsection),
+//   y_c = P F (S_{0,c} x_0 + S_{1,c} x_1),   (A^H y)_m = sum_c conj(S_{m,c}) F^H P^H y_c.
+// Layout of slice b (offsets from the plan's descriptor d): image sets
+// [2][H][W] at 2 d.xoff, coil maps [2][C][H][W] at 2 d.soff, k-space
+// [C][H][W] at d.soff (as for SENSE), mask [H] at d.moff.  The kernels are
+// the SENSE column passes and the fused normal operator with the two sets
+// combined before the transform and separated after it; the row passes
+// (along W) are the SENSE ones.
+#pragma once
+#include "sense_impl.h"
+
+namespace mrx {
+
+// Forward column pass: v = S_{0,c} x_0 + S_{1,c} x_1, transform along H,
+// keep sampled rows (signs and centering as k_fwd_col).
+template <class Sd, int WT>
+__global__ void __launch_bounds__(Sd::T * WT)
+k_fwd_col_soft(SenseColArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  using L = LdsInterleaved<N, WT>;
+  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 tw[N];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  if (d.H != N) return;
+  const int W = d.W, tile = blockIdx.x;
+  if (tile * WT >= W) return;
+  const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
+  const bool valid = col < W;
+  for (int i = lid; i < N; i += T * WT) tw[i] = a.tw[i];
+  __syncthreads();
+  const float scale = rsqrtf((float)N);
+  const int64_t plane = (int64_t)N * W;
+  const float2* xin = a.in + 2 * d.xoff;
+  float2 x0[P], x1[P];
+#pragma unroll
+  for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::N1; ++r) {
+      const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+      x0[i * Sd::N1 + r] = valid ? xin[o] : make_float2(0.f, 0.f);
+      x1[i * Sd::N1 + r] = valid ? xin[plane + o] : make_float2(0.f, 0.f);
+    }
+  const float* mrow = a.mask + d.moff;
+  const float2* Sb = a.S + 2 * d.soff;
+  for (int coil = 0; coil < d.C; ++coil) {
+    const float2* S0 = Sb + coil * plane;
+    const float2* S1 = Sb + (d.C + coil) * plane;
+    float2 v[P];
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int k = i * Sd::N1 + r;
+        const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+        const float2 s0 = valid ? S0[o] : make_float2(0.f, 0.f);
+        const float2 s1 = valid ? S1[o] : make_float2(0.f, 0.f);
+        v[k] = cadd(cmul(s0, x0[k]), cmul(s1, x1[k]));
+      }
+    fft_forward<Sd, L>(v, lds, tw, tc, c);
+    float2* oc = a.out + d.soff + coil * plane;
+#pragma unroll
+    for (int i = 0; i < Sd::GFIN; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::NFIN; ++r) {
+        const int j = Sd::freq(tc, i, r);
+        const int k = (j + N / 2) % N;
+        const float sg = (j & 1) ? -scale : scale;
+        if (valid && mrow[k] != 0.f) oc[(int64_t)k * W + col] = cscale(v[i * Sd::NFIN + r], sg);
+      }
+  }
+}
+
+// Adjoint column pass: per coil, the sampled rows of the row-pass output in
+// frequency order with the centering sign, inverse transform along H, then
+// x_m += conj(S_{m,c}) v for both sets.
+template <class Sd, int WT>
+__global__ void __launch_bounds__(Sd::T * WT)
+k_adj_col_soft(SenseColArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
+  using L = LdsInterleaved<N, WT>;
+  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 tw[N];
+  __shared__ float mk[N];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  if (d.H != N) return;
+  const int W = d.W, tile = blockIdx.x;
+  if (tile * WT >= W) return;
+  const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
+  const bool valid = col < W;
+  for (int i = lid; i < N; i += T * WT) {
+    tw[i] = a.tw[i];
+    mk[i] = a.mask[d.moff + i];
+  }
+  __syncthreads();
+  const float scale = rsqrtf((float)N);
+  const int64_t plane = (int64_t)N * W;
+  const float2* Sb = a.S + 2 * d.soff;
+  float2 acc0[P], acc1[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) acc0[k] = acc1[k] = make_float2(0.f, 0.f);
+  for (int coil = 0; coil < d.C; ++coil) {
+    const float2* ic = a.in + d.soff + coil * plane;
+    float2 v[P];
+#pragma unroll
+    for (int i = 0; i < Sd::GFIN; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::NFIN; ++r) {
+        const int j = Sd::freq(tc, i, r);
+        const int k = (j + N / 2) % N;
+        const float sg = (j & 1) ? -scale : scale;
+        float2 u = make_float2(0.f, 0.f);
+        if (valid && mk[k] != 0.f) u = cscale(ic[(int64_t)k * W + col], sg);
+        v[i * Sd::NFIN + r] = u;
+      }
+    fft_inverse<Sd, L>(v, lds, tw, tc, c);
+    if (valid) {
+      const float2* S0 = Sb + coil * plane;
+      const float2* S1 = Sb + (d.C + coil) * plane;
+#pragma unroll
+      for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+        for (int r = 0; r < Sd::N1; ++r) {
+          const int k = i * Sd::N1 + r;
+          const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+          acc0[k] = cadd(acc0[k], cmulc(S0[o], v[k]));
+          acc1[k] = cadd(acc1[k], cmulc(S1[o], v[k]));
+        }
+    }
+  }
+  if (!valid) return;
+  float2* xo = a.out + 2 * d.xoff;
+#pragma unroll
+  for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::N1; ++r) {
+      const int k = i * Sd::N1 + r;
+      const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
+      xo[o] = acc0[k];
+      xo[plane + o] = acc1[k];
+    }
+}
+
+// Normal operator (A^H A + lambda I) p on both sets, one pass over the coil
+// maps: per coil v = S_{0,c} p_0 + S_{1,c} p_1, transform along H, mask,
+// inverse transform, q_m += conj(S_{m,c}) v; q_m += lambda p_m.  One
+// workgroup = WT columns of one slice (2-D grid: column tiles x slices of
+// the launch).  Mode 1 (CG step, as k_normal): p = r + beta p formed on the
+// fly from pin and r (beta = rho_k / rho_{k-1} from the rr partials) and
+// written to pout, and the tile's Re<p, q> partial written to pq_part.  The
+// operand is re-read for every coil (it is L2-resident) so that only the
+// two accumulators and the transform stay in registers.
+template <class Sd, int WT>
+__global__ void __launch_bounds__(Sd::T * WT, 2)
+k_normal_soft(NormalArgs a) {
+  constexpr int N = Sd::N, P = Sd::P, T = Sd::T, NT = T * WT;
+  static_assert(NT % 64 == 0, "the tile's dot product reduces over whole wavefronts");
+  using L = LdsInterleaved<N, WT>;
+  __shared__ float2 lds[L::SIZE];
+  __shared__ float2 tw[N];
+  __shared__ float mk[N];
+  __shared__ float red[NT / 64];
+  __shared__ float sc[1];
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  if (d.H != N) return;
+  const int W = d.W, tile = blockIdx.x;
+  if (tile * WT >= W) return;
+  const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
+  const bool valid = col < W;
+  const uint32_t voff = (uint32_t)(tc * W + (valid ? col : W - 1)) * 8u;
+  auto so = [&](int i, int r) { return (uint32_t)((T * i + r * Sd::M1) * W) * 8u; };
+  const uint32_t pbytes = (uint32_t)N * (uint32_t)W * 8u;
+  const bool cg = a.mode == 1;
+  if (cg && a.stopped[b]) return;
+  for (int i = lid; i < N; i += NT) {
+    tw[i] = a.tw[i];
+    mk[i] = a.mask[d.moff + (i + N / 2) % N] * (1.0f / N);
+  }
+  if (lid < 64) {
+    float beta = 0.f;
+    if (cg && a.iter > 0) {
+      const float rc = wave_sum_fixed(a.rr_cur + (int64_t)b * a.nrr, a.nrr, lid);
+      const float rp = wave_sum_fixed(a.rr_prev + (int64_t)b * a.nrr, a.nrr, lid);
+      beta = rp > 0.f ? rc / rp : 0.f;
+    }
+    if (lid == 0) sc[0] = beta;
+  }
+  __syncthreads();
+  const int64_t plane = (int64_t)N * W;
+  const int64_t xo = 2 * d.xoff;
+  const bool upd = cg && a.iter > 0;
+  const float beta = sc[0];
+  const BufPlane pin0(a.pin + xo, pbytes), pin1(a.pin + xo + plane, pbytes);
+  const BufPlane rin0(upd ? a.r + xo : a.pin + xo, pbytes), rin1(upd ? a.r + xo + plane : a.pin + xo + plane, pbytes);
+  auto pval = [&](const BufPlane& pp, const BufPlane& rr, uint32_t s) {
+    const float2 pv = pp.ld(voff, s);
+    if (!upd) return pv;
+    const float2 rv = rr.ld(voff, s);
+    return make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
+  };
+  if (cg && valid) {
+    const BufPlane pout0(a.pout + xo, pbytes), pout1(a.pout + xo + plane, pbytes);
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        pout0.st(pval(pin0, rin0, so(i, r)), voff, so(i, r));
+        pout1.st(pval(pin1, rin1, so(i, r)), voff, so(i, r));
+      }
+  }
+  float2 acc0[P], acc1[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) acc0[k] = acc1[k] = make_float2(0.f, 0.f);
+  const float2* Sb = a.S + 2 * d.soff;
+  for (int coil = 0; coil < d.C; ++coil) {
+    const BufPlane S0(Sb + coil * plane, pbytes), S1(Sb + (d.C + coil) * plane, pbytes);
+    float2 v[P];
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const uint32_t s = so(i, r);
+        v[i * Sd::N1 + r] = cadd(cmul(S0.ld(voff, s), pval(pin0, rin0, s)), cmul(S1.ld(voff, s), pval(pin1, rin1, s)));
+      }
+    // the tile region sees only alternating forward and inverse transforms
+    fft_forward<Sd, L, BlockSyncPost>(v, lds, tw, tc, c);
+    fft_inverse<Sd, L, BlockSyncPost, FreqScale>(v, lds, tw, tc, c, FreqScale{mk});
+#pragma unroll
+    for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int k = i * Sd::N1 + r;
+        acc0[k] = cadd(acc0[k], cmulc(S0.ld_nt(voff, so(i, r)), v[k]));
+        acc1[k] = cadd(acc1[k], cmulc(S1.ld_nt(voff, so(i, r)), v[k]));
+      }
+  }
+  const float lam = a.lam ? a.lam[b] : 0.f;
+  const BufPlane q0(a.qout + xo, pbytes), q1(a.qout + xo + plane, pbytes);
+  float dot = 0.f;
+#pragma unroll
+  for (int i = 0; i < Sd::G1; ++i)
+#pragma unroll
+    for (int r = 0; r < Sd::N1; ++r) {
+      const int k = i * Sd::N1 + r;
+      const uint32_t s = so(i, r);
+      const float2 p0 = pval(pin0, rin0, s), p1 = pval(pin1, rin1, s);
+      const float2 u0 = make_float2(acc0[k].x + lam * p0.x, acc0[k].y + lam * p0.y);
+      const float2 u1 = make_float2(acc1[k].x + lam * p1.x, acc1[k].y + lam * p1.y);
+      dot += p0.x * u0.x + p0.y * u0.y + p1.x * u1.x + p1.y * u1.y;
+      if (valid) {
+        q0.st(u0, voff, s);
+        q1.st(u1, voff, s);
+      }
+    }
+  if (!valid) dot = 0.f;
+  if (cg) {
+    const float s = block_sum_fixed(dot, red);
+    if (lid == 0) a.pq_part[(int64_t)b * a.npq + tile] = s;
+  }
+}
+
+template <class Sd, int WT>
+hipError_t launch_normal_soft(const NormalArgs& a0, int maxW, hipStream_t s) {
+  NormalArgs a = a0;
+  a.tiles = (maxW + WT - 1) / WT;
+  if (a.mode == 1 && a.tiles > a.npq) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_normal_soft<Sd, WT>), dim3(a.tiles, a.nslices), dim3(Sd::T * WT), 0, s, a);
+  return hipGetLastError();
+}
+template <class Sd, int WT>
+hipError_t launch_fwd_col_soft(const SenseColArgs& a, int maxW, hipStream_t s) {
+  hipLaunchKernelGGL((k_fwd_col_soft<Sd, WT>), dim3((maxW + WT - 1) / WT, a.nslices), dim3(Sd::T * WT), 0, s, a);
+  return hipGetLastError();
+}
+template <class Sd, int WT>
+hipError_t launch_adj_col_soft(const SenseColArgs& a, int maxW, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_col_soft<Sd, WT>), dim3((maxW + WT - 1) / WT, a.nslices), dim3(Sd::T * WT), 0, s, a);
+  return hipGetLastError();
+}
+
+// Registers the soft-SENSE kernels of one length (built for each length's
+// default schedule).
+template <class Sd, int WT>
+struct RegistrarSoft {
+  RegistrarSoft(const char* name) {
+    SoftVariant v{Sd::N, &launch_normal_soft<Sd, WT>, &launch_fwd_col_soft<Sd, WT>, &launch_adj_col_soft<Sd, WT>,
+                  name};
+    register_soft_variant(v);
+  }
+};
+
+}  // namespace mrx

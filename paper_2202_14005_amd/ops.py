@@ -32,7 +32,8 @@ class Plan:
     ``H``, ``W``, ``C`` are ints (even batch of ``B`` slices) or per-slice
     sequences (uneven batch)."""
 
-    def __init__(self, H, W, C, B: int | None = None, device=None, network: bool = False, vn: bool = False):
+    def __init__(self, H, W, C, B: int | None = None, device=None, network: bool = False, vn: bool = False,
+                 soft: bool = False):
         L = lib()
         if isinstance(H, int):
             if B is None:
@@ -50,10 +51,11 @@ class Plan:
         arr = lambda v: (ctypes.c_int32 * len(v))(*v)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            flags = (1 if network else 0) | (2 if vn else 0)
+            flags = (1 if network else 0) | (2 if vn else 0) | (4 if soft else 0)
             check(L.mrx_plan_create(ctypes.byref(h), self.B, arr(Hs), arr(Ws), arr(Cs), flags), "plan_create")
         self.network = network
         self.vn = vn
+        self.soft = soft
         self._weights_key = None
         self._h = h
         ni, nc, nm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -303,6 +305,89 @@ class Plan:
                                       _ptr(lt), int(T), int(n_cg), ctypes.byref(grads.c_grads()), _ptr(gl),
                                       _ptr(ga), int(bool(accumulate)), _stream(self.device)), "modl_backward")
         return gl, ga
+
+    # ---------------------------------------------------------- soft-SENSE
+    # Two coil-map sets: images [B, 2, H, W] (flat 2 n_image for uneven
+    # batches), maps [B, 2, C, H, W] (flat 2 n_coil), k-space as for SENSE.
+    def _simg(self, t, name):
+        return self._chk(t, name, 2 * self.n_image, torch.complex64, (self.B, 2, self.H[0], self.W[0]))
+
+    def _smaps(self, t, name):
+        return self._chk(t, name, 2 * self.n_coil, torch.complex64, (self.B, 2, self.C[0], self.H[0], self.W[0]))
+
+    def _empty_simg(self):
+        shape = (self.B, 2, self.H[0], self.W[0]) if self.even else (2 * self.n_image,)
+        return torch.empty(shape, dtype=torch.complex64, device=self.device)
+
+    def _need_soft(self):
+        if not self.soft:
+            raise ValueError("this plan was created without soft=True")
+
+    def soft_sense_fwd(self, x, S, mask, noise=None, out=None):
+        self._need_soft(); self._simg(x, "x"); self._smaps(S, "S"); self._mask(mask, "mask")
+        self._coil(noise, "noise")
+        y = self._coil(out, "out") if out is not None else self._empty_coil()
+        check(lib().mrx_soft_sense_fwd(self._h, _ptr(x), _ptr(S), _ptr(mask), _ptr(noise), _ptr(y),
+                                       _stream(self.device)), "soft_sense_fwd")
+        return y
+
+    def soft_sense_adj(self, y, S, mask, out=None):
+        self._need_soft(); self._coil(y, "y"); self._smaps(S, "S"); self._mask(mask, "mask")
+        x = self._simg(out, "out") if out is not None else self._empty_simg()
+        check(lib().mrx_soft_sense_adj(self._h, _ptr(y), _ptr(S), _ptr(mask), _ptr(x), _stream(self.device)),
+              "soft_sense_adj")
+        return x
+
+    def soft_sense_normal(self, x, S, mask, lam=None, out=None):
+        self._need_soft(); self._simg(x, "x"); self._smaps(S, "S"); self._mask(mask, "mask")
+        lt = self.lam(lam) if lam is not None else None
+        q = self._simg(out, "out") if out is not None else self._empty_simg()
+        check(lib().mrx_soft_sense_normal(self._h, _ptr(x), _ptr(S), _ptr(mask), _ptr(lt), _ptr(q),
+                                          _stream(self.device)), "soft_sense_normal")
+        return q
+
+    def soft_cg_dc(self, aHy, S, mask, lam, n_iter, z=None, out=None, hist=False):
+        self._need_soft(); self._simg(aHy, "aHy"); self._simg(z, "z"); self._smaps(S, "S"); self._mask(mask, "mask")
+        lt = self.lam(lam)
+        x = self._simg(out, "out") if out is not None else self._empty_simg()
+        h = torch.empty((self.B, n_iter + 1), dtype=torch.float32, device=self.device) if hist else None
+        check(lib().mrx_soft_cg_dc(self._h, _ptr(aHy), _ptr(z), _ptr(S), _ptr(mask), _ptr(lt), int(n_iter),
+                                   _ptr(x), _ptr(h), _stream(self.device)), "soft_cg_dc")
+        return (x, h) if hist else x
+
+    def soft_modl_forward(self, aHy, S, mask, cnn: "CNN", lam, T, n_cg, states=False, out=None):
+        self._need_soft(); self._simg(aHy, "aHy"); self._smaps(S, "S"); self._mask(mask, "mask")
+        self.set_weights(cnn)
+        lt = self.lam(lam)
+        x = self._simg(out, "out") if out is not None else self._empty_simg()
+        st = (torch.empty((T + 1,) + tuple(x.shape), dtype=torch.complex64, device=self.device)
+              if states else None)
+        check(lib().mrx_soft_modl_forward(self._h, _ptr(aHy), _ptr(S), _ptr(mask), _ptr(lt), int(T), int(n_cg),
+                                          _ptr(x), _ptr(st), _stream(self.device)), "soft_modl_forward")
+        return (x, st) if states else x
+
+    def soft_modl_backward(self, g_out, states, aHy, S, mask, cnn: "CNN", lam, T, n_cg, grads: "CNNGrads",
+                           accumulate=False, need_aHy=False):
+        self._need_soft(); self._simg(g_out, "g_out"); self._simg(aHy, "aHy"); self._smaps(S, "S")
+        self._mask(mask, "mask")
+        self.set_weights(cnn)
+        lt = self.lam(lam)
+        gl = torch.zeros(self.B, dtype=torch.float32, device=self.device)
+        ga = self._empty_simg() if need_aHy else None
+        check(lib().mrx_soft_modl_backward(self._h, _ptr(g_out), _ptr(states), _ptr(aHy), _ptr(S), _ptr(mask),
+                                           _ptr(lt), int(T), int(n_cg), ctypes.byref(grads.c_grads()), _ptr(gl),
+                                           _ptr(ga), int(bool(accumulate)), _stream(self.device)),
+              "soft_modl_backward")
+        return gl, ga
+
+    def soft_coil_mse_grad(self, x, S, ref):
+        """(loss [1], g) of the MSE on the coil images against ref (coil sized)."""
+        self._need_soft(); self._simg(x, "x"); self._smaps(S, "S"); self._coil(ref, "ref")
+        g = self._empty_simg()
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        check(lib().mrx_soft_coil_mse_grad(self._h, _ptr(x), _ptr(S), _ptr(ref), _ptr(g), _ptr(loss),
+                                           _stream(self.device)), "soft_coil_mse_grad")
+        return loss, g
 
     # ------------------------------------------------------------- VarNet
     def _vn_params(self, k, w, lam):
