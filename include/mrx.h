@@ -391,6 +391,37 @@ mrx_status mrx_vn_stage_backward(mrx_plan plan, const float* g, const float* x, 
                                  float* g_x, float* g_k, float* g_w, float* g_lam,
                                  int32_t accumulate, void* stream);
 
+/*
+ * iPALM, the training algorithm named for VarNet (Iterative Training
+ * Algorithms; Variational Network subsection), on n fp32 parameters (complex
+ * parameters as interleaved pairs).  Step k = 1, 2, ...: extrapolate
+ *   y = theta + alpha (theta - theta_prev)          (alpha = (k - 1)/(k + 2)),
+ * evaluate the loss gradient g at y, then
+ *   theta_prev = theta;  theta = y - tau g          (mrx_ipalm_update),
+ * and apply the proximal map, here mrx_vn_project.  All device arrays of n
+ * floats; y may not alias theta or theta_prev.
+ */
+mrx_status mrx_ipalm_extrapolate(const float* theta, const float* theta_prev, float* y, int64_t n,
+                                 float alpha, void* stream);
+mrx_status mrx_ipalm_update(float* theta, float* theta_prev, const float* y, const float* g, int64_t n,
+                            float tau, void* stream);
+/*
+ * The VarNet constraints as a projection: each of n_filters complex filters
+ * of `taps` taps (interleaved, consecutive; taps <= 256) to zero mean and unit
+ * Euclidean norm (a filter that is zero after removing its mean stays zero),
+ * and each of n_lam step sizes to lambda >= 0.  In place on the device.
+ */
+mrx_status mrx_vn_project(float* k, int32_t n_filters, int32_t taps, float* lam, int32_t n_lam,
+                          void* stream);
+/*
+ * The VarNet training option that scales the data so that max|x^0| = 1, per
+ * slice: s_b = 1 / max_i |x_b[i]| (1 for an all-zero slice), x (image sized)
+ * and, where not NULL, y (coil sized k-space) and ref (image sized) of slice
+ * b multiplied by s_b in place; scale_out: device float[B] receives s_b.
+ * Uses the workspace.
+ */
+mrx_status mrx_normalize_max(mrx_plan plan, float* x, float* y, float* ref, float* scale_out, void* stream);
+
 /* Choose the fastest registered column schedule for each (H, W) group of the
  * plan by timing each on the given stream (synchronises the host): four CG
  * iterations over the plan when its workspace is set (scratch_a is the

@@ -46,6 +46,10 @@ SIGNATURES = {
     "mrx_soft_modl_forward": (c_int32, [P, P, P, P, P, c_int32, c_int32, P, P, P]),
     "mrx_soft_modl_backward": (c_int32, [P, P, P, P, P, P, P, c_int32, c_int32, P, P, P, c_int32, P]),
     "mrx_soft_coil_mse_grad": (c_int32, [P, P, P, P, P, P, P]),
+    "mrx_ipalm_extrapolate": (c_int32, [P, P, P, c_int64, c_float, P]),
+    "mrx_ipalm_update": (c_int32, [P, P, P, P, c_int64, c_float, P]),
+    "mrx_vn_project": (c_int32, [P, c_int32, c_int32, P, c_int32, P]),
+    "mrx_normalize_max": (c_int32, [P, P, P, P, P, P]),
     "mrx_status_word": (c_int32, [P, P, c_int32, P]),
     "mrx_plan_autotune": (c_int32, [P, P, P, P, P, P]),
     "mrx_cnn_set_weights": (c_int32, [P, P, P]),

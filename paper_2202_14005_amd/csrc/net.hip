@@ -507,9 +507,8 @@ mrx_status mrx_mse_grad(mrx_plan p, const float* x, const float* ref, float* g, 
   if (!p) return fail(MRX_EINVAL, "mse_grad: null plan");
   if (!x || !ref) return fail(MRX_EINVAL, "mse_grad: null data pointer");
   if (!p->ws) return fail(MRX_ENOWORKSPACE, "mse_grad: workspace not set");
-  if (!(p->flags & MRX_PLAN_NETWORK)) return fail(MRX_ENOWORKSPACE, "mse_grad: plan needs MRX_PLAN_NETWORK");
   hipStream_t s = (hipStream_t)stream;
-  float* part = (float*)(p->ws + p->ws_loss);
+  float* part = (float*)(p->ws + p->ws_part);  // B x nrr partial sums (every plan's workspace)
   const float scale = 1.0f / (float)p->n_image;
   hipLaunchKernelGGL(k_mse, dim3(p->nrr, p->B), dim3(256), 0, s, p->d_desc, p->d_all, (const float2*)x,
                      (const float2*)ref, (float2*)g, part, p->nrr, scale);

@@ -389,6 +389,15 @@ class Plan:
                                            _stream(self.device)), "soft_coil_mse_grad")
         return loss, g
 
+    def normalize_max(self, x, y=None, ref=None):
+        """Scale each slice so that max|x| = 1 (x, and y and ref if given, in
+        place); returns the per-slice factors [B]."""
+        self._img(x, "x"); self._coil(y, "y"); self._img(ref, "ref")
+        sc = torch.empty(self.B, dtype=torch.float32, device=self.device)
+        check(lib().mrx_normalize_max(self._h, _ptr(x), _ptr(y), _ptr(ref), _ptr(sc), _stream(self.device)),
+              "normalize_max")
+        return sc
+
     # ------------------------------------------------------------- VarNet
     def _vn_params(self, k, w, lam):
         from ._lib import VnParams
@@ -587,21 +596,71 @@ class VarNet:
         return cls(plan, torch.from_numpy(p["k"]).to(d), torch.from_numpy(p["w"]).to(d),
                    torch.from_numpy(p["lam"]).to(d))
 
-    def forward(self, aHy, S, mask):
-        """Returns (x^T, states [T + 1, ...])."""
+    def params(self):
+        return [self.k, self.w, self.lam]
+
+    def forward(self, aHy, S, mask, params=None):
+        """Returns (x^T, states [T + 1, ...]); params (k, w, lam) override
+        the network's own."""
+        k, w, lam = params if params is not None else self.params()
         states = [aHy]
         for t in range(self.T):
-            states.append(self.plan.vn_stage(states[-1], aHy, S, mask, self.k[t], self.w[t], self.lam[t:t + 1]))
+            states.append(self.plan.vn_stage(states[-1], aHy, S, mask, k[t], w[t], lam[t:t + 1]))
         return states[-1], states
 
-    def backward(self, g, states, aHy, S, mask):
+    def backward(self, g, states, aHy, S, mask, params=None):
         """Reverse pass from the stored states; returns (gk, gw, glam, g_x0)."""
-        gk, gw = torch.zeros_like(self.k), torch.zeros_like(self.w)
-        gl = torch.zeros_like(self.lam)
+        k, w, lam = params if params is not None else self.params()
+        gk, gw = torch.zeros_like(k), torch.zeros_like(w)
+        gl = torch.zeros_like(lam)
         for t in range(self.T - 1, -1, -1):
-            g, _ = self.plan.vn_stage_backward(g, states[t], aHy, S, mask, self.k[t], self.w[t],
-                                               self.lam[t:t + 1], grads=(gk[t], gw[t], gl[t:t + 1]))
+            g, _ = self.plan.vn_stage_backward(g, states[t], aHy, S, mask, k[t], w[t],
+                                               lam[t:t + 1], grads=(gk[t], gw[t], gl[t:t + 1]))
         return gk, gw, gl, g
+
+
+def _floats(t):
+    """A device tensor as its fp32 storage (complex as interleaved pairs)."""
+    return torch.view_as_real(t).reshape(-1) if t.is_complex() else t.reshape(-1)
+
+
+class IPALM:
+    """iPALM training of a VarNet (the algorithm the paper names for it):
+    step k extrapolates y = theta + alpha_k (theta - theta_prev) with
+    alpha_k = (k - 1) / (k + 2), takes the MSE gradient of the network at y
+    on the given batch, steps theta = y - tau g and projects onto the
+    VarNet constraints (filters zero mean and unit norm, step sizes >= 0).
+    The projection is applied to the initial weights too."""
+
+    def __init__(self, net: "VarNet", tau: float):
+        self.net, self.tau, self.steps = net, float(tau), 0
+        st = _stream(net.plan.device)
+        T = net.T
+        check(lib().mrx_vn_project(_ptr(net.k), T * net.k.shape[1], net.k.shape[2] * net.k.shape[3], _ptr(net.lam), T,
+                                   st), "vn_project")
+        self.prev = [p.clone() for p in net.params()]
+        self.work = [torch.empty_like(p) for p in net.params()]
+
+    def step(self, aHy, S, mask, ref):
+        """One iPALM step on the batch (aHy, S, mask) with reference images
+        ref; returns the loss at the extrapolated point (device [1])."""
+        net, plan = self.net, self.net.plan
+        st = _stream(plan.device)
+        self.steps += 1
+        a = (self.steps - 1.0) / (self.steps + 2.0)
+        for th, pr, y in zip(net.params(), self.prev, self.work):
+            check(lib().mrx_ipalm_extrapolate(_ptr(th), _ptr(pr), _ptr(y), _floats(th).numel(), a, st),
+                  "ipalm_extrapolate")
+        x, states = net.forward(aHy, S, mask, params=self.work)
+        loss, g = plan.mse_grad(x, ref)
+        grads = net.backward(g, states, aHy, S, mask, params=self.work)[:3]
+        for th, pr, y, gg in zip(net.params(), self.prev, self.work, grads):
+            check(lib().mrx_ipalm_update(_ptr(th), _ptr(pr), _ptr(y), _ptr(gg), _floats(th).numel(), self.tau, st),
+                  "ipalm_update")
+        T = net.T
+        check(lib().mrx_vn_project(_ptr(net.k), T * net.k.shape[1], net.k.shape[2] * net.k.shape[3], _ptr(net.lam), T,
+                                   st), "vn_project")
+        return loss
 
 
 def schedules(n: int):
