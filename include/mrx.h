@@ -360,6 +360,13 @@ mrx_status mrx_mse_grad(mrx_plan plan, const float* x, const float* ref, float* 
                         void* stream);
 
 /*
+ * out[0] = sum of the n floats a[0..n) (+ out[0] if accumulate != 0), in a
+ * fixed order; device pointers.  Reduces MoDL's per-slice lambda gradients
+ * to the gradient of the one shared, trainable lambda.
+ */
+mrx_status mrx_sum_f32(const float* a, int32_t n, float* out, int32_t accumulate, void* stream);
+
+/*
  * One Adam step (the training algorithm named in the Methods section) on n
  * fp32 parameters: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * w -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  step >= 1.

@@ -50,6 +50,7 @@ SIGNATURES = {
     "mrx_ipalm_update": (c_int32, [P, P, P, P, c_int64, c_float, P]),
     "mrx_vn_project": (c_int32, [P, c_int32, c_int32, P, c_int32, P]),
     "mrx_normalize_max": (c_int32, [P, P, P, P, P, P]),
+    "mrx_sum_f32": (c_int32, [P, c_int32, P, c_int32, P]),
     "mrx_status_word": (c_int32, [P, P, c_int32, P]),
     "mrx_plan_autotune": (c_int32, [P, P, P, P, P, P]),
     "mrx_cnn_set_weights": (c_int32, [P, P, P]),

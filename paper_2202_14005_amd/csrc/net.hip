@@ -431,6 +431,21 @@ mrx_status mrx_modl_backward(mrx_plan p, const float* g_out, const float* states
   return MRX_OK;
 }
 
+// out[0] (+)= sum of a[0..n) in a fixed order (per-thread strided sums, a
+// fixed butterfly, the four wavefront sums in order).
+__global__ void __launch_bounds__(256) k_sum_f32(const float* a, int n, float* out, int accumulate) {
+  __shared__ float red[4];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < n; i += 256) s += a[i];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float t = ((red[0] + red[1]) + red[2]) + red[3];
+    out[0] = accumulate ? out[0] + t : t;
+  }
+}
+
 // ------------------------------------------------------------ soft-SENSE
 // Images of soft-SENSE plans hold [2][H][W] per slice at 2 xoff.  The
 // network block updates the first set's image only: it is taken out into the
@@ -650,6 +665,14 @@ mrx_status mrx_soft_coil_mse_grad(mrx_plan p, const float* x, const float* S, co
     e = hipGetLastError();
   }
   return e == hipSuccess ? MRX_OK : hip_fail(e, "soft_coil_mse_grad");
+}
+
+mrx_status mrx_sum_f32(const float* a, int32_t n, float* out, int32_t accumulate, void* stream) {
+  if (!a || !out) return fail(MRX_EINVAL, "sum_f32: null pointer");
+  if (n < 0) return fail(MRX_EINVAL, "sum_f32: negative count");
+  hipLaunchKernelGGL(k_sum_f32, dim3(1), dim3(256), 0, (hipStream_t)stream, a, n, out, accumulate);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "sum_f32");
 }
 
 mrx_status mrx_adam_step(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,

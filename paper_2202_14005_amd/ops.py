@@ -553,12 +553,24 @@ class Adam:
 
 
 class MoDL:
-    """MoDL network: x^0 = A^H y, T unrolls of [denoiser, CG data consistency]."""
+    """MoDL network: x^0 = A^H y, T unrolls of [denoiser, CG data consistency].
+    With learn_lam the one shared lambda is a trained parameter (a device
+    float32 tensor [1]): train_step sums its per-slice gradients, takes an
+    Adam step on it with the weights' optimiser settings and keeps it >= 0."""
 
-    def __init__(self, plan: Plan, cnn: CNN, lam=0.05, T=5, n_cg=10):
+    def __init__(self, plan: Plan, cnn: CNN, lam=0.05, T=5, n_cg=10, learn_lam=False):
         if not plan.network:
             raise ValueError("MoDL needs a plan created with network=True")
-        self.plan, self.cnn, self.lam, self.T, self.n_cg = plan, cnn, lam, T, n_cg
+        self.plan, self.cnn, self.T, self.n_cg = plan, cnn, T, n_cg
+        self.learn_lam = learn_lam
+        if learn_lam:
+            self.lam = torch.full((1,), float(lam), dtype=torch.float32, device=plan.device)
+            self._lam_m = torch.zeros_like(self.lam)
+            self._lam_v = torch.zeros_like(self.lam)
+            self._lam_g = torch.zeros_like(self.lam)
+            self._lam_steps = 0
+        else:
+            self.lam = lam
 
     def forward(self, y, S, mask, states=False):
         aHy = self.plan.sense_adj(y, S, mask)
@@ -572,8 +584,15 @@ class MoDL:
         aHy = p.sense_adj(y, S, mask)
         xT, states = p.modl_forward(aHy, S, mask, self.cnn, self.lam, self.T, self.n_cg, states=True)
         loss, g = p.mse_grad(xT, x_ref)
-        p.modl_backward(g, states, aHy, S, mask, self.cnn, self.lam, self.T, self.n_cg, grads)
+        gl, _ = p.modl_backward(g, states, aHy, S, mask, self.cnn, self.lam, self.T, self.n_cg, grads)
         opt.step(grads)
+        if self.learn_lam:
+            st = _stream(p.device)
+            check(lib().mrx_sum_f32(_ptr(gl), gl.numel(), _ptr(self._lam_g), 0, st), "sum_f32")
+            self._lam_steps += 1
+            check(lib().mrx_adam_step(_ptr(self.lam), _ptr(self._lam_g), _ptr(self._lam_m), _ptr(self._lam_v), 1,
+                                      opt.lr, opt.b1, opt.b2, opt.eps, self._lam_steps, st), "adam_step")
+            check(lib().mrx_vn_project(None, 0, 1, _ptr(self.lam), 1, st), "vn_project")
         return loss
 
 

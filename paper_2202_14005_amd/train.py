@@ -73,29 +73,45 @@ def nrmse(x, ref):
 
 
 def train(H=320, W=320, C=15, B=4, T=5, n_cg=10, lam=0.05, lr=1e-4, steps=500, n_train=2000,
-          train_base=100000, seed=7, last_scale=0.1, log_every=25, device=None, verbose=True, tune=True):
-    """Train a MoDL denoiser; returns (cnn, history).  With ``tune`` the
-    normal operator's schedule is chosen by the autotuner on the first batch."""
+          train_base=100000, seed=7, last_scale=0.1, log_every=25, device=None, verbose=True, tune=True,
+          learn_lam=False, phases=None):
+    """Train a MoDL denoiser; returns (cnn, history), and with learn_lam the
+    trained lambda in the last history entry.  ``phases`` is a list of
+    (unrolls, steps) trained one after the other from the same weights,
+    each with a fresh Adam state -- the paper's two-step MoDL training is
+    [(1, n1), (10, n2)]; by default one phase (T, steps).  With ``tune`` the
+    normal operator's schedule is chosen by the autotuner on the first
+    batch."""
     dev = torch.device(device) if device else torch.device("cuda", torch.cuda.current_device())
     plan = ops.Plan(H, W, C, B=B, device=dev, network=True)
     src = PhantomSource(plan, H, W, C)
     cnn = ops.CNN.init(seed=seed, device=dev, last_scale=last_scale)
     grads = ops.CNNGrads(cnn)
-    opt = ops.Adam(cnn, lr=lr)
-    net = ops.MoDL(plan, cnn, lam=lam, T=T, n_cg=n_cg)
     hist = []
     t0 = time.perf_counter()
-    for it in range(steps):
-        seeds = [train_base + (it * B + k) % n_train for k in range(B)]
-        y, S, m, x = src.batch(seeds)
-        if tune and it == 0:
-            plan.autotune(S, m)
-        loss = net.train_step(y, S, m, x, grads, opt)
-        if it % log_every == 0 or it == steps - 1:
-            lv = float(loss.item())
-            hist.append({"step": it, "loss": lv, "time_s": time.perf_counter() - t0})
-            if verbose:
-                print(f"step {it:5d} loss {lv:.4e}", flush=True)
+    it = 0
+    lam_now = lam
+    for ph, (T_ph, steps_ph) in enumerate(phases or [(T, steps)]):
+        opt = ops.Adam(cnn, lr=lr)
+        net = ops.MoDL(plan, cnn, lam=lam_now, T=T_ph, n_cg=n_cg, learn_lam=learn_lam)
+        for k in range(steps_ph):
+            seeds = [train_base + (it * B + j) % n_train for j in range(B)]
+            y, S, m, x = src.batch(seeds)
+            if tune and it == 0:
+                plan.autotune(S, m)
+            loss = net.train_step(y, S, m, x, grads, opt)
+            if k % log_every == 0 or k == steps_ph - 1:
+                lv = float(loss.item())
+                e = {"step": it, "phase": ph, "unrolls": T_ph, "loss": lv, "time_s": time.perf_counter() - t0}
+                if learn_lam:
+                    e["lambda"] = float(net.lam.item())
+                hist.append(e)
+                if verbose:
+                    print(f"step {it:5d} (T = {T_ph}) loss {lv:.4e}" +
+                          (f" lambda {e['lambda']:.4f}" if learn_lam else ""), flush=True)
+            it += 1
+        if learn_lam:
+            lam_now = float(net.lam.item())
     return cnn, hist
 
 
@@ -149,11 +165,20 @@ def main():
     ap.add_argument("--n-eval", type=int, default=64)
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write the trained weights (.npz, arrays only)")
+    ap.add_argument("--learn-lam", action="store_true", help="train the shared lambda with the weights")
+    ap.add_argument("--two-step", default=None, metavar="N1,N2",
+                    help="the paper's two-step training: N1 steps with one unroll, then N2 with --unrolls")
     a = ap.parse_args()
-    cnn, hist = train(H=a.size, W=a.size, C=a.coils, B=a.batch, T=a.unrolls, lr=a.lr, steps=a.steps)
+    phases = None
+    if a.two_step:
+        n1, n2 = (int(v) for v in a.two_step.split(","))
+        phases = [(1, n1), (a.unrolls, n2)]
+    cnn, hist = train(H=a.size, W=a.size, C=a.coils, B=a.batch, T=a.unrolls, lr=a.lr, steps=a.steps,
+                      learn_lam=a.learn_lam, phases=phases)
     if a.save:
         cnn.save(a.save)
-    ev = evaluate(cnn, H=a.size, W=a.size, C=a.coils, B=a.batch, T=a.unrolls, n_eval=a.n_eval)
+    lam = hist[-1]["lambda"] if a.learn_lam else 0.05
+    ev = evaluate(cnn, H=a.size, W=a.size, C=a.coils, B=a.batch, T=a.unrolls, lam=lam, n_eval=a.n_eval)
     out = {"train": hist, "eval": ev}
     if a.out:
         json.dump(out, open(a.out, "w"), indent=1)

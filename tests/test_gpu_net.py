@@ -218,7 +218,7 @@ def modl_case(B, H, W, C, seed=400):
     return d, aHy
 
 
-@pytest.mark.parametrize("B,H,W,C,T", [(2, 48, 40, 4, 2), (1, 320, 320, 15, 5)])
+@pytest.mark.parametrize("B,H,W,C,T", [(2, 48, 40, 4, 2), (1, 320, 320, 15, 5), (2, 48, 40, 4, 10)])
 def test_modl_forward_parity(B, H, W, C, T):
     d, aHy = modl_case(B, H, W, C)
     w = weights(last_scale=0.1)
