@@ -18,6 +18,13 @@ names, in float64 / complex128, citing the part of the paper it follows:
   mode pass;
 * ``vn``     -- the variational-network stage (eq. update_vn);
 * ``adam``   -- the Adam update and the MSE loss (eq. network_optimize);
+* ``soft_sense`` -- SENSE with several coil-map sets (Extensions to the
+  SENSE-Model);
+* ``toeplitz`` -- non-Cartesian SENSE by the non-uniform DFT and its normal
+  operator as a PSF convolution on a twice-padded grid (Extensions to the
+  SENSE-Model);
+* ``ipalm``  -- iPALM and the VarNet constraint projections (Iterative
+  Training Algorithms);
 * ``metrics``-- relative error and NRMSE.
 
 Where the paper is silent, the reading taken is stated in each docstring.

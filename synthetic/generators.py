@@ -18,6 +18,8 @@ section, which are not available here):
   the regular pattern (every R-th line plus a centre block).
 * Noise: sigma * (N(0,1) + i N(0,1)) per k-space sample, sigma = 1e-3 (the
   paper's training-data recipe, Results section).
+* Non-Cartesian: radial spokes through the centre with a random rotation
+  per slice (``radial_trajectory``), the same phantoms and coil maps.
 
 Everything is drawn in float64 with ``numpy.random.default_rng(seed)`` and
 rounded once to complex64 / float32.
@@ -218,6 +220,44 @@ def batch_inputs(seeds, H: int, W: int, C: int, R: int, n_center: int,
     """Stack ``slice_inputs`` over ``seeds``: x [B,H,W], S [B,C,H,W], mask [B,H],
     noise [B,C,H,W]."""
     sl = [slice_inputs(s, H, W, C, R, n_center, mask_kind, sigma) for s in seeds]
+    return {k: np.stack([d[k] for d in sl]) for k in sl[0]}
+
+
+def radial_trajectory(seed: int, H: int, W: int, n_spokes: int, n_read: int) -> np.ndarray:
+    """Radial sampling (the paper's non-Cartesian experiment uses 44 spokes):
+    n_spokes lines through the k-space centre at angles
+    theta_s = theta_0 + pi s / n_spokes (theta_0 ~ U(0, pi / n_spokes)), each
+    with n_read equispaced samples t_i = (i - n_read / 2) / n_read, i <
+    n_read, of the extent; returns traj [n_spokes * n_read, 2] float32 of
+    (ky, kx) = (t_i H sin theta_s, t_i W cos theta_s) in cycles per field
+    of view (so the samples span [-H/2, H/2) x [-W/2, W/2))."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(0.0, math.pi / n_spokes) + math.pi * np.arange(n_spokes) / n_spokes
+    t = (np.arange(n_read) - n_read / 2) / n_read
+    ky = np.outer(np.sin(th), t) * H
+    kx = np.outer(np.cos(th), t) * W
+    return np.stack([ky.ravel(), kx.ravel()], axis=1).astype(np.float32)
+
+
+def noncart_slice_inputs(seed: int, H: int, W: int, C: int, n_spokes: int, n_read: int,
+                         sigma: float = 1e-3):
+    """One non-Cartesian slice: phantom x [H,W], coils S [C,H,W], radial
+    trajectory traj [M,2] (M = n_spokes n_read) and noise [C,M]."""
+    M = n_spokes * n_read
+    rng = np.random.default_rng(seed + 32452843)
+    n = sigma * (rng.standard_normal((C, M)) + 1j * rng.standard_normal((C, M)))
+    return {
+        "x": phantom(seed, H, W),
+        "S": coil_maps(seed + 7919, C, H, W),
+        "traj": radial_trajectory(seed + 15485863, H, W, n_spokes, n_read),
+        "noise": n.astype(np.complex64),
+    }
+
+
+def noncart_batch_inputs(seeds, H: int, W: int, C: int, n_spokes: int, n_read: int, sigma: float = 1e-3):
+    """Stack ``noncart_slice_inputs``: x [B,H,W], S [B,C,H,W], traj [B,M,2],
+    noise [B,C,M]."""
+    sl = [noncart_slice_inputs(s, H, W, C, n_spokes, n_read, sigma) for s in seeds]
     return {k: np.stack([d[k] for d in sl]) for k in sl[0]}
 
 
