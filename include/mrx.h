@@ -61,6 +61,7 @@ typedef struct mrx_plan_s* mrx_plan;
 #define MRX_PLAN_NETWORK 1u /* also reserve workspace for the CNN / MoDL calls */
 #define MRX_PLAN_VN 2u      /* also reserve workspace for the VarNet stage calls */
 #define MRX_PLAN_SOFT_SENSE 4u /* two sets of coil maps (soft-SENSE); see mrx_soft_* */
+#define MRX_PLAN_TOEPLITZ 8u   /* non-Cartesian sampling: normal operator by the PSF; see mrx_toeplitz_psf */
 
 /*
  * Parameters of one variational-network stage (device pointers): k = 24
@@ -107,7 +108,10 @@ const char* mrx_last_error(void);
  * stream (parallel branches when the stream is being captured).  Returns
  * MRX_EUNSUPPORTED for sizes without a schedule, MRX_EINVAL for bad counts.
  * flags: 0, or MRX_PLAN_NETWORK and/or MRX_PLAN_VN to size the workspace
- * for the MoDL network calls and the VarNet stage calls.  The column
+ * for the MoDL network calls and the VarNet stage calls; MRX_PLAN_SOFT_SENSE
+ * for two coil-map sets; MRX_PLAN_TOEPLITZ for non-Cartesian sampling (with
+ * MRX_PLAN_NETWORK at most; every H and W must then also satisfy
+ * mrx_toeplitz_supported).  The column
  * schedule of each size group comes from the in-process tuning cache
  * (filled by mrx_plan_autotune and mrx_tune_cache_load) when it holds an
  * entry for the group's (H, W, C, slice count), else the length's default;
@@ -212,6 +216,56 @@ mrx_status mrx_cg_dc_backward(mrx_plan plan, const float* gx, const float* x, co
                               int32_t accumulate, void* stream);
 
 /*
+ * Non-Cartesian SENSE (Extensions to the SENSE-Model subsection) on a plan
+ * created with MRX_PLAN_TOEPLITZ.  The sampling of slice b is a trajectory
+ * of M points (the same M for every slice), traj[(b M + j) 2 + {0, 1}] =
+ * (ky_j, kx_j) in cycles per field of view (float, device); pixel (r, s) of
+ * an H x W image sits at (r - H/2, s - W/2), and the forward model is the
+ * non-uniform DFT
+ *   y_{c,j} = (HW)^{-1/2} sum_{r,s} S_c[r,s] x[r,s] exp(-2 pi i (ky_j (r - H/2)/H + kx_j (s - W/2)/W)),
+ * evaluated exactly (no gridding), which on the Cartesian grid is the
+ * centred unitary DFT of the Cartesian calls.  k-space data y: [C][M]
+ * complex per slice, slices packed in order.  These three calls are the
+ * one-off steps the paper precomputes for a dataset; they run a sum over
+ * all samples per pixel (or pixels per sample) in fp32 with each phase
+ * formed in double precision, so they cost O(H W M C) and are not part of
+ * the iterations.
+ *
+ * mrx_nufft_fwd: y = A x (+ noise, [C][M] per slice, or NULL).
+ * mrx_nufft_adj: x = A^H y (the adjoint reconstruction).
+ * mrx_toeplitz_psf: psf = the real 2H x 2W spectrum of the sampling's
+ *   point spread function on the twice-padded grid, row-major [2H][2W] per
+ *   slice at offset 4 x (the slice's image offset):
+ *     psf[ky][kx] = (HW)^{-1} sum_j D_H(ky_j - ky/2) D_W(kx_j - kx/2),
+ *     D_n(u) = sum_{|d| < n} exp(2 pi i d u / n),
+ *   the unnormalised 2-D DFT of h[dy, dx] = (HW)^{-1} sum_j
+ *   exp(2 pi i (ky_j dy / H + kx_j dx / W)) laid out cyclically (offset
+ *   (dy, dx) at (dy mod 2H, dx mod 2W), zero on row H and column W).
+ *
+ * On a Toeplitz plan the operator calls take psf where the Cartesian calls
+ * take the row mask: mrx_sense_normal, mrx_cg_dc, mrx_dc_judge,
+ * mrx_modl_forward(_from) and mrx_modl_backward then use
+ *   A^H A u = sum_c conj(S_c) crop(IDFT(psf * DFT(pad(S_c u)))),
+ * (pad: u into the top-left H x W of a zero 2H x 2W grid, DFT the
+ * unnormalised 2-D DFT, IDFT its inverse, crop the top-left H x W), the
+ * Toeplitz form of the normal operator, in three passes per application
+ * through a workspace buffer of 2 x (the coil-sized count) complex values.
+ * mrx_sense_fwd / mrx_sense_adj, mrx_cg_dc_noalloc and the VarNet and
+ * soft-SENSE calls return MRX_EINVAL on such a plan; mrx_plan_autotune does
+ * nothing.  plan_create returns MRX_EUNSUPPORTED when 2H or 2W has no
+ * Toeplitz decomposition (see mrx_toeplitz_supported).  Errors: MRX_EINVAL
+ * for a null pointer or M outside [1, 2^26].
+ */
+mrx_status mrx_nufft_fwd(mrx_plan plan, const float* traj, int32_t M, const float* x, const float* S,
+                         const float* noise, float* y, void* stream);
+mrx_status mrx_nufft_adj(mrx_plan plan, const float* traj, int32_t M, const float* y, const float* S,
+                         float* x, void* stream);
+mrx_status mrx_toeplitz_psf(mrx_plan plan, const float* traj, int32_t M, float* psf, void* stream);
+/* 1 if image side n has Toeplitz kernels (a decomposition of 2n with first
+ * radix 2), else 0. */
+int32_t mrx_toeplitz_supported(int32_t n);
+
+/*
  * Soft-SENSE: the SENSE model with two sets of coil maps (Extensions to the
  * SENSE-Model subsection), for objects larger than the field of view:
  *   y_c = P F (S_{0,c} x_0 + S_{1,c} x_1),  (A^H y)_m = sum_c conj(S_{m,c}) F^H P^H y_c.
@@ -306,6 +360,20 @@ mrx_status mrx_cnn_layer_forward(mrx_plan plan, int32_t layer, const void* in, v
 mrx_status mrx_modl_forward(mrx_plan plan, const float* aHy, const float* S, const float* mask,
                             const float* lambda, int32_t T, int32_t n_cg, float* x_out,
                             float* states, void* stream);
+
+/*
+ * mrx_modl_forward from a given start image x^0 = x0 (image-sized, device)
+ * instead of aHy: the non-Cartesian networks start from the SENSE
+ * reconstruction x^0 = (A^H A + lambda I)^{-1} A^H y (Extensions to the
+ * SENSE-Model subsection; mrx_cg_dc with z = NULL computes it).  states[0]
+ * receives x0, so mrx_modl_backward applies unchanged to the weights and
+ * lambda; its g_aHy then holds the gradient through the data-consistency
+ * blocks plus the one reaching x^0 (the latter is the caller's to route
+ * through its x0).  x0 may alias x_out.
+ */
+mrx_status mrx_modl_forward_from(mrx_plan plan, const float* x0, const float* aHy, const float* S,
+                                 const float* mask, const float* lambda, int32_t T, int32_t n_cg,
+                                 float* x_out, float* states, void* stream);
 
 /*
  * Reverse mode of mrx_modl_forward from the stored states x^0..x^T: for

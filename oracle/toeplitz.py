@@ -162,3 +162,53 @@ def modl_forward(x0, aHy, S, P, weights, lam, T, n_cg, bf16=False):
         zs.append(z)
         states.append(x)
     return x, states, zs
+
+
+def modl_backward(g_out, states, zs, aHy, S, P, weights, lam, T, n_cg, bf16=False):
+    """Reverse mode of ``modl_forward`` (as ``oracle.modl.backward``, the
+    data-consistency blocks through the PSF form): each block's adjoint is
+    v = (A^H A + lambda I)^{-1} g (self-adjoint), g_z = lambda v,
+    g_lambda = Re<v, z - x>.  Returns (grads [(gW, gb)], g_lambda [B],
+    g_aHy, g_x0)."""
+    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64).reshape(-1), (np.shape(aHy)[0],))
+    g = _c(g_out)
+    gW = [(np.zeros_like(np.asarray(W, dtype=np.float64)),
+           np.zeros_like(np.asarray(b, dtype=np.float64))) for W, b in weights]
+    g_lam = np.zeros(lam.shape)
+    g_a = np.zeros_like(g)
+    for t in range(T - 1, -1, -1):
+        v, _ = ocg.cg(lambda u: normal(u, S, P, lam), g, n_cg)
+        g_lam += np.sum(np.conj(v) * (_c(zs[t]) - _c(states[t + 1])), axis=(-2, -1)).real
+        g_a += v
+        g, lg = cnn.denoise_backward(states[t], weights, lam[:, None, None] * v, bf16=bf16)
+        gW = [(a[0] + b[0], a[1] + b[1]) for a, b in zip(gW, lg)]
+    return gW, g_lam, g_a, g
+
+
+def nudft_adj_pixels(y, S, traj, pixels):
+    """A^H y at the listed pixels only ([(b, r, s), ...]): the definition
+    evaluated one pixel at a time (for spot checks of large images)."""
+    y, S = _c(y), _c(S)
+    _, C, H, W = S.shape
+    out = []
+    for b, r, s in pixels:
+        t = np.asarray(traj[b], dtype=np.float64)
+        e = np.exp(2j * np.pi * (t[:, 0] * (r - H // 2) / H + t[:, 1] * (s - W // 2) / W))
+        u = y[b] @ e / np.sqrt(H * W)  # [C]
+        out.append(np.sum(np.conj(S[b, :, r, s]) * u))
+    return np.array(out)
+
+
+def nudft_fwd_samples(x, S, traj, samples):
+    """A x at the listed samples only ([(b, j), ...]) -> [len, C]: the
+    definition evaluated one sample at a time (for spot checks)."""
+    x, S = _c(x), _c(S)
+    _, C, H, W = S.shape
+    r = np.arange(H) - H // 2
+    s = np.arange(W) - W // 2
+    out = []
+    for b, j in samples:
+        ky, kx = np.asarray(traj[b][j], dtype=np.float64)
+        e = np.exp(-2j * np.pi * (ky * r[:, None] / H + kx * s[None, :] / W))
+        out.append(np.sum(S[b] * x[b][None] * e[None], axis=(1, 2)) / np.sqrt(H * W))
+    return np.array(out)

@@ -58,6 +58,11 @@ SIGNATURES = {
     "mrx_cnn_layer_forward": (c_int32, [P, c_int32, P, P, P]),
     "mrx_cnn_backward": (c_int32, [P, P, P, P, P, c_int32, P]),
     "mrx_modl_forward": (c_int32, [P, P, P, P, P, c_int32, c_int32, P, P, P]),
+    "mrx_modl_forward_from": (c_int32, [P, P, P, P, P, P, c_int32, c_int32, P, P, P]),
+    "mrx_nufft_fwd": (c_int32, [P, P, c_int32, P, P, P, P, P]),
+    "mrx_nufft_adj": (c_int32, [P, P, c_int32, P, P, P, P]),
+    "mrx_toeplitz_psf": (c_int32, [P, P, c_int32, P, P]),
+    "mrx_toeplitz_supported": (c_int32, [c_int32]),
     "mrx_modl_backward": (c_int32, [P, P, P, P, P, P, P, c_int32, c_int32, P, P, P, c_int32, P]),
     "mrx_mse_grad": (c_int32, [P, P, P, P, P, P]),
     "mrx_adam_step": (c_int32, [P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),

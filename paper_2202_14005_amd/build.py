@@ -159,6 +159,42 @@ GENERIC_SCHEDULES = [g for g in (generic_schedule(n) for n in range(8, 1025, 2)
                                  if _smooth235(n) and n not in _TUNED) if g]
 SCHEDULES = SCHEDULES + GENERIC_SCHEDULES
 
+
+def toep_schedule(L: int):
+    """Decomposition of a padded transform length L = 2N for the Toeplitz
+    normal operator: L = 2 * N2 * N3 (first radix 2, so that the zero half of
+    a padded input is the digit-1 slots), N2, N3 <= 40, T a power of two
+    dividing every level's transform count, at most 48 points a thread.
+    Preference: fewest points a thread (at least 16), three levels.  Row
+    passes use one wavefront a workgroup (64 / T rows), the column pass
+    128 / T columns.  None if no decomposition fits."""
+    import math
+    N = L // 2
+    divs = lambda n: [d for d in range(1, n + 1) if n % d == 0]
+    best = None
+    for n2 in divs(N):
+        n3 = N // n2
+        if n2 < 2 or n2 > 40 or n3 > 40:
+            continue
+        g = math.gcd(math.gcd(L // 2, L // n2), L // n3)
+        for t in divs(g):
+            P = L // t
+            if t > 64 or t & (t - 1) or P > 48:
+                continue
+            score = (max(P, 16), 0 if n3 > 1 else 1, -n3)
+            if best is None or score < best[0]:
+                best = (score, (n2, n3, t))
+    if best is None:
+        return None
+    n2, n3, t = best[1]
+    return (f"t{L}_2x{n2}x{n3}_t{t}", n2, n3, t, max(1, 64 // t), max(1, 128 // t))
+
+
+# one Toeplitz schedule per padded length 2N of every image length N <= 512
+# that has a Cartesian schedule (and a decomposition)
+TOEP_SCHEDULES = [g for g in (toep_schedule(2 * n) for n in sorted({e[1] * e[2] * e[3] for e in SCHEDULES})
+                              if 2 * n <= 1024) if g]
+
 COMMON_SOURCES = ["api.hip", "ops.hip", "cg_kernels.hip", "autotune.hip", "net.hip", "conv.hip",
                   "conv_wgrad.hip", "vn.hip", "judge.hip"]
 
@@ -172,7 +208,7 @@ HIP_FLAGS = [
 
 def _extra_sources():
     return [s for s in sorted(os.listdir(CSRC))
-            if s.endswith(".hip") and s not in COMMON_SOURCES and s != "sense_inst.hip"]
+            if s.endswith(".hip") and s not in COMMON_SOURCES and s not in ("sense_inst.hip", "toep_inst.hip")]
 
 
 def _jobs():
@@ -195,6 +231,10 @@ def _jobs():
                 f"-DMRX_WTC={wtc}", f"-DMRX_WTR={wtr}", f"-DMRX_G={g}", f"-DMRX_KS={ks}",
                 f"-DMRX_WL={wl}", f"-DMRX_KSPL={kspl}", f"-DMRX_SOFT={soft}", f'-DMRX_NAME="{name}"']
         jobs.append((os.path.join(CSRC, "sense_inst.hip"), os.path.join(BUILD, f"sched_{name}.o"), defs))
+    for name, n2, n3, t, twr, twc in TOEP_SCHEDULES:
+        defs = [f"-DMRX_N2={n2}", f"-DMRX_N3={n3}", f"-DMRX_T={t}", f"-DMRX_TWR={twr}", f"-DMRX_TWC={twc}",
+                f'-DMRX_NAME="{name}"']
+        jobs.append((os.path.join(CSRC, "toep_inst.hip"), os.path.join(BUILD, f"toep_{name}.o"), defs))
     return jobs
 
 

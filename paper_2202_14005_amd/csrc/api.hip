@@ -62,6 +62,16 @@ static std::vector<SoftVariant>& soft_registry() {
   return v;
 }
 void register_soft_variant(const SoftVariant& v) { soft_registry().push_back(v); }
+static std::vector<ToepVariant>& toep_registry() {
+  static std::vector<ToepVariant> v;
+  return v;
+}
+void register_toep_variant(const ToepVariant& v) { toep_registry().push_back(v); }
+const ToepVariant* find_toep(int N) {
+  for (auto& v : toep_registry())
+    if (v.N == N) return &v;
+  return nullptr;
+}
 const SoftVariant* find_soft(int N) {
   for (auto& v : soft_registry())
     if (v.N == N) return &v;
@@ -107,20 +117,27 @@ int32_t mrx_supported_length(int32_t n) {
   return (find_col(n, nullptr) && find_row(n)) ? 1 : 0;
 }
 
+int32_t mrx_toeplitz_supported(int32_t n) {
+  return (n > 0 && n <= 512 && mrx_supported_length(n) && find_toep(2 * n)) ? 1 : 0;
+}
+
 mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int32_t* W,
                            const int32_t* C, uint32_t flags) {
   if (!out) return fail(MRX_EINVAL, "plan_create: null plan pointer");
   *out = nullptr;
   if (B <= 0 || B > (1 << 20)) return fail(MRX_EINVAL, "plan_create: batch size must be in [1, 2^20]");
   if (!H || !W || !C) return fail(MRX_EINVAL, "plan_create: null shape array");
-  if (flags & ~(MRX_PLAN_NETWORK | MRX_PLAN_VN | MRX_PLAN_SOFT_SENSE))
+  if (flags & ~(MRX_PLAN_NETWORK | MRX_PLAN_VN | MRX_PLAN_SOFT_SENSE | MRX_PLAN_TOEPLITZ))
     return fail(MRX_EINVAL, "plan_create: unknown flags");
   if ((flags & MRX_PLAN_SOFT_SENSE) && (flags & MRX_PLAN_VN))
     return fail(MRX_EINVAL, "plan_create: soft-SENSE plans have no VarNet workspace");
+  if ((flags & MRX_PLAN_TOEPLITZ) && (flags & (MRX_PLAN_VN | MRX_PLAN_SOFT_SENSE)))
+    return fail(MRX_EINVAL, "plan_create: Toeplitz plans take neither MRX_PLAN_VN nor MRX_PLAN_SOFT_SENSE");
   auto* p = new mrx_plan_s();
   p->B = B;
   p->flags = flags;
   p->sets = (flags & MRX_PLAN_SOFT_SENSE) ? 2 : 1;
+  p->toep = (flags & MRX_PLAN_TOEPLITZ) != 0;
   int64_t xo = 0, so = 0, mo = 0;
   for (int b = 0; b < B; ++b) {
     const int h = H[b], w = W[b], c = C[b];
@@ -173,8 +190,29 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
       g.rowW = find_row(g.W);
       g.rowH = find_row(g.H);
       g.soft = find_soft(g.H);
+      if (p->toep) {
+        g.toepH = find_toep(2 * g.H);
+        g.toepW = find_toep(2 * g.W);
+      }
     }
   }
+  if (p->toep)
+    for (auto& g : p->groups) {
+      if (!g.toepH || !g.toepW) {
+        delete p;
+        return fail(MRX_EUNSUPPORTED, "plan_create: no Toeplitz kernels for " + std::to_string(g.H) + "x" +
+                                          std::to_string(g.W) + " (padded lengths " + std::to_string(2 * g.H) +
+                                          ", " + std::to_string(2 * g.W) + ")");
+      }
+      // enough workgroups for the chip: about 2048 single-wavefront row
+      // workgroups and 1024 column workgroups a pass
+      const int ns = (int)g.slices.size();
+      const int rblk = (g.H + g.toepW->rows_wt - 1) / g.toepW->rows_wt;
+      const int ctil = (2 * g.W + g.toepH->cols_wt - 1) / g.toepH->cols_wt;
+      g.toep_split1 = std::max(1, std::min(g.maxC, (2048 + rblk * ns - 1) / (rblk * ns)));
+      g.toep_split2 = std::max(1, std::min(g.maxC, (1024 + ctil * ns - 1) / (ctil * ns)));
+      g.toep_split3 = std::max(1, std::min(std::min(g.maxC, KSPL_MAX), (2048 + rblk * ns - 1) / (rblk * ns)));
+    }
   if (p->sets > 1)
     for (auto& g : p->groups)
       if (!g.soft) {
@@ -183,6 +221,9 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
       }
   refresh_desc(p, false);
   p->npq = (p->maxW + 1) / 2;  // upper bound on column tiles x coil split (tile width >= 8)
+  for (auto& g : p->groups)
+    if (p->toep)
+      p->npq = std::max(p->npq, ((g.H + g.toepW->rows_wt - 1) / g.toepW->rows_wt) * g.toep_split3);
   p->nrr = (int)((p->sets * p->maxHW + CG_EPB - 1) / CG_EPB);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { delete p; return hip_fail(e, "plan_create: hipGetDevice"); }
@@ -192,6 +233,10 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   for (auto& g : p->groups) {
     if (std::find(lens.begin(), lens.end(), g.H) == lens.end()) lens.push_back(g.H);
     if (std::find(lens.begin(), lens.end(), g.W) == lens.end()) lens.push_back(g.W);
+    if (p->toep) {
+      if (std::find(lens.begin(), lens.end(), 2 * g.H) == lens.end()) lens.push_back(2 * g.H);
+      if (std::find(lens.begin(), lens.end(), 2 * g.W) == lens.end()) lens.push_back(2 * g.W);
+    }
   }
   for (int n : lens) tb += align256(sizeof(float2) * n);
   e = hipMalloc(&p->d_tables, tb);
@@ -252,6 +297,7 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   p->ws_part = take(sizeof(float) * B * p->nrr);
   p->ws_stop = take(sizeof(int) * B);
   p->ws_status = take(sizeof(uint32_t) * B);
+  if (p->toep) p->ws_tbuf = take(sizeof(float2) * 2 * p->n_coil);
   p->ws_bytes_base = w;
   p->ws_bytes = w + extra_workspace_bytes(p);
   // auxiliary streams for concurrent size groups (at most 3: with the
@@ -342,6 +388,7 @@ mrx_status mrx_sense_fwd(mrx_plan p, const float* x, const float* S, const float
                          const float* noise, float* y, void* stream) {
   if (!p) return fail(MRX_EINVAL, "sense_fwd: null plan");
   if (!x || !S || !mask || !y) return fail(MRX_EINVAL, "sense_fwd: null data pointer");
+  if (p->toep) return fail(MRX_EINVAL, "sense_fwd: Toeplitz plan (the forward model is mrx_nufft_fwd)");
   hipStream_t s = (hipStream_t)stream;
   for (auto& g : p->groups) {
     SenseColArgs ca{p->d_desc, g.d_slices, (int)g.slices.size(), (const float2*)S, mask,
@@ -360,6 +407,7 @@ mrx_status mrx_sense_adj(mrx_plan p, const float* y, const float* S, const float
                          void* stream) {
   if (!p) return fail(MRX_EINVAL, "sense_adj: null plan");
   if (!y || !S || !mask || !x) return fail(MRX_EINVAL, "sense_adj: null data pointer");
+  if (p->toep) return fail(MRX_EINVAL, "sense_adj: Toeplitz plan (the adjoint is mrx_nufft_adj)");
   if (!p->ws) return fail(MRX_ENOWORKSPACE, "sense_adj: workspace not set");
   return sense_adj_impl(p, (const float2*)y, (const float2*)S, mask, (float2*)x, (hipStream_t)stream);
 }
@@ -369,6 +417,7 @@ mrx_status mrx_sense_normal(mrx_plan p, const float* x, const float* S, const fl
   if (!p) return fail(MRX_EINVAL, "sense_normal: null plan");
   if (!x || !S || !mask || !out) return fail(MRX_EINVAL, "sense_normal: null data pointer");
   if (x == out) return fail(MRX_EINVAL, "sense_normal: input and output must not alias");
+  if (p->toep && !p->ws) return fail(MRX_ENOWORKSPACE, "sense_normal: workspace not set (Toeplitz plan)");
   return normal_impl(p, (const float2*)x, (const float2*)S, mask, lambda, (float2*)out, (hipStream_t)stream);
 }
 

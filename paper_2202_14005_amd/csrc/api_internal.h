@@ -21,6 +21,12 @@ struct Group {
   const RowVariant* rowW = nullptr;  // transform along W (row pass)
   const RowVariant* rowH = nullptr;
   const SoftVariant* soft = nullptr;  // soft-SENSE kernels (plans with two map sets)
+  // Toeplitz plans: the padded-length kernels (2H: column pass, 2W: row
+  // passes), the coil groups of the first two passes and the output planes
+  // of the last in CG steps
+  const ToepVariant* toepH = nullptr;
+  const ToepVariant* toepW = nullptr;
+  int toep_split1 = 1, toep_split2 = 1, toep_split3 = 1;
 };
 
 }  // namespace mrx
@@ -40,6 +46,10 @@ struct mrx_plan_s {
   // CG element kernels
   int sets = 1;
   mrx::SliceDesc* d_desc_soft = nullptr;
+  // non-Cartesian plan (MRX_PLAN_TOEPLITZ): the normal operator is the PSF
+  // convolution; ws_tbuf holds the padded per-coil spectra [C][H][2W]
+  bool toep = false;
+  size_t ws_tbuf = 0;
   // device tables (plan owned)
   void* d_tables = nullptr;
   mrx::SliceDesc* d_desc = nullptr;
@@ -97,6 +107,7 @@ mrx_status hip_fail(hipError_t e, const char* what);
 const ColVariant* find_col(int N, const char* name);
 const RowVariant* find_row(int N);
 const SoftVariant* find_soft(int N);
+const ToepVariant* find_toep(int N);
 std::vector<const ColVariant*> col_variants(int N);
 
 extern std::mutex g_tune_mu;
@@ -179,5 +190,9 @@ mrx_status soft_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const 
                          hipStream_t s);
 mrx_status soft_normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
                             float2* out, hipStream_t s);
+// Toeplitz plans: the three passes of the normal operator for one size
+// group (a.pin .. a.stopped as for a plain application or a CG step; tw,
+// split and the buffer are filled in here)
+hipError_t toep_apply(mrx_plan_s* p, Group& g, ToepArgs a, hipStream_t s);
 
 }  // namespace mrx

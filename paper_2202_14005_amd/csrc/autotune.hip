@@ -21,6 +21,7 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
                                         void* stream) {
   if (!p) return fail(MRX_EINVAL, "autotune: null plan");
   if (!S || !mask || !a || !b) return fail(MRX_EINVAL, "autotune: null data pointer");
+  if (p->toep) return MRX_OK;  // one Toeplitz schedule per padded length: nothing to choose
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

@@ -344,8 +344,14 @@ mrx_status mrx_cnn_layer_forward(mrx_plan p, int32_t layer, const void* in, void
 
 mrx_status mrx_modl_forward(mrx_plan p, const float* aHy, const float* S, const float* mask, const float* lambda,
                             int32_t T, int32_t n_cg, float* x_out, float* states, void* stream) {
+  return mrx_modl_forward_from(p, aHy, aHy, S, mask, lambda, T, n_cg, x_out, states, stream);
+}
+
+mrx_status mrx_modl_forward_from(mrx_plan p, const float* x0, const float* aHy, const float* S, const float* mask,
+                                 const float* lambda, int32_t T, int32_t n_cg, float* x_out, float* states,
+                                 void* stream) {
   if (!p) return fail(MRX_EINVAL, "modl_forward: null plan");
-  if (!aHy || !S || !mask || !lambda || !x_out) return fail(MRX_EINVAL, "modl_forward: null data pointer");
+  if (!x0 || !aHy || !S || !mask || !lambda || !x_out) return fail(MRX_EINVAL, "modl_forward: null data pointer");
   if (T < 0 || T > 1000 || n_cg < 0 || n_cg > 100000) return fail(MRX_EINVAL, "modl_forward: T or n_cg out of range");
   mrx_status st = net_ready(p, "modl_forward");
   if (st != MRX_OK) return st;
@@ -353,13 +359,13 @@ mrx_status mrx_modl_forward(mrx_plan p, const float* aHy, const float* S, const 
   const int64_t ni = p->n_image;
   float2* z = (float2*)(p->ws + p->ws_z);
   float2* st2 = (float2*)states;
-  const float2* prev = (const float2*)aHy;
+  const float2* prev = (const float2*)x0;
   if (st2) {
-    hipError_t e = copy_c((const float2*)aHy, st2, ni, s);
+    hipError_t e = copy_c((const float2*)x0, st2, ni, s);
     if (e != hipSuccess) return hip_fail(e, "modl_forward: copy");
   }
   if (T == 0) {
-    hipError_t e = copy_c((const float2*)aHy, (float2*)x_out, ni, s);
+    hipError_t e = copy_c((const float2*)x0, (float2*)x_out, ni, s);
     return e == hipSuccess ? MRX_OK : hip_fail(e, "modl_forward: copy");
   }
   for (int t = 0; t < T; ++t) {

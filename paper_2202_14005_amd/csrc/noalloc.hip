@@ -77,6 +77,7 @@ extern "C" mrx_status mrx_cg_dc_noalloc(mrx_plan p, const float* aHy, const floa
   if (!p) return fail(MRX_EINVAL, "cg_dc_noalloc: null plan");
   if (!aHy || !S || !mask || !lambda || !x) return fail(MRX_EINVAL, "cg_dc_noalloc: null data pointer");
   if (n_iter < 0 || n_iter > 100000) return fail(MRX_EINVAL, "cg_dc_noalloc: n_iter out of range");
+  if (p->toep) return fail(MRX_EINVAL, "cg_dc_noalloc: Toeplitz plans need the workspace (use mrx_cg_dc)");
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "cg_dc_noalloc: hipGetDevice");

@@ -26,7 +26,8 @@ hipError_t clear_status(mrx_plan_s* p, hipStream_t s) {
 
 mrx_status refresh_desc(mrx_plan_s* p, bool upload) {
   for (auto& g : p->groups)
-    for (int b : g.slices) p->desc[b].nq = (g.col && g.col->kspl > 1) ? g.col->kspl : 1;
+    for (int b : g.slices)
+      p->desc[b].nq = p->toep ? g.toep_split3 : (g.col && g.col->kspl > 1) ? g.col->kspl : 1;
   if (!upload) return MRX_OK;
   hipError_t e = hipMemcpy(p->d_desc, p->desc.data(), sizeof(SliceDesc) * p->B, hipMemcpyHostToDevice);
   return e == hipSuccess ? MRX_OK : hip_fail(e, "plan: descriptor upload");
@@ -75,8 +76,44 @@ mrx_status sense_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const
   return MRX_OK;
 }
 
+hipError_t toep_apply(mrx_plan_s* p, Group& g, ToepArgs a, hipStream_t s) {
+  const bool cg = a.mode == 1;
+  a.slices = g.d_slices;
+  a.nslices = (int)g.slices.size();
+  a.tbuf = (float2*)(p->ws + p->ws_tbuf);
+  a.tw = p->tw.at(2 * g.W);
+  a.split = g.toep_split1;
+  hipError_t e = g.toepW->rows_fwd(a, g.H, s);
+  if (e != hipSuccess) return e;
+  a.tw = p->tw.at(2 * g.H);
+  a.split = g.toep_split2;
+  e = g.toepH->cols(a, 2 * g.W, s);
+  if (e != hipSuccess) return e;
+  a.tw = p->tw.at(2 * g.W);
+  a.split = cg ? g.toep_split3 : 1;
+  return g.toepW->rows_adj(a, g.H, s);
+}
+
+static mrx_status toep_normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* psf,
+                                   const float* lam, float2* out, hipStream_t s) {
+  KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
+  hipError_t e = for_groups(p, s, [&](Group& g, hipStream_t sg) {
+    ToepArgs a{};
+    a.desc = p->d_desc;
+    a.S = S;
+    a.psf = psf;
+    a.lam = lam;
+    a.pin = x;
+    a.qout = out;
+    a.mode = 0;
+    return toep_apply(p, g, a, sg);
+  });
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "toeplitz normal operator");
+}
+
 mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
                        float2* out, hipStream_t s) {
+  if (p->toep) return toep_normal_impl(p, x, S, mask, lam, out, s);
   KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
   hipError_t e = for_groups(p, s, [&](Group& g, hipStream_t sg) {
     NormalArgs na{};
@@ -187,6 +224,27 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
     {
       KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
       e = for_groups(p, s, [&](Group& g, hipStream_t sg) {
+        if (p->toep) {
+          ToepArgs ta{};
+          ta.desc = p->d_desc;
+          ta.S = S;
+          ta.psf = mask;
+          ta.lam = lam;
+          ta.pin = pb[k == 0 ? 0 : ((k - 1) & 1)];
+          ta.qout = q;
+          ta.qstride = p->n_image;
+          ta.mode = 1;
+          ta.iter = k;
+          ta.r = r;
+          ta.pout = pb[k & 1];
+          ta.rr_cur = rr_cur;
+          ta.rr_prev = rr_prev;
+          ta.nrr = p->nrr;
+          ta.pq_part = pq;
+          ta.npq = p->npq;
+          ta.stopped = a.stopped;
+          return toep_apply(p, g, ta, sg);
+        }
         NormalArgs na{};
         na.desc = p->d_desc;
         na.slices = g.d_slices;

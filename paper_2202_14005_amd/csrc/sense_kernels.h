@@ -92,6 +92,46 @@ struct SoftVariant {
   const char* name;
 };
 
+// Toeplitz normal operator of non-Cartesian SENSE (kernels in toeplitz.h):
+// arguments of its three passes and the kernels of one padded length.
+struct ToepArgs {
+  const SliceDesc* desc;
+  const int* slices;
+  int nslices;
+  const float2* S;     // coil maps (SENSE layout)
+  const float* psf;    // real [2H][2W] per slice at 4 xoff
+  const float* lam;    // per-slice lambda or null
+  const float2* pin;   // operand
+  float2* qout;        // result (partial planes qstride apart in CG steps)
+  int64_t qstride;
+  float2* tbuf;        // [C][H][2W] per slice at 2 soff
+  const float2* tw;    // exp(-2 pi i j / N) for the kernel's length N
+  int split;           // coil groups (first two passes) / output planes (last)
+  // CG step (mode 1): as NormalArgs
+  int mode, iter;
+  const float2* r;
+  float2* pout;
+  const float* rr_cur;
+  const float* rr_prev;
+  int nrr;
+  float* pq_part;
+  int npq;
+  const int* stopped;
+};
+
+using ToepFn = hipError_t (*)(const ToepArgs&, int maxdim, hipStream_t);
+
+struct ToepVariant {
+  int N;             // transform length (twice an image side)
+  ToepFn rows_fwd;   // first pass (N = 2W)
+  ToepFn cols;       // middle pass (N = 2H)
+  ToepFn rows_adj;   // last pass (N = 2W)
+  int rows_wt;       // rows per workgroup of the row passes
+  int cols_wt;       // columns per workgroup of the column pass
+  const char* name;
+};
+void register_toep_variant(const ToepVariant& v);
+
 void register_col_variant(const ColVariant& v);
 void register_row_variant(const RowVariant& v);
 void register_soft_variant(const SoftVariant& v);

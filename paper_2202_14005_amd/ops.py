@@ -33,7 +33,7 @@ class Plan:
     sequences (uneven batch)."""
 
     def __init__(self, H, W, C, B: int | None = None, device=None, network: bool = False, vn: bool = False,
-                 soft: bool = False):
+                 soft: bool = False, toeplitz: bool = False):
         L = lib()
         if isinstance(H, int):
             if B is None:
@@ -51,11 +51,12 @@ class Plan:
         arr = lambda v: (ctypes.c_int32 * len(v))(*v)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            flags = (1 if network else 0) | (2 if vn else 0) | (4 if soft else 0)
+            flags = (1 if network else 0) | (2 if vn else 0) | (4 if soft else 0) | (8 if toeplitz else 0)
             check(L.mrx_plan_create(ctypes.byref(h), self.B, arr(Hs), arr(Ws), arr(Cs), flags), "plan_create")
         self.network = network
         self.vn = vn
         self.soft = soft
+        self.toeplitz = toeplitz
         self._weights_key = None
         self._h = h
         ni, nc, nm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -85,7 +86,54 @@ class Plan:
         return self._chk(t, name, self.n_coil, torch.complex64, (self.B, self.C[0], self.H[0], self.W[0]))
 
     def _mask(self, t, name):
+        """The sampling argument: the row mask, or on a Toeplitz plan the PSF
+        spectrum (float32 [B, 2H, 2W])."""
+        if self.toeplitz:
+            return self._chk(t, name, 4 * self.n_image, torch.float32, (self.B, 2 * self.H[0], 2 * self.W[0]))
         return self._chk(t, name, self.n_mask, torch.float32, (self.B, self.H[0]))
+
+    # ------------------------------------------------------ non-Cartesian
+    def _traj(self, traj):
+        if not isinstance(traj, torch.Tensor) or traj.dtype != torch.float32 or not traj.is_contiguous():
+            raise TypeError("traj must be a contiguous float32 tensor [B, M, 2]")
+        if traj.dim() != 3 or traj.shape[0] != self.B or traj.shape[2] != 2:
+            raise ValueError(f"traj must have shape [B, M, 2], got {tuple(traj.shape)}")
+        return int(traj.shape[1])
+
+    def nufft_fwd(self, x, S, traj, noise=None, out=None):
+        """y = A x (+ noise): the non-uniform DFT of the coil images at the
+        trajectory, complex64 [B, C, M] (even batch; packed otherwise)."""
+        M = self._traj(traj)
+        self._img(x, "x"); self._coil(S, "S")
+        n = sum(self.C) * M
+        y = out if out is not None else torch.empty(
+            (self.B, self.C[0], M) if self.even else (n,), dtype=torch.complex64, device=self.device)
+        for t, nm in ((y, "out"), (noise, "noise")):
+            if t is not None and (t.dtype != torch.complex64 or t.numel() != n or not t.is_contiguous()):
+                raise ValueError(f"{nm} must be a contiguous complex64 tensor of {n} elements")
+        check(lib().mrx_nufft_fwd(self._h, _ptr(traj), M, _ptr(x), _ptr(S), _ptr(noise), _ptr(y),
+                                  _stream(self.device)), "nufft_fwd")
+        return y
+
+    def nufft_adj(self, y, S, traj, out=None):
+        """x = A^H y, the adjoint reconstruction from non-Cartesian data."""
+        M = self._traj(traj)
+        self._coil(S, "S")
+        if y.dtype != torch.complex64 or y.numel() != sum(self.C) * M or not y.is_contiguous():
+            raise ValueError("y must be a contiguous complex64 tensor of sum(C) * M elements")
+        x = self._img(out, "out") if out is not None else self._empty_img()
+        check(lib().mrx_nufft_adj(self._h, _ptr(traj), M, _ptr(y), _ptr(S), _ptr(x), _stream(self.device)),
+              "nufft_adj")
+        return x
+
+    def toeplitz_psf(self, traj, out=None):
+        """The real PSF spectrum on the twice-padded grid, float32 [B, 2H, 2W]."""
+        M = self._traj(traj)
+        shape = (self.B, 2 * self.H[0], 2 * self.W[0]) if self.even else (4 * self.n_image,)
+        o = out if out is not None else torch.empty(shape, dtype=torch.float32, device=self.device)
+        self._chk(o, "out", 4 * self.n_image, torch.float32, (self.B, 2 * self.H[0], 2 * self.W[0]))
+        check(lib().mrx_toeplitz_psf(self._h, _ptr(traj), M, _ptr(o), _stream(self.device)), "toeplitz_psf")
+        return o
 
     def _chk(self, t, name, numel, dtype, even_shape):
         if t is None:
@@ -280,17 +328,22 @@ class Plan:
                                      int(bool(accumulate)), _stream(self.device)), "cnn_backward")
         return gx
 
-    def modl_forward(self, aHy, S, mask, cnn: "CNN", lam, T, n_cg, states=False, out=None):
-        """x^T of eq. update_modl from x^0 = aHy; with states=True also the
-        iterates x^0..x^T [T + 1, ...]."""
-        self._img(aHy, "aHy"); self._coil(S, "S"); self._mask(mask, "mask")
+    def modl_forward(self, aHy, S, mask, cnn: "CNN", lam, T, n_cg, states=False, out=None, x0=None):
+        """x^T of eq. update_modl from x^0 = aHy (or from ``x0``, as the
+        non-Cartesian networks start from a SENSE reconstruction); with
+        states=True also the iterates x^0..x^T [T + 1, ...]."""
+        self._img(aHy, "aHy"); self._coil(S, "S"); self._mask(mask, "mask"); self._img(x0, "x0")
         self.set_weights(cnn)
         lt = self.lam(lam)
         x = self._img(out, "out") if out is not None else self._empty_img()
         st = (torch.empty((T + 1,) + tuple(x.shape), dtype=torch.complex64, device=self.device)
               if states else None)
-        check(lib().mrx_modl_forward(self._h, _ptr(aHy), _ptr(S), _ptr(mask), _ptr(lt), int(T), int(n_cg),
-                                     _ptr(x), _ptr(st), _stream(self.device)), "modl_forward")
+        if x0 is None:
+            check(lib().mrx_modl_forward(self._h, _ptr(aHy), _ptr(S), _ptr(mask), _ptr(lt), int(T), int(n_cg),
+                                         _ptr(x), _ptr(st), _stream(self.device)), "modl_forward")
+        else:
+            check(lib().mrx_modl_forward_from(self._h, _ptr(x0), _ptr(aHy), _ptr(S), _ptr(mask), _ptr(lt), int(T),
+                                              int(n_cg), _ptr(x), _ptr(st), _stream(self.device)), "modl_forward")
         return (x, st) if states else x
 
     def modl_backward(self, g_out, states, aHy, S, mask, cnn: "CNN", lam, T, n_cg, grads: "CNNGrads",

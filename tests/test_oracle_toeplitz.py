@@ -184,3 +184,54 @@ def test_radial_generator_covers_the_extent():
     assert t[:, 0].min() >= -16 and t[:, 0].max() < 16 and t[:, 1].min() >= -12 and t[:, 1].max() < 12
     d = noncart_slice_inputs(5, 16, 16, 4, 5, 32)
     assert d["noise"].shape == (4, 160)
+
+
+def test_adjoint_at_pixels_matches_full(rng):
+    B, C, H, W, M = 2, 3, 7, 6, 25
+    S = rand_c(rng, B, C, H, W)
+    traj = rand_traj(rng, B, M, H, W)
+    y = rand_c(rng, B, C, M)
+    full = tp.nudft_adj(y, S, traj)
+    pix = [(0, 0, 0), (1, 6, 5), (1, 3, 2), (0, 4, 1)]
+    got = tp.nudft_adj_pixels(y, S, traj, pix)
+    assert np.max(np.abs(got - np.array([full[b, r, s] for b, r, s in pix]))) < 1e-13
+
+
+def test_modl_backward_finite_differences(rng):
+    """g_lambda and one weight entry of the non-Cartesian MoDL reverse pass
+    against central differences of L = Re<g, x^T>."""
+    from oracle import cnn as ocnn
+    B, C, H, W, M = 1, 2, 6, 6, 30
+    S = rand_c(rng, B, C, H, W) * 0.5
+    traj = rand_traj(rng, B, M, H, W)
+    P = tp.psf(traj, H, W)
+    aHy = tp.nudft_adj(rand_c(rng, B, C, M), S, traj)
+    ch = [2, 4, 4, 4, 4, 2]
+    wts = [(rng.standard_normal((ch[l + 1], ch[l], 3, 3)) * 0.3, rng.standard_normal(ch[l + 1]) * 0.1)
+           for l in range(5)]
+    lam, T, n = 0.3, 2, 60
+    x0 = tp.sense_init(aHy, S, P, lam, n)
+    g = rand_c(rng, B, H, W)
+    xT, states, zs = tp.modl_forward(x0, aHy, S, P, wts, lam, T, n)
+    gW, gl, _, _ = tp.modl_backward(g, states, zs, aHy, S, P, wts, lam, T, n)
+    L = lambda x: np.sum(np.conj(g) * x).real
+    eps = 1e-6
+    lp = L(tp.modl_forward(x0, aHy, S, P, wts, lam + eps, T, n)[0])
+    lm = L(tp.modl_forward(x0, aHy, S, P, wts, lam - eps, T, n)[0])
+    assert abs((lp - lm) / (2 * eps) - gl[0]) < 1e-5 * max(1.0, abs(gl[0]))
+    w2 = [(W_.copy(), b_.copy()) for W_, b_ in wts]
+    w2[2][0][1, 3, 0, 2] += eps
+    lp = L(tp.modl_forward(x0, aHy, S, P, w2, lam, T, n)[0])
+    w2[2][0][1, 3, 0, 2] -= 2 * eps
+    lm = L(tp.modl_forward(x0, aHy, S, P, w2, lam, T, n)[0])
+    assert abs((lp - lm) / (2 * eps) - gW[2][0][1, 3, 0, 2]) < 1e-5 * max(1.0, abs(gW[2][0][1, 3, 0, 2]))
+
+
+def test_forward_at_samples_matches_full(rng):
+    B, C, H, W, M = 2, 3, 6, 8, 21
+    x, S = rand_c(rng, B, H, W), rand_c(rng, B, C, H, W)
+    traj = rand_traj(rng, B, M, H, W)
+    full = tp.nudft_fwd(x, S, traj)
+    sm = [(0, 0), (1, 20), (0, 7)]
+    got = tp.nudft_fwd_samples(x, S, traj, sm)
+    assert np.max(np.abs(got - np.array([full[b, :, j] for b, j in sm]))) < 1e-13
