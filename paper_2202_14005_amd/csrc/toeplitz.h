@@ -103,9 +103,12 @@ k_toep_rows_fwd(ToepArgs a) {
 // ----------------------------------------------------------- middle pass
 // WT frequency columns a workgroup (of the 2W), T threads a column, the
 // column's PSF values in registers for all the group's coils; grid.x =
-// column tiles x coil groups, grid.y = slices.  The transform chain forward,
-// inverse, forward, ... allows the post-write-only barriers of the
-// Cartesian operator.
+// column tiles x coil groups (rounded up to a multiple of 16), grid.y =
+// slices.  Tiles 2k and 2k + 1 (the two halves of a 128-byte row segment
+// for WT = 8) get block ids 8 apart, so that they run on the same XCD
+// (workgroups go to the 8 XCDs in turn) and share its L2.  The transform
+// chain forward, inverse, forward, ... allows the post-write-only barriers
+// of the Cartesian operator.
 template <class Sd, int WT>
 __global__ void __launch_bounds__(Sd::T * WT, 2)
 k_toep_cols(ToepArgs a) {
@@ -119,7 +122,9 @@ k_toep_cols(ToepArgs a) {
   if (2 * d.H != N) return;
   const int W2 = 2 * d.W, C = d.C;
   const int tiles = (W2 + WT - 1) / WT;
-  const int tile = blockIdx.x % tiles, grp = blockIdx.x / tiles;
+  const int Lb = blockIdx.x;
+  const int ug = (((Lb >> 4) * 8 + (Lb & 7)) << 1) + ((Lb >> 3) & 1);
+  const int tile = ug % tiles, grp = ug / tiles;
   if (grp >= a.split) return;
   if (a.mode == 1 && a.stopped[b]) return;
   const int c_begin = grp * C / a.split, c_end = (grp + 1) * C / a.split;
@@ -232,7 +237,8 @@ hipError_t launch_toep_rows_fwd(const ToepArgs& a, int maxH, hipStream_t s) {
 }
 template <class Sd, int WT>
 hipError_t launch_toep_cols(const ToepArgs& a, int maxW2, hipStream_t s) {
-  dim3 grid((unsigned)(((maxW2 + WT - 1) / WT) * a.split), (unsigned)a.nslices);
+  const int n = ((maxW2 + WT - 1) / WT) * a.split;
+  dim3 grid((unsigned)(((n + 15) / 16) * 16), (unsigned)a.nslices);
   hipLaunchKernelGGL((k_toep_cols<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
   return hipGetLastError();
 }
