@@ -62,6 +62,7 @@ typedef struct mrx_plan_s* mrx_plan;
 #define MRX_PLAN_VN 2u      /* also reserve workspace for the VarNet stage calls */
 #define MRX_PLAN_SOFT_SENSE 4u /* two sets of coil maps (soft-SENSE); see mrx_soft_* */
 #define MRX_PLAN_TOEPLITZ 8u   /* non-Cartesian sampling: normal operator by the PSF; see mrx_toeplitz_psf */
+#define MRX_PLAN_BATCHNORM 16u /* denoiser with batch normalisation (needs MRX_PLAN_NETWORK); see mrx_cnn_set_bn */
 
 /*
  * Parameters of one variational-network stage (device pointers): k = 24
@@ -314,7 +315,8 @@ mrx_status mrx_status_word(mrx_plan plan, uint32_t* dev_flags, int32_t clear, vo
 /*
  * MoDL residual denoiser D(x) = x + N(x) (MoDL subsection: a residual network
  * of L = 5 convolution layers with F = 64 channels and ReLU; batch
- * normalisation is not used).  N: 3x3 convolutions with zero "same" padding
+ * normalisation only on plans created with MRX_PLAN_BATCHNORM, see
+ * mrx_cnn_set_bn).  N: 3x3 convolutions with zero "same" padding
  * and bias, ReLU after layers 1-4; the complex image enters as channels
  * (real, imag).  Convolutions run on bf16 MFMA with fp32 accumulation; the
  * layer activations are stored as bf16.  Needs a plan created with
@@ -332,6 +334,29 @@ mrx_status mrx_status_word(mrx_plan plan, uint32_t* dev_flags, int32_t clear, vo
  * `stream`: calls on other streams must be ordered after it.
  */
 mrx_status mrx_cnn_set_weights(mrx_plan plan, const mrx_cnn_params* w, void* stream);
+
+/*
+ * Batch normalisation of the denoiser (the MoDL subsection's conv + BN +
+ * ReLU layers), on a plan created with MRX_PLAN_BATCHNORM | MRX_PLAN_NETWORK:
+ * each hidden layer l < 4 becomes
+ *   y = conv(a, W_l)  (no bias: the layer's bias is not used and its
+ *                      gradient is written as zero),
+ *   a' = ReLU(gamma_l (y - mu) / sqrt(var + 1e-5) + beta_l),
+ * with mu, var the mean and biased variance of y per channel over every
+ * pixel of the plan's batch (the statistics of the batch being processed,
+ * so the slices of a batch are coupled); the last layer is unchanged.  Every
+ * network call (mrx_cnn_forward/backward, mrx_modl_forward(_from)/backward,
+ * the soft-SENSE MoDL calls) then normalises each application of the
+ * denoiser with its own batch's statistics, and the reverse calls also
+ * write (or, with accumulate, add) g_gamma and g_beta.
+ * gamma, beta: device float[4][64]; g_gamma, g_beta: device float[4][64] or
+ * NULL (not computed).  Kept as pointers (plan state, like the biases): they
+ * must stay valid; in-place updates are seen by the next call.  The
+ * statistics are reduced in a fixed order (deterministic).  Returns
+ * MRX_EINVAL on a plan without MRX_PLAN_BATCHNORM; network calls on such a
+ * plan before this call return MRX_EINVAL.
+ */
+mrx_status mrx_cnn_set_bn(mrx_plan plan, const float* gamma, const float* beta, float* g_gamma, float* g_beta);
 /* z = x + N(x) (image-sized complex, must not alias). */
 mrx_status mrx_cnn_forward(mrx_plan plan, const float* x, float* z, void* stream);
 /*

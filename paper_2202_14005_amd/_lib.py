@@ -59,6 +59,7 @@ SIGNATURES = {
     "mrx_cnn_backward": (c_int32, [P, P, P, P, P, c_int32, P]),
     "mrx_modl_forward": (c_int32, [P, P, P, P, P, c_int32, c_int32, P, P, P]),
     "mrx_modl_forward_from": (c_int32, [P, P, P, P, P, P, c_int32, c_int32, P, P, P]),
+    "mrx_cnn_set_bn": (c_int32, [P, P, P, P, P]),
     "mrx_nufft_fwd": (c_int32, [P, P, c_int32, P, P, P, P, P]),
     "mrx_nufft_adj": (c_int32, [P, P, c_int32, P, P, P, P]),
     "mrx_toeplitz_psf": (c_int32, [P, P, c_int32, P, P]),

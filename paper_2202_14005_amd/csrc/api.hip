@@ -127,8 +127,10 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   *out = nullptr;
   if (B <= 0 || B > (1 << 20)) return fail(MRX_EINVAL, "plan_create: batch size must be in [1, 2^20]");
   if (!H || !W || !C) return fail(MRX_EINVAL, "plan_create: null shape array");
-  if (flags & ~(MRX_PLAN_NETWORK | MRX_PLAN_VN | MRX_PLAN_SOFT_SENSE | MRX_PLAN_TOEPLITZ))
+  if (flags & ~(MRX_PLAN_NETWORK | MRX_PLAN_VN | MRX_PLAN_SOFT_SENSE | MRX_PLAN_TOEPLITZ | MRX_PLAN_BATCHNORM))
     return fail(MRX_EINVAL, "plan_create: unknown flags");
+  if ((flags & MRX_PLAN_BATCHNORM) && !(flags & MRX_PLAN_NETWORK))
+    return fail(MRX_EINVAL, "plan_create: MRX_PLAN_BATCHNORM needs MRX_PLAN_NETWORK");
   if ((flags & MRX_PLAN_SOFT_SENSE) && (flags & MRX_PLAN_VN))
     return fail(MRX_EINVAL, "plan_create: soft-SENSE plans have no VarNet workspace");
   if ((flags & MRX_PLAN_TOEPLITZ) && (flags & (MRX_PLAN_VN | MRX_PLAN_SOFT_SENSE)))

@@ -67,6 +67,13 @@ struct mrx_plan_s {
   size_t ws_pk = 0, ws_wpart = 0, ws_bpart = 0, ws_loss = 0;
   size_t ws_s1[3] = {0, 0, 0};  // soft-SENSE: first-set images in the SENSE layout (denoiser in/out)
   const float* net_b[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // batch normalisation of the hidden layers (MRX_PLAN_BATCHNORM): gamma,
+  // beta [4][64] and their gradients (device, caller owned), workspace
+  size_t ws_bnpre[4] = {0, 0, 0, 0}, ws_bnstats = 0, ws_bnpart = 0, ws_bnsgz = 0, ws_bnslots = 0;
+  const float* bn_gamma = nullptr;
+  const float* bn_beta = nullptr;
+  float* bn_ggamma = nullptr;
+  float* bn_gbeta = nullptr;
   // VarNet workspace
   size_t ws_vn_kt = 0, ws_vn_u = 0, ws_vn_e = 0, ws_vn_kg = 0, ws_vn_s = 0, ws_vn_qx = 0, ws_vn_qg = 0;
   size_t ws_vn_plam = 0, ws_vn_pk = 0, ws_vn_pw = 0;

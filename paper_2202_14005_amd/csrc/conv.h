@@ -27,6 +27,9 @@ struct PackedNet {
 enum ConvMode : int {
   CONV_FWD = 0,     // bias + ReLU (first, mid); bias + residual (last)
   CONV_DGRAD = 1,   // no bias; output multiplied by ReLU'(act) ; last: add residual grad
+  // first, mid with batch normalisation (no bias, no ReLU):
+  CONV_STATS = 2,   // no output; per-workgroup fp32 sums of y and y^2 per channel into stat_part
+  CONV_NORM = 3,    // output (y - mean) * istd per channel (bn_stats), the normalised value
 };
 
 struct ConvArgs {
@@ -53,6 +56,11 @@ struct ConvArgs {
   // outside their slice) -- the bias gradient of the layer whose ReLU masks
   // the output, before rounding to bf16.  Null: not computed.
   float* bias_part;
+  // CONV_STATS: [slot][128] (64 sums of y, then 64 sums of y^2 over the
+  // workgroup's pixels inside the image), slot as for bias_part
+  float* stat_part;
+  // CONV_NORM: per-channel mean [64] then 1 / sqrt(var + eps) [64]
+  const float* bn_stats;
 };
 
 }  // namespace mrx

@@ -69,9 +69,9 @@ struct WaveFence {
 };
 
 template <class PixFn>
-__device__ __forceinline__ void epi_block64(const f32x16& a0, const f32x16& a1, const float* sbias, int mode,
-                                            uint2* stg, int lane, PixFn pix, uint16_t* out,
-                                            const uint16_t* rref) {
+__device__ __forceinline__ void epi_block64(const f32x16& a0, const f32x16& a1, const float* sbias,
+                                            const float* sscl, int mode, uint2* stg, int lane, PixFn pix,
+                                            uint16_t* out, const uint16_t* rref) {
   const int n = lane & 31, hsel = lane >> 5, kx = (n >> 1) & 15;
 #pragma unroll
   for (int m = 0; m < 2; ++m)
@@ -85,6 +85,8 @@ __device__ __forceinline__ void epi_block64(const f32x16& a0, const f32x16& a1, 
         if (mode == CONV_FWD) {
           v += sbias[co0 + j];
           v = v > 0.f ? v : 0.f;
+        } else if (mode == CONV_NORM) {
+          v = (v + sbias[co0 + j]) * sscl[co0 + j];
         }
         hv[j] = v;
       }
@@ -200,6 +202,70 @@ __device__ __forceinline__ float* bias_slot(const ConvArgs& a) {
   return a.bias_part + ((int64_t)blockIdx.x + (int64_t)a.tiles_x * (blockIdx.y + (int64_t)a.tiles_y * blockIdx.z)) * CNN_F;
 }
 
+// Statistics epilogue of a convolution feeding a batch normalisation: the
+// block is staged as fp32 as in epi_block64_bsum and read back as whole
+// pixels; bs[e] and bs2[e] accumulate, per lane, y and y^2 of channel
+// (lane & 7) * 8 + e over the lane's pixels inside the image.  Nothing is
+// stored.
+template <class PixFn>
+__device__ __forceinline__ void epi_block64_stats(const f32x16& a0, const f32x16& a1, float4* stgf, int lane,
+                                                  PixFn pix, float (&bs)[8], float (&bs2)[8]) {
+  const int n = lane & 31, hsel = lane >> 5;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int q = m * 8 + 2 * g + hsel;
+      const f32x16& a = m ? a1 : a0;
+      stgf[n * 16 + (q ^ (n & 15))] = make_float4(a[4 * g], a[4 * g + 1], a[4 * g + 2], a[4 * g + 3]);
+    }
+  const int c = lane & 7;
+  WaveFence::sync();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int pi = r * 8 + (lane >> 3), k = pi & 15;
+    if (pix(pi) < 0) continue;
+    const float4 f0 = stgf[pi * 16 + ((2 * c) ^ k)], f1 = stgf[pi * 16 + ((2 * c + 1) ^ k)];
+    const float fv[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      bs[e] += fv[e];
+      bs2[e] += fv[e] * fv[e];
+    }
+  }
+  WaveFence::sync();  // stgf is free for the next block
+}
+
+// The workgroup's statistics slot (128 floats: sums of y, then of y^2) from
+// the lanes' sums, in the fixed order of bias_partial_store; wsum: 512 floats.
+__device__ __forceinline__ void stats_partial_store(float (&bs)[8], float (&bs2)[8], float* wsum, float* slot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 8; o <= 32; o <<= 1)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      bs[e] += __shfl_xor(bs[e], o, 64);
+      bs2[e] += __shfl_xor(bs2[e], o, 64);
+    }
+  if (lane < 8) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      wsum[wv * 128 + lane * 8 + e] = bs[e];
+      wsum[wv * 128 + 64 + lane * 8 + e] = bs2[e];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 128)
+    slot[threadIdx.x] = ((wsum[threadIdx.x] + wsum[128 + threadIdx.x]) + wsum[256 + threadIdx.x]) + wsum[384 + threadIdx.x];
+}
+
+__device__ __forceinline__ float* stat_slot(const ConvArgs& a) {
+  return a.stat_part + ((int64_t)blockIdx.x + (int64_t)a.tiles_x * (blockIdx.y + (int64_t)a.tiles_y * blockIdx.z)) * 2 * CNN_F;
+}
+
+// epilogue kinds of the first and middle layers
+constexpr int EPI_PLAIN = 0, EPI_BSUM = 1, EPI_STATS = 2;
+
 // ------------------------------------------------------------- 64 -> 64
 // 16 x 16-pixel tiles (41.5 KB of LDS) so that three workgroups fit on a CU;
 // each wave computes 4 rows x 16 columns x 64 output channels as 2 pixel
@@ -209,6 +275,21 @@ __device__ __forceinline__ float* bias_slot(const ConvArgs& a) {
 // the weight fragments of the next tap are fetched from L2 while the
 // current tap runs, in two register sets used in turn (a rolled loop with
 // one set made the compiler wait for the loads at the back edge).
+// The epilogue's per-channel terms in LDS: the bias (forward), or minus the
+// mean and the inverse standard deviation (CONV_NORM).
+__device__ __forceinline__ void stage_bias(const ConvArgs& a, float* sbias, float* sscl) {
+  if (threadIdx.x < CNN_F) {
+    const int c = threadIdx.x;
+    if (a.mode == CONV_NORM) {
+      sbias[c] = -a.bn_stats[c];
+      sscl[c] = a.bn_stats[CNN_F + c];
+    } else {
+      sbias[c] = (a.mode == CONV_FWD && a.bias) ? a.bias[c] : 0.f;
+      sscl[c] = 1.f;
+    }
+  }
+}
+
 constexpr int TW16 = CONV_TW;
 constexpr int TILE16_PX = (CONV_TH + 2) * (TW16 + 2);
 constexpr int TILE1_PX = TILE16_PX;  // first layer: complex pixels (bf16 re, im in one word)
@@ -239,8 +320,8 @@ __device__ __forceinline__ void load_tile64_16(uint4* tile, const uint16_t* in, 
 // The 64 -> 64 layer on a staged input tile (all of its 18 x 18 pixels and
 // 64 channels in LDS, swizzled): MFMA loop and epilogue.  wa holds the
 // first tap's weight fragments on entry.
-template <bool BSUM>
-__device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, const ConvArgs& a,
+template <int EPI>
+__device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, const float* sscl, const ConvArgs& a,
                                               const SliceDesc& d, int ty0, int tx0, uint4 (&wa)[4][2]) {
   const int H = d.H, W = d.W;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -294,6 +375,9 @@ __device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, c
   uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
   const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
   float bs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float bs2[EPI == EPI_STATS ? 8 : 1];
+#pragma unroll
+  for (int e = 0; e < (EPI == EPI_STATS ? 8 : 1); ++e) bs2[e] = 0.f;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int gy0 = ty0 + wv * 4 + nb * 2;
@@ -301,27 +385,32 @@ __device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, c
       const int gy = gy0 + (i >> 4), gx = tx0 + (i & 15);
       return (gy < H && gx < W) ? ((int64_t)gy * W + gx) * CNN_F : -1;
     };
-    if constexpr (BSUM)
+    if constexpr (EPI == EPI_BSUM)
       epi_block64_bsum(acc[0][nb], acc[1][nb], (float4*)tile + wv * 512, lane, pix, out, rref, bs);
+    else if constexpr (EPI == EPI_STATS)
+      epi_block64_stats(acc[0][nb], acc[1][nb], (float4*)tile + wv * 512, lane, pix, bs, bs2);
     else
-      epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, (uint2*)tile + wv * 512, lane, pix, out, rref);
+      epi_block64(acc[0][nb], acc[1][nb], sbias, sscl, a.mode, (uint2*)tile + wv * 512, lane, pix, out, rref);
   }
   // 4 waves x 8 KB of fp32 staging end at 32 KB of the 41.5 KB tile
-  if constexpr (BSUM) bias_partial_store(bs, (float*)((float4*)tile + 4 * 512), bias_slot(a));
+  if constexpr (EPI == EPI_BSUM) bias_partial_store(bs, (float*)((float4*)tile + 4 * 512), bias_slot(a));
+  if constexpr (EPI == EPI_STATS) stats_partial_store(bs, bs2, (float*)((float4*)tile + 4 * 512), stat_slot(a));
 }
 
-template <bool BSUM>
+template <int EPI>
 __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
-  static_assert(4 * 512 * sizeof(float4) + 4 * CNN_F * sizeof(float) <= TILE16_PX * 8 * sizeof(uint4),
+  static_assert(4 * 512 * sizeof(float4) + 4 * 2 * CNN_F * sizeof(float) <= TILE16_PX * 8 * sizeof(uint4),
                 "fp32 staging and wave sums must fit in the tile");
   __shared__ uint4 tile[TILE16_PX * 8];
   __shared__ float sbias[CNN_F];
+  __shared__ float sscl[CNN_F];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
   const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
   if (tx0 >= W || ty0 >= H) {
-    if (BSUM && threadIdx.x < CNN_F) bias_slot(a)[threadIdx.x] = 0.f;
+    if (EPI == EPI_BSUM && threadIdx.x < CNN_F) bias_slot(a)[threadIdx.x] = 0.f;
+    if (EPI == EPI_STATS && threadIdx.x < 2 * CNN_F) stat_slot(a)[threadIdx.x] = 0.f;
     return;
   }
   const int lane = threadIdx.x & 63;
@@ -332,10 +421,10 @@ __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
     wa[kc][0] = ldg16(wp + (kc * 2 + 0) * 512);
     wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
   }
-  if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
+  stage_bias(a, sbias, sscl);
   load_tile64_16(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
   __syncthreads();
-  mid16_compute<BSUM>(tile, sbias, a, d, ty0, tx0, wa);
+  mid16_compute<EPI>(tile, sbias, sscl, a, d, ty0, tx0, wa);
 }
 
 // ------------------------------------------- 2 -> 64 -> 64, fused (forward)
@@ -459,26 +548,28 @@ __global__ void __launch_bounds__(256, 3) k_conv_first_mid(ConvArgs a) {
     wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
   }
   __syncthreads();
-  mid16_compute<false>(tile, sbias, a, d, ty0, tx0, wa);
+  mid16_compute<EPI_PLAIN>(tile, sbias, nullptr, a, d, ty0, tx0, wa);
 }
 
 // ---------------------------------------------------------------- 2 -> 64
 // Input: complex image (fp32 pairs), rounded to bf16.  K = 9 taps x 2 channels
 // = 18, padded to 32 (two 16-deep MFMA steps).  16 x 16-pixel tiles; each
 // wave computes 4 rows x 16 columns x 64 channels (2 pixel blocks).
-template <bool BSUM>
+template <int EPI>
 __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
   __shared__ uint32_t tile[TILE1_PX];
   __shared__ float sbias[CNN_F];
+  __shared__ float sscl[CNN_F];
   // epilogue staging: 4 KB per wave (bf16), or 8 KB per wave (fp32) and the
-  // waves' bias sums when BSUM
-  __shared__ uint4 stage[BSUM ? 4 * 512 + CNN_F : 4 * 256];
+  // waves' channel sums (64 floats each for bias sums, 128 for statistics)
+  __shared__ uint4 stage[EPI == EPI_STATS ? 4 * 512 + 2 * CNN_F : EPI == EPI_BSUM ? 4 * 512 + CNN_F : 4 * 256];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
   const int tx0 = blockIdx.x * TW16, ty0 = blockIdx.y * CONV_TH;
   if (tx0 >= W || ty0 >= H) {
-    if (BSUM && threadIdx.x < CNN_F) bias_slot(a)[threadIdx.x] = 0.f;
+    if (EPI == EPI_BSUM && threadIdx.x < CNN_F) bias_slot(a)[threadIdx.x] = 0.f;
+    if (EPI == EPI_STATS && threadIdx.x < 2 * CNN_F) stat_slot(a)[threadIdx.x] = 0.f;
     return;
   }
   const float2* in = a.in_c + d.xoff;
@@ -490,7 +581,7 @@ __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
     wf[k][0] = ldg16(wp + (k * 2 + 0) * 512);
     wf[k][1] = ldg16(wp + (k * 2 + 1) * 512);
   }
-  if (threadIdx.x < CNN_F) sbias[threadIdx.x] = (a.mode == CONV_FWD && a.bias) ? a.bias[threadIdx.x] : 0.f;
+  stage_bias(a, sbias, sscl);
   {
     constexpr int PT = (TILE1_PX + 255) / 256;
     float2 v[PT];
@@ -546,6 +637,9 @@ __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
   uint16_t* out = a.out_bf16 + d.xoff * CNN_F;
   const uint16_t* rref = a.relu_ref ? a.relu_ref + d.xoff * CNN_F : nullptr;
   float bs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float bs2[EPI == EPI_STATS ? 8 : 1];
+#pragma unroll
+  for (int e = 0; e < (EPI == EPI_STATS ? 8 : 1); ++e) bs2[e] = 0.f;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int gy0 = ty0 + wv * 4 + nb * 2;
@@ -553,12 +647,15 @@ __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
       const int gy = gy0 + (i >> 4), gx = tx0 + (i & 15);
       return (gy < H && gx < W) ? ((int64_t)gy * W + gx) * CNN_F : -1;
     };
-    if constexpr (BSUM)
+    if constexpr (EPI == EPI_BSUM)
       epi_block64_bsum(acc[0][nb], acc[1][nb], (float4*)stage + wv * 512, lane, pix, out, rref, bs);
+    else if constexpr (EPI == EPI_STATS)
+      epi_block64_stats(acc[0][nb], acc[1][nb], (float4*)stage + wv * 512, lane, pix, bs, bs2);
     else
-      epi_block64(acc[0][nb], acc[1][nb], sbias, a.mode, (uint2*)stage + wv * 512, lane, pix, out, rref);
+      epi_block64(acc[0][nb], acc[1][nb], sbias, sscl, a.mode, (uint2*)stage + wv * 512, lane, pix, out, rref);
   }
-  if constexpr (BSUM) bias_partial_store(bs, (float*)((float4*)stage + 4 * 512), bias_slot(a));
+  if constexpr (EPI == EPI_BSUM) bias_partial_store(bs, (float*)((float4*)stage + 4 * 512), bias_slot(a));
+  if constexpr (EPI == EPI_STATS) stats_partial_store(bs, bs2, (float*)((float4*)stage + 4 * 512), stat_slot(a));
 }
 
 // ---------------------------------------------------------------- 64 -> 2
@@ -676,13 +773,17 @@ __global__ void k_pack_last(const float* Wm, uint16_t* out, int transpose) {
 
 hipError_t conv_launch(int kind, const ConvArgs& a, hipStream_t s) {
   dim3 g16(a.tiles_x, a.tiles_y, a.nslices);
-  const bool bsum = a.mode == CONV_DGRAD && a.bias_part;
+  const int epi = (a.mode == CONV_DGRAD && a.bias_part) ? EPI_BSUM : a.mode == CONV_STATS ? EPI_STATS : EPI_PLAIN;
+  if (a.mode == CONV_STATS && !a.stat_part) return hipErrorInvalidValue;
+  if (a.mode == CONV_NORM && !a.bn_stats) return hipErrorInvalidValue;
   if (kind == 0) {
-    if (bsum) hipLaunchKernelGGL(k_conv_first<true>, g16, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_conv_first<false>, g16, dim3(256), 0, s, a);
+    if (epi == EPI_BSUM) hipLaunchKernelGGL(k_conv_first<EPI_BSUM>, g16, dim3(256), 0, s, a);
+    else if (epi == EPI_STATS) hipLaunchKernelGGL(k_conv_first<EPI_STATS>, g16, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_conv_first<EPI_PLAIN>, g16, dim3(256), 0, s, a);
   } else if (kind == 1) {
-    if (bsum) hipLaunchKernelGGL(k_conv_mid16<true>, g16, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_conv_mid16<false>, g16, dim3(256), 0, s, a);
+    if (epi == EPI_BSUM) hipLaunchKernelGGL(k_conv_mid16<EPI_BSUM>, g16, dim3(256), 0, s, a);
+    else if (epi == EPI_STATS) hipLaunchKernelGGL(k_conv_mid16<EPI_STATS>, g16, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_conv_mid16<EPI_PLAIN>, g16, dim3(256), 0, s, a);
   }
   else if (kind == 2) hipLaunchKernelGGL(k_conv_last, g16, dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_conv_first_mid, g16, dim3(256), 0, s, a);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include "../../include/mrx.h"
 #include "api_internal.h"
+#include "bn.h"
 #include "conv.h"
 #include "wgrad.h"
 
@@ -46,6 +47,16 @@ size_t net_workspace_bytes(mrx_plan_s* p) {
   p->ws_bpart = take((size_t)((p->maxW + CONV_TW - 1) / CONV_TW) * ((p->maxH + CONV_TH - 1) / CONV_TH) * p->B *
                      CNN_F * 4);
   p->ws_loss = take((size_t)p->B * p->nrr * 4);
+  if (p->flags & MRX_PLAN_BATCHNORM) {
+    // the hidden layers' normalised outputs, their statistics, the reverse
+    // pass's partial and channel sums, the convolutions' statistics slots
+    for (int i = 0; i < 4; ++i) p->ws_bnpre[i] = take(ni * CNN_F * 2);
+    p->ws_bnstats = take((size_t)4 * BN_STATS * 4);
+    p->ws_bnpart = take((size_t)BN_BLOCKS * CNN_F * 4);
+    p->ws_bnslots = take((size_t)((p->maxW + CONV_TW - 1) / CONV_TW) * ((p->maxH + CONV_TH - 1) / CONV_TH) * p->B *
+                         2 * CNN_F * 4);
+    p->ws_bnsgz = take((size_t)CNN_F * 4);
+  }
   return w;
 }
 
@@ -81,13 +92,64 @@ static mrx_status net_ready(mrx_plan_s* p, const char* who) {
   if (!(p->flags & MRX_PLAN_NETWORK))
     return fail(MRX_ENOWORKSPACE, std::string(who) + ": plan was created without MRX_PLAN_NETWORK");
   if (!p->net_ready) return fail(MRX_EINVAL, std::string(who) + ": call mrx_cnn_set_weights first");
+  if ((p->flags & MRX_PLAN_BATCHNORM) && !p->bn_gamma)
+    return fail(MRX_EINVAL, std::string(who) + ": call mrx_cnn_set_bn first (batch-normalisation plan)");
   return MRX_OK;
 }
 
-// z = x + N(x); activations of layers 1-4 stay in the workspace, or, with
-// fuse12 (inference), those of layers 2-4 only: the first two layers then
-// run as one kernel and the first layer's activation is never stored.
+static float* bn_stats(mrx_plan_s* p, int layer) { return (float*)(p->ws + p->ws_bnstats) + layer * BN_STATS; }
+
+// Forward with batch normalisation after each hidden layer (statistics of
+// the batch; the first two layers are not fused, as the second needs the
+// first's statistics).  Each hidden convolution runs twice: summing y and
+// y^2 per channel, then writing the normalised yhat (kept for the reverse
+// pass), from which a = ReLU(gamma yhat + beta).  No hidden bias.
+static mrx_status cnn_fwd_bn(mrx_plan_s* p, const float2* x, float2* z, hipStream_t s) {
+  uint16_t* act[4];
+  uint16_t* pre[4];
+  for (int i = 0; i < 4; ++i) {
+    act[i] = (uint16_t*)(p->ws + p->ws_act[i]);
+    pre[i] = (uint16_t*)(p->ws + p->ws_bnpre[i]);
+  }
+  float* slots = (float*)(p->ws + p->ws_bnslots);
+  const int nslots = ((p->maxW + CONV_TW - 1) / CONV_TW) * ((p->maxH + CONV_TH - 1) / CONV_TH) * p->B;
+  hipError_t e = hipSuccess;
+  for (int l = 0; l <= 3 && e == hipSuccess; ++l) {
+    const int kind = l == 0 ? 0 : 1;
+    ConvArgs m = conv_args(p);
+    if (l == 0) m.in_c = x;
+    else m.in_bf16 = act[l - 1];
+    m.wpk = pk_ptr(p, 0, l);
+    m.mode = CONV_STATS;
+    m.stat_part = slots;
+    e = conv_launch(kind, m, s);
+    if (e == hipSuccess) e = bn_finish_stats(slots, nslots, p->n_image, bn_stats(p, l), s);
+    if (e == hipSuccess) {
+      m.mode = CONV_NORM;
+      m.bn_stats = bn_stats(p, l);
+      m.out_bf16 = pre[l];
+      KernelTimer kt(p, kind == 1 ? MRX_KERNEL_CONV_MID : -1, s);
+      e = conv_launch(kind, m, s);
+    }
+    if (e == hipSuccess)
+      e = bn_apply_forward(pre[l], act[l], p->n_image, p->bn_gamma + l * CNN_F, p->bn_beta + l * CNN_F,
+                           bn_stats(p, l), s);
+  }
+  if (e == hipSuccess) {
+    ConvArgs f = conv_args(p);
+    f.mode = CONV_FWD;
+    f.in_bf16 = act[3];
+    f.out_c = z;
+    f.resid = x;
+    f.wpk = pk_ptr(p, 0, 4);
+    f.bias = p->net_b[4];
+    e = conv_launch(2, f, s);
+  }
+  return e == hipSuccess ? MRX_OK : hip_fail(e, "cnn_forward (batch normalisation)");
+}
+
 static mrx_status cnn_fwd(mrx_plan_s* p, const float2* x, float2* z, hipStream_t s, bool fuse12 = false) {
+  if (p->flags & MRX_PLAN_BATCHNORM) return cnn_fwd_bn(p, x, z, s);
   uint16_t* act[4];
   for (int i = 0; i < 4; ++i) act[i] = (uint16_t*)(p->ws + p->ws_act[i]);
   ConvArgs a = conv_args(p);
@@ -159,6 +221,27 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
   };
   float* bpart = (float*)(p->ws + p->ws_bpart);
   const int nbslots = ((p->maxW + CONV_TW - 1) / CONV_TW) * ((p->maxH + CONV_TH - 1) / CONV_TH) * p->B;
+  // The fp32 channel sums of the gradient after hidden layer l's ReLU
+  // derivative (gbuf holds that gradient, bf16): the bias gradient of layer
+  // l, or, with batch normalisation, g_beta, after which gbuf is turned into
+  // the gradient before the normalisation (the hidden layers then have no
+  // bias: their bias gradient is zero).
+  const bool bn = (p->flags & MRX_PLAN_BATCHNORM) != 0;
+  auto hidden = [&](int l, uint16_t* gbuf) -> hipError_t {
+    if (!bn) return bias_reduce(bpart, nbslots, g->b[l], accumulate, s);
+    float* sgz = (float*)(p->ws + p->ws_bnsgz);
+    hipError_t r = bias_reduce(bpart, nbslots, sgz, 0, s);
+    if (r != hipSuccess) return r;
+    return bn_backward((const uint16_t*)(p->ws + p->ws_bnpre[l]), gbuf, p->n_image, p->bn_gamma + l * CNN_F,
+                       bn_stats(p, l), sgz, (float*)(p->ws + p->ws_bnpart),
+                       p->bn_ggamma ? p->bn_ggamma + l * CNN_F : nullptr,
+                       p->bn_gbeta ? p->bn_gbeta + l * CNN_F : nullptr, accumulate, s);
+  };
+  if (bn && !accumulate)
+    for (int l = 0; l < 4; ++l) {
+      e = fill_u32((uint32_t*)g->b[l], 0u, CNN_F, s);
+      if (e != hipSuccess) return hip_fail(e, "cnn_backward: clear");
+    }
   // layer 5 (64 -> 2); its input gradient masked by layer 4's ReLU is layer
   // 4's pre-activation gradient, whose fp32 sums give layer 4's bias gradient
   e = wg(2, nullptr, act[3], gz, 4);
@@ -172,7 +255,7 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
     a.bias_part = bpart;
     e = conv_launch(0, a, s);
   }
-  if (e == hipSuccess) e = bias_reduce(bpart, nbslots, g->b[3], accumulate, s);
+  if (e == hipSuccess) e = hidden(3, gb[0]);
   // layers 4, 3, 2 (64 -> 64)
   int cur = 0;
   for (int l = 3; l >= 1 && e == hipSuccess; --l) {
@@ -189,7 +272,7 @@ static mrx_status cnn_bwd(mrx_plan_s* p, const float2* x, const float2* gz, floa
       KernelTimer kt(p, MRX_KERNEL_CONV_MID, s);
       e = conv_launch(1, m, s);
     }
-    if (e == hipSuccess) e = bias_reduce(bpart, nbslots, g->b[l - 1], accumulate, s);
+    if (e == hipSuccess) e = hidden(l - 1, gb[1 - cur]);
     cur = 1 - cur;
   }
   // layer 1 (2 -> 64) and the residual
@@ -294,6 +377,18 @@ mrx_status mrx_cnn_set_weights(mrx_plan p, const mrx_cnn_params* w, void* stream
     if (e != hipSuccess) return hip_fail(e, "cnn_set_weights: pack");
   }
   p->net_ready = true;
+  return MRX_OK;
+}
+
+mrx_status mrx_cnn_set_bn(mrx_plan p, const float* gamma, const float* beta, float* g_gamma, float* g_beta) {
+  if (!p) return fail(MRX_EINVAL, "cnn_set_bn: null plan");
+  if (!(p->flags & MRX_PLAN_BATCHNORM))
+    return fail(MRX_EINVAL, "cnn_set_bn: plan was created without MRX_PLAN_BATCHNORM");
+  if (!gamma || !beta) return fail(MRX_EINVAL, "cnn_set_bn: null gamma or beta");
+  p->bn_gamma = gamma;
+  p->bn_beta = beta;
+  p->bn_ggamma = g_gamma;
+  p->bn_gbeta = g_beta;
   return MRX_OK;
 }
 

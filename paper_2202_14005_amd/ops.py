@@ -33,7 +33,7 @@ class Plan:
     sequences (uneven batch)."""
 
     def __init__(self, H, W, C, B: int | None = None, device=None, network: bool = False, vn: bool = False,
-                 soft: bool = False, toeplitz: bool = False):
+                 soft: bool = False, toeplitz: bool = False, batchnorm: bool = False):
         L = lib()
         if isinstance(H, int):
             if B is None:
@@ -51,12 +51,15 @@ class Plan:
         arr = lambda v: (ctypes.c_int32 * len(v))(*v)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            flags = (1 if network else 0) | (2 if vn else 0) | (4 if soft else 0) | (8 if toeplitz else 0)
+            flags = ((1 if network else 0) | (2 if vn else 0) | (4 if soft else 0) | (8 if toeplitz else 0)
+                     | (16 if batchnorm else 0))
             check(L.mrx_plan_create(ctypes.byref(h), self.B, arr(Hs), arr(Ws), arr(Cs), flags), "plan_create")
         self.network = network
         self.vn = vn
         self.soft = soft
         self.toeplitz = toeplitz
+        self.batchnorm = batchnorm
+        self._bn = None
         self._weights_key = None
         self._h = h
         ni, nc, nm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -291,6 +294,15 @@ class Plan:
 
 
     # ------------------------------------------------------------- network
+    def set_bn(self, bn: "BatchNorm"):
+        """Batch normalisation parameters for every later network call (plan
+        created with batchnorm=True); the tensors are kept referenced."""
+        if not self.batchnorm:
+            raise ValueError("set_bn needs a plan created with batchnorm=True")
+        check(lib().mrx_cnn_set_bn(self._h, _ptr(bn.gamma), _ptr(bn.beta), _ptr(bn.g_gamma), _ptr(bn.g_beta)),
+              "cnn_set_bn")
+        self._bn = bn
+
     def set_weights(self, cnn: "CNN", force=False):
         """Pack the denoiser weights (bf16 MFMA fragments) into the workspace;
         skipped when the same weights (same tensors and version) are packed."""
@@ -512,6 +524,7 @@ class CNN:
         self.w = [w.contiguous() for w in weights]
         self.b = [b.contiguous() for b in biases]
         self.version = 0
+        self.bn = None  # BatchNorm parameters trained with these weights, if any
         for l, (w, b) in enumerate(zip(self.w, self.b)):
             co, ci = self.CHANNELS[l + 1], self.CHANNELS[l]
             if tuple(w.shape) != (co, ci, 3, 3) or tuple(b.shape) != (co,):
@@ -587,19 +600,43 @@ class CNNGrads:
         return out
 
 
-class Adam:
-    """Adam state over a CNN's parameters, stepped by the library kernel."""
+class BatchNorm:
+    """gamma and beta of the denoiser's batch normalisation (device float32
+    [4, 64], one row per hidden layer) and their gradient buffers; set on a
+    plan created with batchnorm=True by ``Plan.set_bn``."""
 
-    def __init__(self, cnn: CNN, lr=1e-4, b1=0.9, b2=0.999, eps=1e-8):
-        self.cnn, self.lr, self.b1, self.b2, self.eps = cnn, lr, b1, b2, eps
-        self.m = [torch.zeros_like(p) for p in cnn.params()]
-        self.v = [torch.zeros_like(p) for p in cnn.params()]
+    def __init__(self, device=None, gamma=None, beta=None):
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        f = lambda a, v: (torch.as_tensor(a, dtype=torch.float32).to(dev).reshape(4, 64).contiguous()
+                          if a is not None else torch.full((4, 64), v, dtype=torch.float32, device=dev))
+        self.gamma, self.beta = f(gamma, 1.0), f(beta, 0.0)
+        self.g_gamma = torch.zeros_like(self.gamma)
+        self.g_beta = torch.zeros_like(self.beta)
+
+    def params(self):
+        return [self.gamma, self.beta]
+
+    def grads(self):
+        return [self.g_gamma, self.g_beta]
+
+
+class Adam:
+    """Adam state over a CNN's parameters (and, with ``bn``, the batch
+    normalisation's gamma and beta), stepped by the library kernel."""
+
+    def __init__(self, cnn: CNN, lr=1e-4, b1=0.9, b2=0.999, eps=1e-8, bn: "BatchNorm | None" = None):
+        self.cnn, self.lr, self.b1, self.b2, self.eps, self.bn = cnn, lr, b1, b2, eps, bn
+        ps = cnn.params() + (bn.params() if bn is not None else [])
+        self.m = [torch.zeros_like(p) for p in ps]
+        self.v = [torch.zeros_like(p) for p in ps]
         self.t = 0
 
     def step(self, grads: CNNGrads):
         self.t += 1
         stream = _stream(self.cnn.w[0].device)
-        for p, g, m, v in zip(self.cnn.params(), grads.params(), self.m, self.v):
+        ps = self.cnn.params() + (self.bn.params() if self.bn is not None else [])
+        gs = grads.params() + (self.bn.grads() if self.bn is not None else [])
+        for p, g, m, v in zip(ps, gs, self.m, self.v):
             check(lib().mrx_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), self.lr, self.b1, self.b2,
                                       self.eps, self.t, stream), "adam_step")
         self.cnn.version += 1  # the packed bf16 copies are now stale
@@ -611,10 +648,12 @@ class MoDL:
     float32 tensor [1]): train_step sums its per-slice gradients, takes an
     Adam step on it with the weights' optimiser settings and keeps it >= 0."""
 
-    def __init__(self, plan: Plan, cnn: CNN, lam=0.05, T=5, n_cg=10, learn_lam=False):
+    def __init__(self, plan: Plan, cnn: CNN, lam=0.05, T=5, n_cg=10, learn_lam=False, bn: "BatchNorm | None" = None):
         if not plan.network:
             raise ValueError("MoDL needs a plan created with network=True")
         self.plan, self.cnn, self.T, self.n_cg = plan, cnn, T, n_cg
+        if bn is not None:
+            plan.set_bn(bn)
         self.learn_lam = learn_lam
         if learn_lam:
             self.lam = torch.full((1,), float(lam), dtype=torch.float32, device=plan.device)

@@ -74,26 +74,29 @@ def nrmse(x, ref):
 
 def train(H=320, W=320, C=15, B=4, T=5, n_cg=10, lam=0.05, lr=1e-4, steps=500, n_train=2000,
           train_base=100000, seed=7, last_scale=0.1, log_every=25, device=None, verbose=True, tune=True,
-          learn_lam=False, phases=None):
+          learn_lam=False, phases=None, batchnorm=False):
     """Train a MoDL denoiser; returns (cnn, history), and with learn_lam the
-    trained lambda in the last history entry.  ``phases`` is a list of
+    trained lambda in the last history entry.  With batchnorm the denoiser's
+    hidden layers carry batch normalisation (the paper's MoDL), its gamma
+    and beta trained beside the weights and returned as ``cnn.bn``.  ``phases`` is a list of
     (unrolls, steps) trained one after the other from the same weights,
     each with a fresh Adam state -- the paper's two-step MoDL training is
     [(1, n1), (10, n2)]; by default one phase (T, steps).  With ``tune`` the
     normal operator's schedule is chosen by the autotuner on the first
     batch."""
     dev = torch.device(device) if device else torch.device("cuda", torch.cuda.current_device())
-    plan = ops.Plan(H, W, C, B=B, device=dev, network=True)
+    plan = ops.Plan(H, W, C, B=B, device=dev, network=True, batchnorm=batchnorm)
     src = PhantomSource(plan, H, W, C)
     cnn = ops.CNN.init(seed=seed, device=dev, last_scale=last_scale)
+    cnn.bn = ops.BatchNorm(device=dev) if batchnorm else None
     grads = ops.CNNGrads(cnn)
     hist = []
     t0 = time.perf_counter()
     it = 0
     lam_now = lam
     for ph, (T_ph, steps_ph) in enumerate(phases or [(T, steps)]):
-        opt = ops.Adam(cnn, lr=lr)
-        net = ops.MoDL(plan, cnn, lam=lam_now, T=T_ph, n_cg=n_cg, learn_lam=learn_lam)
+        opt = ops.Adam(cnn, lr=lr, bn=cnn.bn)
+        net = ops.MoDL(plan, cnn, lam=lam_now, T=T_ph, n_cg=n_cg, learn_lam=learn_lam, bn=cnn.bn)
         for k in range(steps_ph):
             seeds = [train_base + (it * B + j) % n_train for j in range(B)]
             y, S, m, x = src.batch(seeds)
@@ -120,9 +123,10 @@ def evaluate(cnn, H=320, W=320, C=15, B=4, T=5, n_cg=10, lam=0.05, eval_base=200
     """NRMSE of MoDL and of plain CG-SENSE (lambda / iteration sweep) on
     held-out phantoms, with per-setting throughput."""
     dev = torch.device(device) if device else torch.device("cuda", torch.cuda.current_device())
-    plan = ops.Plan(H, W, C, B=B, device=dev, network=True)
+    bn = getattr(cnn, "bn", None)
+    plan = ops.Plan(H, W, C, B=B, device=dev, network=True, batchnorm=bn is not None)
     src = PhantomSource(plan, H, W, C, coil_seed=91000)
-    net = ops.MoDL(plan, cnn, lam=lam, T=T, n_cg=n_cg)
+    net = ops.MoDL(plan, cnn, lam=lam, T=T, n_cg=n_cg, bn=bn)
     e_modl, e_cg = [], {}
     batches = [src.batch([eval_base + i * B + k for k in range(B)]) for i in range(n_eval // B)]
     for y, S, m, x in batches:
@@ -166,6 +170,8 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write the trained weights (.npz, arrays only)")
     ap.add_argument("--learn-lam", action="store_true", help="train the shared lambda with the weights")
+    ap.add_argument("--batchnorm", action="store_true",
+                    help="batch normalisation in the denoiser's hidden layers (batch statistics)")
     ap.add_argument("--two-step", default=None, metavar="N1,N2",
                     help="the paper's two-step training: N1 steps with one unroll, then N2 with --unrolls")
     a = ap.parse_args()
@@ -174,7 +180,7 @@ def main():
         n1, n2 = (int(v) for v in a.two_step.split(","))
         phases = [(1, n1), (a.unrolls, n2)]
     cnn, hist = train(H=a.size, W=a.size, C=a.coils, B=a.batch, T=a.unrolls, lr=a.lr, steps=a.steps,
-                      learn_lam=a.learn_lam, phases=phases)
+                      learn_lam=a.learn_lam, phases=phases, batchnorm=a.batchnorm)
     if a.save:
         cnn.save(a.save)
     lam = hist[-1]["lambda"] if a.learn_lam else 0.05
