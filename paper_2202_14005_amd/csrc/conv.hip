@@ -68,7 +68,7 @@ struct WaveFence {
   }
 };
 
-template <class PixFn>
+template <bool NORM, class PixFn>
 __device__ __forceinline__ void epi_block64(const f32x16& a0, const f32x16& a1, const float* sbias,
                                             const float* sscl, int mode, uint2* stg, int lane, PixFn pix,
                                             uint16_t* out, const uint16_t* rref) {
@@ -82,11 +82,11 @@ __device__ __forceinline__ void epi_block64(const f32x16& a0, const f32x16& a1, 
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float v = m ? a1[4 * g + j] : a0[4 * g + j];
-        if (mode == CONV_FWD) {
+        if constexpr (NORM) {
+          v = (v + sbias[co0 + j]) * sscl[co0 + j];
+        } else if (mode == CONV_FWD) {
           v += sbias[co0 + j];
           v = v > 0.f ? v : 0.f;
-        } else if (mode == CONV_NORM) {
-          v = (v + sbias[co0 + j]) * sscl[co0 + j];
         }
         hv[j] = v;
       }
@@ -263,8 +263,11 @@ __device__ __forceinline__ float* stat_slot(const ConvArgs& a) {
   return a.stat_part + ((int64_t)blockIdx.x + (int64_t)a.tiles_x * (blockIdx.y + (int64_t)a.tiles_y * blockIdx.z)) * 2 * CNN_F;
 }
 
-// epilogue kinds of the first and middle layers
-constexpr int EPI_PLAIN = 0, EPI_BSUM = 1, EPI_STATS = 2;
+// epilogue kinds of the first and middle layers: plain (forward bias +
+// ReLU, or input gradient), input gradient with bias sums, statistics, and
+// normalisation (each a compile-time variant, so that the plain forward
+// compiles to the same code as without batch normalisation)
+constexpr int EPI_PLAIN = 0, EPI_BSUM = 1, EPI_STATS = 2, EPI_NORM = 3;
 
 // ------------------------------------------------------------- 64 -> 64
 // 16 x 16-pixel tiles (41.5 KB of LDS) so that three workgroups fit on a CU;
@@ -275,17 +278,17 @@ constexpr int EPI_PLAIN = 0, EPI_BSUM = 1, EPI_STATS = 2;
 // the weight fragments of the next tap are fetched from L2 while the
 // current tap runs, in two register sets used in turn (a rolled loop with
 // one set made the compiler wait for the loads at the back edge).
-// The epilogue's per-channel terms in LDS: the bias (forward), or minus the
-// mean and the inverse standard deviation (CONV_NORM).
+// The epilogue's per-channel terms in LDS: the bias (forward), or, for the
+// normalising variant, minus the mean and the inverse standard deviation.
+template <bool NORM>
 __device__ __forceinline__ void stage_bias(const ConvArgs& a, float* sbias, float* sscl) {
   if (threadIdx.x < CNN_F) {
     const int c = threadIdx.x;
-    if (a.mode == CONV_NORM) {
+    if constexpr (NORM) {
       sbias[c] = -a.bn_stats[c];
       sscl[c] = a.bn_stats[CNN_F + c];
     } else {
       sbias[c] = (a.mode == CONV_FWD && a.bias) ? a.bias[c] : 0.f;
-      sscl[c] = 1.f;
     }
   }
 }
@@ -390,7 +393,8 @@ __device__ __forceinline__ void mid16_compute(uint4* tile, const float* sbias, c
     else if constexpr (EPI == EPI_STATS)
       epi_block64_stats(acc[0][nb], acc[1][nb], (float4*)tile + wv * 512, lane, pix, bs, bs2);
     else
-      epi_block64(acc[0][nb], acc[1][nb], sbias, sscl, a.mode, (uint2*)tile + wv * 512, lane, pix, out, rref);
+      epi_block64<EPI == EPI_NORM>(acc[0][nb], acc[1][nb], sbias, sscl, a.mode, (uint2*)tile + wv * 512, lane, pix,
+                                   out, rref);
   }
   // 4 waves x 8 KB of fp32 staging end at 32 KB of the 41.5 KB tile
   if constexpr (EPI == EPI_BSUM) bias_partial_store(bs, (float*)((float4*)tile + 4 * 512), bias_slot(a));
@@ -403,7 +407,7 @@ __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
                 "fp32 staging and wave sums must fit in the tile");
   __shared__ uint4 tile[TILE16_PX * 8];
   __shared__ float sbias[CNN_F];
-  __shared__ float sscl[CNN_F];
+  __shared__ float sscl[EPI == EPI_NORM ? CNN_F : 1];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
@@ -421,7 +425,7 @@ __global__ void __launch_bounds__(256, 3) k_conv_mid16(ConvArgs a) {
     wa[kc][0] = ldg16(wp + (kc * 2 + 0) * 512);
     wa[kc][1] = ldg16(wp + (kc * 2 + 1) * 512);
   }
-  stage_bias(a, sbias, sscl);
+  stage_bias<EPI == EPI_NORM>(a, sbias, sscl);
   load_tile64_16(tile, a.in_bf16 + d.xoff * CNN_F, H, W, ty0, tx0);
   __syncthreads();
   mid16_compute<EPI>(tile, sbias, sscl, a, d, ty0, tx0, wa);
@@ -559,7 +563,7 @@ template <int EPI>
 __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
   __shared__ uint32_t tile[TILE1_PX];
   __shared__ float sbias[CNN_F];
-  __shared__ float sscl[CNN_F];
+  __shared__ float sscl[EPI == EPI_NORM ? CNN_F : 1];
   // epilogue staging: 4 KB per wave (bf16), or 8 KB per wave (fp32) and the
   // waves' channel sums (64 floats each for bias sums, 128 for statistics)
   __shared__ uint4 stage[EPI == EPI_STATS ? 4 * 512 + 2 * CNN_F : EPI == EPI_BSUM ? 4 * 512 + CNN_F : 4 * 256];
@@ -581,7 +585,7 @@ __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
     wf[k][0] = ldg16(wp + (k * 2 + 0) * 512);
     wf[k][1] = ldg16(wp + (k * 2 + 1) * 512);
   }
-  stage_bias(a, sbias, sscl);
+  stage_bias<EPI == EPI_NORM>(a, sbias, sscl);
   {
     constexpr int PT = (TILE1_PX + 255) / 256;
     float2 v[PT];
@@ -652,7 +656,8 @@ __global__ void __launch_bounds__(256, 4) k_conv_first(ConvArgs a) {
     else if constexpr (EPI == EPI_STATS)
       epi_block64_stats(acc[0][nb], acc[1][nb], (float4*)stage + wv * 512, lane, pix, bs, bs2);
     else
-      epi_block64(acc[0][nb], acc[1][nb], sbias, sscl, a.mode, (uint2*)stage + wv * 512, lane, pix, out, rref);
+      epi_block64<EPI == EPI_NORM>(acc[0][nb], acc[1][nb], sbias, sscl, a.mode, (uint2*)stage + wv * 512, lane,
+                                   pix, out, rref);
   }
   if constexpr (EPI == EPI_BSUM) bias_partial_store(bs, (float*)((float4*)stage + 4 * 512), bias_slot(a));
   if constexpr (EPI == EPI_STATS) stats_partial_store(bs, bs2, (float*)((float4*)stage + 4 * 512), stat_slot(a));
@@ -773,16 +778,21 @@ __global__ void k_pack_last(const float* Wm, uint16_t* out, int transpose) {
 
 hipError_t conv_launch(int kind, const ConvArgs& a, hipStream_t s) {
   dim3 g16(a.tiles_x, a.tiles_y, a.nslices);
-  const int epi = (a.mode == CONV_DGRAD && a.bias_part) ? EPI_BSUM : a.mode == CONV_STATS ? EPI_STATS : EPI_PLAIN;
+  const int epi = (a.mode == CONV_DGRAD && a.bias_part) ? EPI_BSUM
+                  : a.mode == CONV_STATS                 ? EPI_STATS
+                  : a.mode == CONV_NORM                  ? EPI_NORM
+                                                         : EPI_PLAIN;
   if (a.mode == CONV_STATS && !a.stat_part) return hipErrorInvalidValue;
   if (a.mode == CONV_NORM && !a.bn_stats) return hipErrorInvalidValue;
   if (kind == 0) {
     if (epi == EPI_BSUM) hipLaunchKernelGGL(k_conv_first<EPI_BSUM>, g16, dim3(256), 0, s, a);
     else if (epi == EPI_STATS) hipLaunchKernelGGL(k_conv_first<EPI_STATS>, g16, dim3(256), 0, s, a);
+    else if (epi == EPI_NORM) hipLaunchKernelGGL(k_conv_first<EPI_NORM>, g16, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_conv_first<EPI_PLAIN>, g16, dim3(256), 0, s, a);
   } else if (kind == 1) {
     if (epi == EPI_BSUM) hipLaunchKernelGGL(k_conv_mid16<EPI_BSUM>, g16, dim3(256), 0, s, a);
     else if (epi == EPI_STATS) hipLaunchKernelGGL(k_conv_mid16<EPI_STATS>, g16, dim3(256), 0, s, a);
+    else if (epi == EPI_NORM) hipLaunchKernelGGL(k_conv_mid16<EPI_NORM>, g16, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_conv_mid16<EPI_PLAIN>, g16, dim3(256), 0, s, a);
   }
   else if (kind == 2) hipLaunchKernelGGL(k_conv_last, g16, dim3(256), 0, s, a);
