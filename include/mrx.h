@@ -547,7 +547,11 @@ enum {
   MRX_KERNEL_CG_UPDATE = 1,  /* CG update of x, r and the residual partials */
   MRX_KERNEL_CONV_MID = 2,   /* 64 -> 64 denoiser layer (forward and input gradient) */
   MRX_KERNEL_WGRAD_MID = 3,  /* weight gradient of a 64 -> 64 layer */
-  MRX_KERNEL_COUNT = 4
+  MRX_KERNEL_VN_FILTER = 4,  /* variational-network stage: filter responses + activation (forward) */
+  MRX_KERNEL_VN_FILTER_REV = 5,  /* the same in the reverse pass (also K g and the activation's derivative) */
+  MRX_KERNEL_VN_ADJOINT = 6, /* transposed filters + stage update (forward and reverse) */
+  MRX_KERNEL_VN_KGRAD = 7,   /* filter gradients of a stage */
+  MRX_KERNEL_COUNT = 8
 };
 mrx_status mrx_plan_kernel_timing(mrx_plan plan, int32_t enable);
 mrx_status mrx_plan_kernel_time(mrx_plan plan, int32_t kid, double* total_us, int32_t* count);

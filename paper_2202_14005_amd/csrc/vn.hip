@@ -18,6 +18,10 @@ constexpr int VT = 16;                 // output tile edge (16 x 16 pixels, 256 
 constexpr int VH = VT + 2 * VN_R;      // tile with halo
 constexpr float VN_SIG = 2.0f / (VN_NW - 1);
 constexpr float VN_INV2S2 = 1.0f / (2.0f * VN_SIG * VN_SIG);
+typedef __attribute__((address_space(4))) float ConstF;  // read-only global memory
+// LDS stride of a pixel's 24 activations in the adjoint: padded to 28 floats
+// so that the float4 reads of 16 consecutive pixels fall in distinct banks
+constexpr int VNP = VN_NK + 4;
 
 // kt[tap][i] = k_i[tap] (complex), from k[i][tap].
 __global__ void k_vn_pack(const float2* k, float2* kt) {
@@ -79,22 +83,40 @@ __global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
   const int gy = y0 + ly, gx = x0 + lx;
   if (gy >= H || gx >= W) return;
   const int64_t o = (d.xoff + (int64_t)gy * W + gx) * VN_NK;
+  // The kernel never writes the RBF weights: read through the constant
+  // address space they stay scalar loads between the output stores.
+  const ConstF* w = (const ConstF*)a.w;
+  // exp(-t^2 / (2 sigma^2)) = 2^(-(t c) t) with c = log2(e) / (2 sigma^2);
+  // Phi'' = -(1 / sigma^2) sum_j w_ij t_j exp(...)
+  constexpr float C2 = VN_INV2S2 * 1.44269504088896341f;
 #pragma unroll
-  for (int i = 0; i < VN_NK; ++i) {
-    float p1 = 0.f, p2 = 0.f;
-    const float* wi = a.w + i * VN_NW;  // uniform
-    for (int j = 0; j < VN_NW; ++j) {
-      const float mu = -1.0f + (2.0f / (VN_NW - 1)) * (float)j;
-      const float t = s[i] - mu;
-      const float e = __expf(-t * t * VN_INV2S2);
-      p1 = fmaf(wi[j], e, p1);
-      if constexpr (REV) p2 = fmaf(wi[j] * (-t * (2.0f * VN_INV2S2)), e, p2);
+  for (int i0 = 0; i0 < VN_NK; i0 += 4) {
+    float4 u4, e4, kg4, s4;
+    float* pu = &u4.x;
+    float* pe = &e4.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k;
+      float p1 = 0.f, p2 = 0.f;
+#pragma unroll
+      for (int j = 0; j < VN_NW; ++j) {
+        const float mu = -1.0f + (2.0f / (VN_NW - 1)) * (float)j;
+        const float wij = w[i * VN_NW + j];
+        const float t = s[i] - mu;
+        const float e = __builtin_amdgcn_exp2f(-(t * C2) * t);
+        p1 = fmaf(wij, e, p1);
+        if constexpr (REV) p2 = fmaf(wij * t, e, p2);
+      }
+      pu[k] = p1;
+      if constexpr (REV) pe[k] = (-2.0f * VN_INV2S2) * p2 * kg[i];
     }
-    a.u[o + i] = p1;
+    *(float4*)(a.u + o + i0) = u4;
     if constexpr (REV) {
-      a.e[o + i] = p2 * kg[i];
-      a.kg[o + i] = kg[i];
-      a.s[o + i] = s[i];
+      kg4 = make_float4(kg[i0], kg[i0 + 1], kg[i0 + 2], kg[i0 + 3]);
+      s4 = make_float4(s[i0], s[i0 + 1], s[i0 + 2], s[i0 + 3]);
+      *(float4*)(a.e + o + i0) = e4;
+      *(float4*)(a.kg + o + i0) = kg4;
+      *(float4*)(a.s + o + i0) = s4;
     }
   }
 }
@@ -105,7 +127,7 @@ __global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
 // and, in the reverse mode, per-workgroup partials of Re<g, qx - aHy>.
 template <bool REV>
 __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
-  __shared__ __attribute__((aligned(16))) float tv[VH * VH * VN_NK];  // [pixel][24]
+  __shared__ __attribute__((aligned(16))) float tv[VH * VH * VNP];  // [pixel][24 + 4 pad]
   __shared__ float red[4];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
@@ -115,12 +137,14 @@ __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
   float lam_part = 0.f;
   if (x0 < W && y0 < H) {
     const float* v = REV ? a.e : a.u;
-    for (int q = threadIdx.x; q < VH * VH * VN_NK; q += 256) {
-      const int p = q / VN_NK, i = q % VN_NK;
+    // six float4 chunks per pixel
+    for (int q = threadIdx.x; q < VH * VH * (VN_NK / 4); q += 256) {
+      const int p = q / (VN_NK / 4), k = q % (VN_NK / 4);
       const int gy = y0 + p / VH - VN_R, gx = x0 + p % VH - VN_R;
-      float val = 0.f;
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) val = v[(d.xoff + (int64_t)gy * W + gx) * VN_NK + i];
-      tv[q] = val;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+        val = *(const float4*)(v + (d.xoff + (int64_t)gy * W + gx) * VN_NK + 4 * k);
+      *(float4*)&tv[p * VNP + 4 * k] = val;
     }
     __syncthreads();
     const int ly = threadIdx.x / VT, lx = threadIdx.x % VT;
@@ -131,7 +155,7 @@ __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
         const int tap = dy * VN_KS + dx;
         const int tp = (ly + 2 * VN_R - dy) * VH + lx + 2 * VN_R - dx;
         const float2* kt = a.kt + tap * VN_NK;
-        const float4* t4 = (const float4*)&tv[tp * VN_NK];  // the 24 values of pixel tp: 6 reads
+        const float4* t4 = (const float4*)&tv[tp * VNP];  // the 24 values of pixel tp: 6 reads
 #pragma unroll
         for (int k = 0; k < VN_NK / 4; ++k) {
           const float4 v4 = t4[k];
@@ -251,10 +275,14 @@ __global__ void __launch_bounds__(256) k_vn_kgrad(VnArgs a) {
 }
 
 // RBF-weight gradients: dw_ij = -sum_p Kg_i[p] exp(-(s_i[p] - mu_j)^2 / (2 sigma^2)).
-// One workgroup per (band, slice); thread t < 24 * 31 owns (i, j).
+// One workgroup per (band, slice); thread t < 24 * 31 owns (i, j).  A chunk
+// of up to 256 columns is staged filter-major ([24][260], zero-padded to a
+// multiple of 4 columns) so that a thread reads four pixels per float4.
+constexpr int VWC = 256;      // columns per chunk
+constexpr int VWS = VWC + 4;  // LDS row stride (floats)
 __global__ void __launch_bounds__(768) k_vn_wgrad(VnArgs a) {
-  __shared__ float sv[256 * VN_NK];
-  __shared__ float gv[256 * VN_NK];
+  __shared__ __attribute__((aligned(16))) float sv[VN_NK * VWS];
+  __shared__ __attribute__((aligned(16))) float gv[VN_NK * VWS];
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
   float* part = a.part_w + (int64_t)wg * (VN_NK * VN_NW);
   const int b = a.slices[blockIdx.y];
@@ -262,23 +290,37 @@ __global__ void __launch_bounds__(768) k_vn_wgrad(VnArgs a) {
   const int H = d.H, W = d.W;
   const int t = threadIdx.x, i = t / VN_NW, j = t % VN_NW;
   const float mu = -1.0f + (2.0f / (VN_NW - 1)) * (float)j;
+  constexpr float C2 = VN_INV2S2 * 1.44269504088896341f;  // exp(-z / (2 sigma^2)) = 2^(-z c)
   float acc = 0.f;
   for (int rr = 0; rr < VN_BAND; ++rr) {
     const int row = blockIdx.x * VN_BAND + rr;
     if (row >= H) break;
-    for (int c0 = 0; c0 < W; c0 += 256) {
-      const int cw = min(256, W - c0);
+    for (int c0 = 0; c0 < W; c0 += VWC) {
+      const int cw = min(VWC, W - c0), cw4 = (cw + 3) & ~3;
       __syncthreads();
-      for (int q = t; q < cw * VN_NK; q += 768) {
-        const int64_t o = (d.xoff + (int64_t)row * W + c0) * VN_NK + q;
-        sv[q] = a.s[o];
-        gv[q] = a.kg[o];
+      for (int q = t; q < cw4 * VN_NK; q += 768) {
+        const int c = q / VN_NK, ii = q % VN_NK;
+        float sval = 0.f, gval = 0.f;  // padding columns add Kg = 0
+        if (c < cw) {
+          const int64_t o = (d.xoff + (int64_t)row * W + c0) * VN_NK + q;
+          sval = a.s[o];
+          gval = a.kg[o];
+        }
+        sv[ii * VWS + c] = sval;
+        gv[ii * VWS + c] = gval;
       }
       __syncthreads();
       if (t < VN_NK * VN_NW) {
-        for (int c = 0; c < cw; ++c) {
-          const float dd = sv[c * VN_NK + i] - mu;
-          acc = fmaf(gv[c * VN_NK + i], __expf(-dd * dd * VN_INV2S2), acc);
+        const float4* s4 = (const float4*)&sv[i * VWS];
+        const float4* g4 = (const float4*)&gv[i * VWS];
+        for (int c = 0; c < cw4 / 4; ++c) {
+          const float4 sq = s4[c], gq = g4[c];
+          const float ss[4] = {sq.x, sq.y, sq.z, sq.w}, gg[4] = {gq.x, gq.y, gq.z, gq.w};
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const float dd = ss[m] - mu;
+            acc = fmaf(gg[m], __builtin_amdgcn_exp2f(-(dd * C2) * dd), acc);
+          }
         }
       }
     }
@@ -388,8 +430,14 @@ mrx_status mrx_vn_stage(mrx_plan p, const float* x, const float* aHy, const floa
   a.q = q;
   a.out = (float2*)x_next;
   dim3 grid((p->maxW + VT - 1) / VT, (p->maxH + VT - 1) / VT, p->B);
-  hipLaunchKernelGGL(k_vn_filter<false>, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_vn_adjoint<false>, grid, dim3(256), 0, s, a);
+  {
+    KernelTimer kt(p, MRX_KERNEL_VN_FILTER, s);
+    hipLaunchKernelGGL(k_vn_filter<false>, grid, dim3(256), 0, s, a);
+  }
+  {
+    KernelTimer kt(p, MRX_KERNEL_VN_ADJOINT, s);
+    hipLaunchKernelGGL(k_vn_adjoint<false>, grid, dim3(256), 0, s, a);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MRX_OK : hip_fail(e, "vn_stage");
 }
@@ -420,11 +468,20 @@ mrx_status mrx_vn_stage_backward(mrx_plan p, const float* g, const float* x, con
   a.out = (float2*)g_x;
   dim3 grid((p->maxW + VT - 1) / VT, (p->maxH + VT - 1) / VT, p->B);
   const int tiles = grid.x * grid.y * grid.z;
-  hipLaunchKernelGGL(k_vn_filter<true>, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_vn_adjoint<true>, grid, dim3(256), 0, s, a);
+  {
+    KernelTimer kt(p, MRX_KERNEL_VN_FILTER_REV, s);
+    hipLaunchKernelGGL(k_vn_filter<true>, grid, dim3(256), 0, s, a);
+  }
+  {
+    KernelTimer kt(p, MRX_KERNEL_VN_ADJOINT, s);
+    hipLaunchKernelGGL(k_vn_adjoint<true>, grid, dim3(256), 0, s, a);
+  }
   const int bands = (p->maxH + VN_BAND - 1) / VN_BAND;
   const int kbands = (p->maxH + VN_KBAND - 1) / VN_KBAND;
-  hipLaunchKernelGGL(k_vn_kgrad, dim3(kbands, p->B), dim3(256), 0, s, a);
+  {
+    KernelTimer kt(p, MRX_KERNEL_VN_KGRAD, s);
+    hipLaunchKernelGGL(k_vn_kgrad, dim3(kbands, p->B), dim3(256), 0, s, a);
+  }
   hipLaunchKernelGGL(k_vn_wgrad, dim3(bands, p->B), dim3(768), 0, s, a);
   const int nk = VN_NK * VN_TAPS * 2, nw = VN_NK * VN_NW;
   const dim3 rb(64 * VR_WAVES);

@@ -276,6 +276,7 @@ class Plan:
 
     # kernel ids of kernel_time
     KERNEL_NORMAL, KERNEL_CG_UPDATE, KERNEL_CONV_MID, KERNEL_WGRAD_MID = 0, 1, 2, 3
+    KERNEL_VN_FILTER, KERNEL_VN_FILTER_REV, KERNEL_VN_ADJOINT, KERNEL_VN_KGRAD = 4, 5, 6, 7
 
     def kernel_timing(self, enable: bool):
         """Switch per-launch event timing of the hot kernels on or off (and

@@ -20,7 +20,9 @@ maps exceed the MALL), ``uneven_graph`` ``reps`` replays of the captured
 64-slice reconstruction (A^H y, MoDL T = 5, CG-SENSE fallback, judge), for
 kernel traces, ``copy`` a device-to-device
 copy of 256 MiB (256 MiB read, 256 MiB written) whose counter readings
-calibrate FETCH_SIZE and WRITE_SIZE.
+calibrate FETCH_SIZE and WRITE_SIZE, ``vn`` ``reps`` forward and reverse
+passes of the variational network (10 stages, 4 slices of 384 x 320, 15
+coils).
 """
 from __future__ import annotations
 
@@ -96,6 +98,22 @@ def main():
                 rec.replay()
         torch.cuda.synchronize()
         print("uneven schedules:", sorted({up.schedule(b) for b in range(up.B)}), flush=True)
+    if "vn" in what:
+        # variational network: 10 stages on 4 slices of 384 x 320, 15 coils;
+        # forward and reverse pass per rep
+        vB, vH, vW = 4, 384, 320
+        vd = batch_inputs([7000 + i for i in range(vB)], vH, vW, C, 4, 24, "vd")
+        vp = ops.Plan(vH, vW, C, B=vB, device=dev, network=True, vn=True)
+        vx, vS, vm = t(vd["x"]), t(vd["S"]), t(vd["mask"])
+        vy = vp.sense_fwd(vx, vS, vm, noise=t(vd["noise"]))
+        vnet = ops.VarNet.init(vp, seed=1, T=10)
+        for _ in range(a.reps):
+            vaHy = vp.sense_adj(vy, vS, vm)
+            vxT, vst = vnet.forward(vaHy, vS, vm)
+            _, vg = vp.mse_grad(vxT, vx)
+            vnet.backward(vg, vst, vaHy, vS, vm)
+        torch.cuda.synchronize()
+        del vd, vp, vnet, vst
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
     dst = torch.empty_like(src)
     torch.cuda.synchronize()

@@ -34,7 +34,7 @@ def case(B, H, W, C, seed=900, kind="regular", nc=28):
     return d, aHy, p
 
 
-@pytest.mark.parametrize("B,H,W,C", [(2, 48, 40, 4), (1, 96, 80, 6), (1, 384, 320, 15)])
+@pytest.mark.parametrize("B,H,W,C", [(2, 48, 40, 4), (1, 96, 80, 6), (1, 50, 270, 4), (1, 384, 320, 15)])
 def test_vn_stage_forward_parity(B, H, W, C):
     d, aHy, p = case(B, H, W, C)
     plan = ops.Plan(H, W, C, B=B, vn=True)
@@ -48,10 +48,12 @@ def test_vn_stage_forward_parity(B, H, W, C):
     assert e < OUT_TOL and pe < 2 * OUT_TOL
 
 
-@pytest.mark.parametrize("B,H,W,C", [(2, 48, 40, 4), (1, 384, 320, 15)])
+@pytest.mark.parametrize("B,H,W,C", [(2, 48, 40, 4), (1, 50, 270, 4), (1, 384, 320, 15)])
 def test_vn_stage_backward_parity(B, H, W, C):
     """At 384 x 320 the filter-gradient kernel walks five 64-column chunks
-    and the RBF-weight kernel two 256-column chunks per row band."""
+    and the RBF-weight kernel two 256-column chunks per row band; at 50 x 270
+    both end on a ragged chunk (14 columns; the RBF-weight kernel pads it to
+    16 with zero gradients) and the 16 x 16 tiles on ragged edges."""
     d, aHy, p = case(B, H, W, C, seed=950)
     t = 1
     rng = np.random.default_rng(4)
