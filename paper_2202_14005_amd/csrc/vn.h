@@ -9,7 +9,7 @@ constexpr int VN_KS = 11;               // filter edge
 constexpr int VN_R = VN_KS / 2;
 constexpr int VN_TAPS = VN_KS * VN_KS;
 constexpr int VN_NW = 31;               // radial basis functions
-constexpr int VN_BAND = 4;              // rows per gradient workgroup
+constexpr int VN_BAND = 3;              // rows per RBF-weight-gradient workgroup (384 rows: 2 per CU)
 
 struct VnArgs {
   const SliceDesc* desc;

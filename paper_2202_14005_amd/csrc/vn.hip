@@ -19,9 +19,10 @@ constexpr int VH = VT + 2 * VN_R;      // tile with halo
 constexpr float VN_SIG = 2.0f / (VN_NW - 1);
 constexpr float VN_INV2S2 = 1.0f / (2.0f * VN_SIG * VN_SIG);
 typedef __attribute__((address_space(4))) float ConstF;  // read-only global memory
-// LDS stride of a pixel's 24 activations in the adjoint: padded to 28 floats
-// so that the float4 reads of 16 consecutive pixels fall in distinct banks
-constexpr int VNP = VN_NK + 4;
+// The adjoint stages the activations of 12 filters at a time: a 12-float
+// pixel stride puts the float4 reads of 16 consecutive pixels in distinct
+// banks, and the 32 KB tile lets four workgroups share a CU.
+constexpr int VNH = VN_NK / 2;
 
 // kt[tap][i] = k_i[tap] (complex), from k[i][tap].
 __global__ void k_vn_pack(const float2* k, float2* kt) {
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
 // and, in the reverse mode, per-workgroup partials of Re<g, qx - aHy>.
 template <bool REV>
 __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
-  __shared__ __attribute__((aligned(16))) float tv[VH * VH * VNP];  // [pixel][24 + 4 pad]
+  __shared__ __attribute__((aligned(16))) float tv[VH * VH * VNH];  // [pixel][12]: one half of the filters
   __shared__ float red[4];
   const int b = a.slices[blockIdx.z];
   const SliceDesc d = a.desc[b];
@@ -137,38 +138,43 @@ __global__ void __launch_bounds__(256) k_vn_adjoint(VnArgs a) {
   float lam_part = 0.f;
   if (x0 < W && y0 < H) {
     const float* v = REV ? a.e : a.u;
-    // six float4 chunks per pixel
-    for (int q = threadIdx.x; q < VH * VH * (VN_NK / 4); q += 256) {
-      const int p = q / (VN_NK / 4), k = q % (VN_NK / 4);
-      const int gy = y0 + p / VH - VN_R, gx = x0 + p % VH - VN_R;
-      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-        val = *(const float4*)(v + (d.xoff + (int64_t)gy * W + gx) * VN_NK + 4 * k);
-      *(float4*)&tv[p * VNP + 4 * k] = val;
-    }
-    __syncthreads();
     const int ly = threadIdx.x / VT, lx = threadIdx.x % VT;
-    float rr = 0.f, ri = 0.f;
-    // s[p] used x[p + d] => adjoint gathers v[p - d]
-    for (int dy = 0; dy < VN_KS; ++dy) {
-      for (int dx = 0; dx < VN_KS; ++dx) {
-        const int tap = dy * VN_KS + dx;
-        const int tp = (ly + 2 * VN_R - dy) * VH + lx + 2 * VN_R - dx;
-        const float2* kt = a.kt + tap * VN_NK;
-        const float4* t4 = (const float4*)&tv[tp * VNP];  // the 24 values of pixel tp: 6 reads
+    // four partial sums per component (filter index mod 4), added at the end
+    float ra[4] = {0.f, 0.f, 0.f, 0.f}, ia[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int h = 0; h < 2; ++h) {
+      if (h) __syncthreads();  // every read of the first half is done
+      // three float4 chunks per pixel
+      for (int q = threadIdx.x; q < VH * VH * (VNH / 4); q += 256) {
+        const int p = q / (VNH / 4), k = q % (VNH / 4);
+        const int gy = y0 + p / VH - VN_R, gx = x0 + p % VH - VN_R;
+        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+          val = *(const float4*)(v + (d.xoff + (int64_t)gy * W + gx) * VN_NK + h * VNH + 4 * k);
+        *(float4*)&tv[p * VNH + 4 * k] = val;
+      }
+      __syncthreads();
+      // s[p] used x[p + d] => adjoint gathers v[p - d]
+      for (int dy = 0; dy < VN_KS; ++dy) {
+        for (int dx = 0; dx < VN_KS; ++dx) {
+          const int tap = dy * VN_KS + dx;
+          const int tp = (ly + 2 * VN_R - dy) * VH + lx + 2 * VN_R - dx;
+          const float2* kt = a.kt + tap * VN_NK + h * VNH;
+          const float4* t4 = (const float4*)&tv[tp * VNH];  // the 12 values of pixel tp: 3 reads
 #pragma unroll
-        for (int k = 0; k < VN_NK / 4; ++k) {
-          const float4 v4 = t4[k];
-          const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
+          for (int k = 0; k < VNH / 4; ++k) {
+            const float4 v4 = t4[k];
+            const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const float2 kk = kt[4 * k + m];
-            rr = fmaf(kk.x, vs[m], rr);
-            ri = fmaf(-kk.y, vs[m], ri);
+            for (int m = 0; m < 4; ++m) {
+              const float2 kk = kt[4 * k + m];
+              ra[m] = fmaf(kk.x, vs[m], ra[m]);
+              ia[m] = fmaf(-kk.y, vs[m], ia[m]);
+            }
           }
         }
       }
     }
+    const float rr = (ra[0] + ra[1]) + (ra[2] + ra[3]), ri = (ia[0] + ia[1]) + (ia[2] + ia[3]);
     const int gy = y0 + ly, gx = x0 + lx;
     if (gy < H && gx < W) {
       const int64_t o = d.xoff + (int64_t)gy * W + gx;
