@@ -75,7 +75,7 @@ struct mrx_plan_s {
   float* bn_ggamma = nullptr;
   float* bn_gbeta = nullptr;
   // VarNet workspace
-  size_t ws_vn_kt = 0, ws_vn_u = 0, ws_vn_e = 0, ws_vn_kg = 0, ws_vn_s = 0, ws_vn_qx = 0, ws_vn_qg = 0;
+  size_t ws_vn_kt = 0, ws_vn_wa = 0, ws_vn_wd = 0, ws_vn_u = 0, ws_vn_e = 0, ws_vn_kg = 0, ws_vn_s = 0, ws_vn_qx = 0, ws_vn_qg = 0;
   size_t ws_vn_plam = 0, ws_vn_pk = 0, ws_vn_pw = 0;
   bool net_ready = false;
   // size groups of one operator application run concurrently: groups after

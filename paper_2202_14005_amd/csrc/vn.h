@@ -16,7 +16,9 @@ struct VnArgs {
   const int* slices;
   int nslices;
   const float2* kt;       // filters, tap-major [121][24] complex
+  const float* wa;        // filters as matrix-core operands [121][2][32]: Re k_i, then -Im k_i (i >= 24: 0)
   const float* w;         // RBF weights [24][31]
+  const float* wd;        // RBF coefficients per group of 8 knots [24][2][32] (k_vn_pack_rbf)
   const float* lam;       // stage step size (device, 1 float)
   const float2* x;        // stage input
   const float2* g;        // reverse mode: gradient w.r.t. the stage output

@@ -3,11 +3,12 @@
 // with N_k = 24 complex 11 x 11 filters (cross-correlation, zero "same"
 // padding, imaginary part of the filter response discarded) and trainable
 // activations Phi'_i(s) = sum_j w_ij exp(-(s - mu_j)^2 / (2 sigma^2)),
-// mu_j = -1 + 2j/30, sigma = 2/30 (31 knots).  All in fp32 on the vector ALUs:
-// the activation's width (sigma = 1/15) turns a 2^-9 relative error of the
-// filter response into a several-percent error of Phi', so bf16 operands
-// would not hold parity.  Filter weights are read tap-major through scalar
-// loads (uniform across a wavefront); image tiles are staged in LDS.
+// mu_j = -1 + 2j/30, sigma = 2/30 (31 knots).  All in fp32: the activation's
+// width (sigma = 1/15) turns a 2^-9 relative error of the filter response
+// into a several-percent error of Phi', so bf16 operands would not hold
+// parity.  The filter responses run on the fp32 matrix cores, everything
+// else on the vector ALUs with the filter and RBF weights read through
+// scalar loads (uniform across a wavefront); image tiles are staged in LDS.
 #include "../../include/mrx.h"
 #include "api_internal.h"
 #include "vn.h"
@@ -24,12 +25,25 @@ typedef __attribute__((address_space(4))) float ConstF;  // read-only global mem
 // banks, and the 32 KB tile lets four workgroups share a CU.
 constexpr int VNH = VN_NK / 2;
 
-// kt[tap][i] = k_i[tap] (complex), from k[i][tap].
-__global__ void k_vn_pack(const float2* k, float2* kt) {
+// kt[tap][i] = k_i[tap] (complex), from k[i][tap]; and the matrix-core
+// operand layout wa[tap][c][32]: c = 0 Re k_i[tap], c = 1 -Im k_i[tap], for
+// i < 24, zero for the padding rows 24..31.
+constexpr int VN_WA = VN_TAPS * 64;  // floats of wa
+__global__ void k_vn_pack(const float2* k, float2* kt, float* wa) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= VN_NK * VN_TAPS) return;
-  const int i = idx % VN_NK, tap = idx / VN_NK;
-  kt[idx] = k[i * VN_TAPS + tap];
+  if (idx < VN_NK * VN_TAPS) {
+    const int i = idx % VN_NK, tap = idx / VN_NK;
+    kt[idx] = k[i * VN_TAPS + tap];
+  }
+  if (idx < VN_WA) {
+    const int tap = idx / 64, c = (idx / 32) % 2, i = idx % 32;
+    float v = 0.f;
+    if (i < VN_NK) {
+      const float2 kk = k[i * VN_TAPS + tap];
+      v = c ? -kk.y : kk.x;
+    }
+    wa[idx] = v;
+  }
 }
 
 __device__ __forceinline__ void load_ctile(float2* tile, const float2* img, int H, int W, int y0, int x0) {
@@ -41,55 +55,62 @@ __device__ __forceinline__ void load_ctile(float2* tile, const float2* img, int 
   }
 }
 
-// Filter responses s_i = Re(k_i * x) (and Kg_i = Re(k_i * g) in the reverse
-// mode) for a 16 x 16 tile, then the activation:
-//   forward: u_i = Phi'_i(s_i)
-//   reverse: u_i = Phi'_i(s_i), e_i = Phi''_i(s_i) * Kg_i, and Kg_i, s_i kept
-// Outputs are [pixel][24] fp32 at offset xoff * 24.
+// A 16 x 16 tile: slice and corner
+struct VnTile {
+  int b, x0, y0;
+};
+
+// The Gaussian RBF in groups of 8 knots.  With knot spacing D (= sigma),
+// group g's centre m = -1 + (8 g + 3.5) D and u = s - m, each of its knots
+// mu = m + (k - 3.5) D (k = 0..7) gives
+//   exp(-(s - mu)^2 / (2 sigma^2)) = F Q^k D_k,
+//   F = exp(-c u (u + 7 D)), Q = exp(2 c D u), D_k = exp(-c D^2 (k - 3.5)^2),
+// c = 1 / (2 sigma^2), so that sum_k w_k exp(...) = F P(Q) with the
+// polynomial P(Q) = sum_k (w_k D_k) Q^k: two exponentials and a Horner
+// scheme per 8 knots.  And sum_k w_k t_k exp(...) (t_k = s - mu_k, for
+// Phi'') = F (u P(Q) - P2(Q)), P2(Q) = sum_k ((k - 3.5) D w_k D_k) Q^k.
+// u is held to [-VN_UC, VN_UC]: Q^7 stays below 2^122, and beyond the bound
+// every knot of the group is more than 0.56 from s, where each term is below
+// exp(-35) of its weight (the held value is that small, or zero).
+constexpr int VN_GK = 8;                      // knots per group
+constexpr int VN_NG = (VN_NW + VN_GK - 1) / VN_GK;  // groups (the last padded with zero weights)
+constexpr int VN_WD = VN_NK * 2 * VN_NG * VN_GK;    // floats of the coefficient table
+constexpr float VN_UC = 0.8f;
+constexpr float VN_LOG2E = 1.44269504088896341f;
+
+// wd[i][0][8 g + k] = w_i,8g+k D_k, wd[i][1][8 g + k] = (k - 3.5) D w_i,8g+k D_k
+// (zero past the last knot), from w[i][31].
+__global__ void k_vn_pack_rbf(const float* w, float* wd) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= VN_WD) return;
+  const int i = idx / (2 * VN_NG * VN_GK), c = (idx / (VN_NG * VN_GK)) % 2, j = idx % (VN_NG * VN_GK);
+  const int k = j % VN_GK;
+  float v = 0.f;
+  if (j < VN_NW) {
+    const double dk = (double)k - 0.5 * (VN_GK - 1);
+    const double Dk = exp(-(double)VN_INV2S2 * (double)VN_SIG * (double)VN_SIG * dk * dk);
+    v = (float)((double)w[i * VN_NW + j] * Dk * (c ? dk * (double)VN_SIG : 1.0));
+  }
+  wd[idx] = v;
+}
+// The activation of one pixel (pix = ly * 16 + lx of the tile) from its 24
+// filter responses s (and, reverse, Kg); stores the [pixel][24] outputs.
 template <bool REV>
-__global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
-  __shared__ float2 tx[VH * VH];
-  __shared__ float2 tg[REV ? VH * VH : 1];
-  const int b = a.slices[blockIdx.z];
-  const SliceDesc d = a.desc[b];
+__device__ __forceinline__ void vn_activation(const VnArgs& a, const VnTile& tl, int pix, const float (&s)[VN_NK],
+                                              const float (&kg)[REV ? VN_NK : 1]) {
+  const SliceDesc d = a.desc[tl.b];
   const int H = d.H, W = d.W;
-  const int x0 = blockIdx.x * VT, y0 = blockIdx.y * VT;
-  if (x0 >= W || y0 >= H) return;
-  load_ctile(tx, a.x + d.xoff, H, W, y0, x0);
-  if constexpr (REV) load_ctile(tg, a.g + d.xoff, H, W, y0, x0);
-  __syncthreads();
-  const int ly = threadIdx.x / VT, lx = threadIdx.x % VT;
-  float s[VN_NK], kg[REV ? VN_NK : 1];
-#pragma unroll
-  for (int i = 0; i < VN_NK; ++i) {
-    s[i] = 0.f;
-    if constexpr (REV) kg[i] = 0.f;
-  }
-  for (int dy = 0; dy < VN_KS; ++dy) {
-    for (int dx = 0; dx < VN_KS; ++dx) {
-      const int tap = dy * VN_KS + dx;
-      const int tp = (ly + dy) * VH + lx + dx;
-      const float2 xv = tx[tp];
-      float2 gv = make_float2(0.f, 0.f);
-      if constexpr (REV) gv = tg[tp];
-      const float2* kt = a.kt + tap * VN_NK;  // uniform: scalar loads
-#pragma unroll
-      for (int i = 0; i < VN_NK; ++i) {
-        const float2 kk = kt[i];
-        s[i] = fmaf(kk.x, xv.x, fmaf(-kk.y, xv.y, s[i]));
-        if constexpr (REV) kg[i] = fmaf(kk.x, gv.x, fmaf(-kk.y, gv.y, kg[i]));
-      }
-    }
-  }
+  const int ly = pix / VT, lx = pix % VT;
+  const int y0 = tl.y0, x0 = tl.x0;
   const int gy = y0 + ly, gx = x0 + lx;
   if (gy >= H || gx >= W) return;
   const int64_t o = (d.xoff + (int64_t)gy * W + gx) * VN_NK;
-  // The kernel never writes the RBF weights: read through the constant
+  // The kernel never writes the coefficients: read through the constant
   // address space they stay scalar loads between the output stores.
-  const ConstF* w = (const ConstF*)a.w;
-  // exp(-t^2 / (2 sigma^2)) = 2^(-(t c) t) with c = log2(e) / (2 sigma^2);
-  // Phi'' = -(1 / sigma^2) sum_j w_ij t_j exp(...)
-  constexpr float C2 = VN_INV2S2 * 1.44269504088896341f;
+  const ConstF* wd = (const ConstF*)a.wd;
+  constexpr float KF = -VN_INV2S2 * VN_LOG2E;                // F = 2^(KF u (u + 7 D))
+  constexpr float KQ = 2.0f * VN_INV2S2 * VN_SIG * VN_LOG2E;  // Q = 2^(KQ u)
+  constexpr float SPAN = (VN_GK - 1) * VN_SIG;
 #pragma unroll
   for (int i0 = 0; i0 < VN_NK; i0 += 4) {
     float4 u4, e4, kg4, s4;
@@ -100,13 +121,23 @@ __global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
       const int i = i0 + k;
       float p1 = 0.f, p2 = 0.f;
 #pragma unroll
-      for (int j = 0; j < VN_NW; ++j) {
-        const float mu = -1.0f + (2.0f / (VN_NW - 1)) * (float)j;
-        const float wij = w[i * VN_NW + j];
-        const float t = s[i] - mu;
-        const float e = __builtin_amdgcn_exp2f(-(t * C2) * t);
-        p1 = fmaf(wij, e, p1);
-        if constexpr (REV) p2 = fmaf(wij * t, e, p2);
+      for (int g = 0; g < VN_NG; ++g) {
+        const float m = -1.0f + (VN_GK * g + 0.5f * (VN_GK - 1)) * VN_SIG;
+        const float u = fminf(fmaxf(s[i] - m, -VN_UC), VN_UC);
+        const float F = __builtin_amdgcn_exp2f((u * KF) * (u + SPAN));
+        const float Q = __builtin_amdgcn_exp2f(u * KQ);
+        const ConstF* c1 = wd + (i * 2) * (VN_NG * VN_GK) + VN_GK * g;
+        float P1 = c1[VN_GK - 1];
+#pragma unroll
+        for (int q = VN_GK - 2; q >= 0; --q) P1 = fmaf(P1, Q, c1[q]);
+        p1 = fmaf(F, P1, p1);
+        if constexpr (REV) {
+          const ConstF* c2 = c1 + VN_NG * VN_GK;
+          float P2 = c2[VN_GK - 1];
+#pragma unroll
+          for (int q = VN_GK - 2; q >= 0; --q) P2 = fmaf(P2, Q, c2[q]);
+          p2 = fmaf(F, fmaf(u, P1, -P2), p2);
+        }
       }
       pu[k] = p1;
       if constexpr (REV) pe[k] = (-2.0f * VN_INV2S2) * p2 * kg[i];
@@ -120,6 +151,113 @@ __global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
       *(float4*)(a.s + o + i0) = s4;
     }
   }
+}
+
+// Filter responses s_i = Re(k_i * x) (and Kg_i = Re(k_i * g) in the reverse
+// mode) for a 16 x 16 tile, then the activation:
+//   forward: u_i = Phi'_i(s_i)
+//   reverse: u_i = Phi'_i(s_i), e_i = Phi''_i(s_i) * Kg_i, and Kg_i, s_i kept
+// Outputs are [pixel][24] fp32 at offset xoff * 24.
+//
+// The responses run on the fp32 matrix cores: per tap one 32 x 32 x 2
+// product D[i][j] += sum_c A[i][c] B[c][j] with A[i][c] = (Re k_i, -Im k_i)
+// (filters padded to 32 rows) and B[c][j] = (Re x, Im x) at pixel j shifted
+// by the tap, so every lane supplies one weight and one pixel value.  Each
+// wavefront owns four rows of the tile (two 32-pixel column blocks); the
+// responses go through LDS to one pixel per lane for the activation on the
+// vector ALUs.
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int VMS = VN_NK + 4;  // LDS pixel stride of the transposed responses (float4 reads conflict-free)
+
+// D layout of the 32 x 32 x 2 product: lane l holds column l % 32, and its
+// register r row 8 (r / 4) + 4 (l / 32) + r % 4; rows 24..31 (r >= 12) are
+// padding.  Writes the 24 real rows of a column block to ts[pixel][VMS].
+__device__ __forceinline__ void vn_put(const v16f& acc, float* ts, int pix, int half) {
+#pragma unroll
+  for (int r = 0; r < 12; ++r) ts[pix * VMS + 8 * (r / 4) + 4 * half + (r % 4)] = acc[r];
+}
+
+// ts[pix][0..23] -> v (the wavefront's own pixels: LDS ordering within the
+// wavefront suffices)
+__device__ __forceinline__ void vn_take(const float* ts, int pix, float (&v)[VN_NK]) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float4* r4 = (const float4*)&ts[pix * VMS];
+#pragma unroll
+  for (int q = 0; q < VN_NK / 4; ++q) {
+    const float4 t = r4[q];
+    v[4 * q] = t.x;
+    v[4 * q + 1] = t.y;
+    v[4 * q + 2] = t.z;
+    v[4 * q + 3] = t.w;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool REV>
+__global__ void __launch_bounds__(256) k_vn_filter(VnArgs a) {
+  __shared__ float tx[2][VH * VH];  // Re, Im planes of the tile with halo
+  __shared__ float tg[REV ? 2 : 1][REV ? VH * VH : 1];
+  __shared__ __attribute__((aligned(16))) float ts[VT * VT * VMS];
+  VnTile tl;
+  tl.b = a.slices[blockIdx.z];
+  tl.x0 = blockIdx.x * VT;
+  tl.y0 = blockIdx.y * VT;
+  const SliceDesc d = a.desc[tl.b];
+  const int H = d.H, W = d.W;
+  if (tl.x0 >= W || tl.y0 >= H) return;
+  for (int p = threadIdx.x; p < VH * VH; p += 256) {
+    const int gy = tl.y0 + p / VH - VN_R, gx = tl.x0 + p % VH - VN_R;
+    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    const int64_t o = d.xoff + (int64_t)gy * W + gx;
+    const float2 xv = in ? a.x[o] : make_float2(0.f, 0.f);
+    tx[0][p] = xv.x;
+    tx[1][p] = xv.y;
+    if constexpr (REV) {
+      const float2 gv = in ? a.g[o] : make_float2(0.f, 0.f);
+      tg[0][p] = gv.x;
+      tg[1][p] = gv.y;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int half = lane >> 5, j = lane & 31;
+  // column block nb holds tile pixels 64 wv + 32 nb + j: row 4 wv + 2 nb + j / 16, column j % 16
+  const int t0 = (4 * wv + j / 16) * VH + j % 16;
+  const float* px = tx[half];
+  const float* pg = tg[REV ? half : 0];
+  v16f s0 = {}, s1 = {}, g0 = {}, g1 = {};
+  const float* wa = a.wa + half * 32 + j;
+#pragma unroll 1
+  for (int dy = 0; dy < VN_KS; ++dy) {
+    float wr[VN_KS];
+#pragma unroll
+    for (int dx = 0; dx < VN_KS; ++dx) wr[dx] = wa[(dy * VN_KS + dx) * 64];
+#pragma unroll
+    for (int dx = 0; dx < VN_KS; ++dx) {
+      const int tp = t0 + dy * VH + dx;
+      s0 = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[dx], px[tp], s0, 0, 0, 0);
+      s1 = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[dx], px[tp + 2 * VH], s1, 0, 0, 0);
+      if constexpr (REV) {
+        g0 = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[dx], pg[tp], g0, 0, 0, 0);
+        g1 = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[dx], pg[tp + 2 * VH], g1, 0, 0, 0);
+      }
+    }
+  }
+  // one pixel per lane (pixel = threadIdx.x: the wavefront's own 64 pixels)
+  float s[VN_NK], kg[REV ? VN_NK : 1];
+  vn_put(s0, ts, 64 * wv + j, half);
+  vn_put(s1, ts, 64 * wv + 32 + j, half);
+  vn_take(ts, threadIdx.x, s);
+  if constexpr (REV) {
+    vn_put(g0, ts, 64 * wv + j, half);
+    vn_put(g1, ts, 64 * wv + 32 + j, half);
+    vn_take(ts, threadIdx.x, kg);
+  }
+  vn_activation<REV>(a, tl, threadIdx.x, s, kg);
 }
 
 // r = K^T v (v: [pixel][24] fp32) for a 16 x 16 tile, fused with the update
@@ -374,6 +512,8 @@ VnArgs vn_args(mrx_plan_s* p, const mrx_vn_params* prm) {
   a.slices = p->d_all;
   a.nslices = p->B;
   a.kt = (const float2*)(p->ws + p->ws_vn_kt);
+  a.wa = (const float*)(p->ws + p->ws_vn_wa);
+  a.wd = (const float*)(p->ws + p->ws_vn_wd);
   a.w = prm->w;
   a.lam = prm->lam;
   a.u = (float*)(p->ws + p->ws_vn_u);
@@ -397,6 +537,8 @@ size_t vn_workspace_bytes(mrx_plan_s* p, size_t base) {
   size_t w = 0;
   auto take = [&](size_t bytes) { size_t o = base + w; w += al(bytes); return o; };
   p->ws_vn_kt = take(sizeof(float2) * VN_NK * VN_TAPS);
+  p->ws_vn_wa = take(sizeof(float) * VN_WA);
+  p->ws_vn_wd = take(sizeof(float) * VN_WD);
   p->ws_vn_u = take(ni * VN_NK * 4);
   p->ws_vn_e = take(ni * VN_NK * 4);
   p->ws_vn_kg = take(ni * VN_NK * 4);
@@ -427,8 +569,10 @@ mrx_status mrx_vn_stage(mrx_plan p, const float* x, const float* aHy, const floa
   hipStream_t s = (hipStream_t)stream;
   VnArgs a = vn_args(p, prm);
   float2* q = (float2*)(p->ws + p->ws_vn_qx);
-  hipLaunchKernelGGL(k_vn_pack, dim3((VN_NK * VN_TAPS + 255) / 256), dim3(256), 0, s, (const float2*)prm->k,
-                     (float2*)(p->ws + p->ws_vn_kt));
+  hipLaunchKernelGGL(k_vn_pack, dim3((VN_WA + 255) / 256), dim3(256), 0, s, (const float2*)prm->k,
+                     (float2*)(p->ws + p->ws_vn_kt), (float*)(p->ws + p->ws_vn_wa));
+  hipLaunchKernelGGL(k_vn_pack_rbf, dim3((VN_WD + 255) / 256), dim3(256), 0, s, prm->w,
+                     (float*)(p->ws + p->ws_vn_wd));
   st = normal_impl(p, (const float2*)x, (const float2*)S, mask, nullptr, q, s);
   if (st != MRX_OK) return st;
   a.x = (const float2*)x;
@@ -461,8 +605,10 @@ mrx_status mrx_vn_stage_backward(mrx_plan p, const float* g, const float* x, con
   VnArgs a = vn_args(p, prm);
   float2* qx = (float2*)(p->ws + p->ws_vn_qx);
   float2* qg = (float2*)(p->ws + p->ws_vn_qg);
-  hipLaunchKernelGGL(k_vn_pack, dim3((VN_NK * VN_TAPS + 255) / 256), dim3(256), 0, s, (const float2*)prm->k,
-                     (float2*)(p->ws + p->ws_vn_kt));
+  hipLaunchKernelGGL(k_vn_pack, dim3((VN_WA + 255) / 256), dim3(256), 0, s, (const float2*)prm->k,
+                     (float2*)(p->ws + p->ws_vn_kt), (float*)(p->ws + p->ws_vn_wa));
+  hipLaunchKernelGGL(k_vn_pack_rbf, dim3((VN_WD + 255) / 256), dim3(256), 0, s, prm->w,
+                     (float*)(p->ws + p->ws_vn_wd));
   st = normal_impl(p, (const float2*)x, (const float2*)S, mask, nullptr, qx, s);
   if (st == MRX_OK) st = normal_impl(p, (const float2*)g, (const float2*)S, mask, nullptr, qg, s);
   if (st != MRX_OK) return st;

@@ -91,3 +91,43 @@ def test_vn_stack_forward_backward():
     assert rel(host(gk), rk) < GRAD_TOL
     assert rel(host(gw), rw) < GRAD_TOL
     assert np.max(np.abs(host(gl) - rl) / np.abs(rl)) < GRAD_TOL
+
+
+def test_vn_stage_wide_responses():
+    """Filter responses well outside the knot range [-1, 1] (the input scaled
+    so that the median |s| is 1.5: a large share beyond +-1, some beyond
+    +-4) and N(0, 1) RBF weights: the kernels' grouped evaluation of the RBF
+    sums (two exponentials and a polynomial per 8 knots, with the offset from
+    a group's centre held to +-0.8) against the oracle's direct sums.  The
+    stage update x - x' (regulariser and data term) is compared on its own
+    besides the output, at the gradient bound."""
+    B, H, W, C = 2, 48, 40, 4
+    d, aHy, p = case(B, H, W, C, seed=970)
+    t = 0
+    k = p["k"][t]
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal(p["w"][t].shape).astype(np.float32)
+    lam = p["lam"][t:t + 1]
+    with oracle_threads():
+        s0 = ovn.filt(aHy, k)
+    x = (aHy * (1.5 / np.median(np.abs(s0)))).astype(np.complex64)
+    g = (rng.standard_normal(aHy.shape) + 1j * rng.standard_normal(aHy.shape)).astype(np.complex64)
+    with oracle_threads():
+        s = ovn.filt(x, k)
+        ref = ovn.stage(x, aHy, d["S"], d["mask"], k, w, lam[0])
+        rx, rk, rw, rl = ovn.stage_backward(g, x, aHy, d["S"], d["mask"], k, w, lam[0])
+    out = np.mean(np.abs(s) > 1.0)
+    print(f"responses: {out:.0%} beyond +-1, max |s| {np.max(np.abs(s)):.1f}")
+    assert out > 0.3 and np.max(np.abs(s)) > 4.0
+    plan = ops.Plan(H, W, C, B=B, vn=True)
+    xn = host(plan.vn_stage(dev(x), dev(aHy), dev(d["S"]), dev(d["mask"]), dev(k), dev(w), dev(lam)))
+    e_out, e_upd = rel(xn, ref), rel(x - xn, x - ref)
+    gx, (gk, gw, gl) = plan.vn_stage_backward(dev(g), dev(x), dev(aHy), dev(d["S"]), dev(d["mask"]), dev(k),
+                                              dev(w), dev(lam))
+    errs = {"g_x": rel(host(gx), rx), "g_k": rel(host(gk), rk), "g_w": rel(host(gw), rw),
+            "g_lam": abs(float(host(gl)[0]) - rl) / abs(rl)}
+    print(f"wide responses: output {e_out:.2e}, update {e_upd:.2e}", {kk: f"{v:.2e}" for kk, v in errs.items()})
+    assert e_out < OUT_TOL and e_upd < GRAD_TOL
+    assert np.all(np.isfinite(host(gx))) and np.all(np.isfinite(host(gw)))
+    for kk, v in errs.items():
+        assert v < GRAD_TOL, kk
