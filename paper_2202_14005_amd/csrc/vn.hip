@@ -419,57 +419,74 @@ __global__ void __launch_bounds__(256) k_vn_kgrad(VnArgs a) {
 }
 
 // RBF-weight gradients: dw_ij = -sum_p Kg_i[p] exp(-(s_i[p] - mu_j)^2 / (2 sigma^2)).
-// One workgroup per (band, slice); thread t < 24 * 31 owns (i, j).  A chunk
-// of up to 256 columns is staged filter-major ([24][260], zero-padded to a
-// multiple of 4 columns) so that a thread reads four pixels per float4.
+// One workgroup per (band, slice).  The knots go in the groups of 8 of the
+// activation (F Q^k D_k per knot): thread t takes filter i and group g
+// (t % 96) on pixel lane t / 96 (every eighth pixel of a chunk), sums
+// Kg F Q^k for its 8 knots with two exponentials per pixel, and the 8
+// lanes are added in order at the end; D_k multiplies the sums.  A chunk of
+// up to 256 columns is staged filter-major ([24][260]).
 constexpr int VWC = 256;      // columns per chunk
 constexpr int VWS = VWC + 4;  // LDS row stride (floats)
+constexpr int VW_PAIRS = VN_NK * VN_NG;  // (filter, group) pairs
+constexpr int VW_LANES = 8;              // pixel lanes
+static_assert(VW_PAIRS * VW_LANES == 768 && VW_PAIRS * VN_GK * VW_LANES <= VN_NK * VWS, "wgrad layout");
 __global__ void __launch_bounds__(768) k_vn_wgrad(VnArgs a) {
-  __shared__ __attribute__((aligned(16))) float sv[VN_NK * VWS];
-  __shared__ __attribute__((aligned(16))) float gv[VN_NK * VWS];
+  __shared__ float sv[VN_NK * VWS];  // (reused for the lane sums at the end)
+  __shared__ float gv[VN_NK * VWS];
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
   float* part = a.part_w + (int64_t)wg * (VN_NK * VN_NW);
   const int b = a.slices[blockIdx.y];
   const SliceDesc d = a.desc[b];
   const int H = d.H, W = d.W;
-  const int t = threadIdx.x, i = t / VN_NW, j = t % VN_NW;
-  const float mu = -1.0f + (2.0f / (VN_NW - 1)) * (float)j;
-  constexpr float C2 = VN_INV2S2 * 1.44269504088896341f;  // exp(-z / (2 sigma^2)) = 2^(-z c)
-  float acc = 0.f;
+  const int t = threadIdx.x, pl = t / VW_PAIRS, ig = t % VW_PAIRS;
+  const int i = ig / VN_NG, g = ig % VN_NG;
+  const float m = -1.0f + (VN_GK * g + 0.5f * (VN_GK - 1)) * VN_SIG;
+  constexpr float KF = -VN_INV2S2 * VN_LOG2E;
+  constexpr float KQ = 2.0f * VN_INV2S2 * VN_SIG * VN_LOG2E;
+  constexpr float SPAN = (VN_GK - 1) * VN_SIG;
+  float acc[VN_GK];
+#pragma unroll
+  for (int k = 0; k < VN_GK; ++k) acc[k] = 0.f;
   for (int rr = 0; rr < VN_BAND; ++rr) {
     const int row = blockIdx.x * VN_BAND + rr;
     if (row >= H) break;
     for (int c0 = 0; c0 < W; c0 += VWC) {
-      const int cw = min(VWC, W - c0), cw4 = (cw + 3) & ~3;
+      const int cw = min(VWC, W - c0);
       __syncthreads();
-      for (int q = t; q < cw4 * VN_NK; q += 768) {
+      for (int q = t; q < cw * VN_NK; q += 768) {
         const int c = q / VN_NK, ii = q % VN_NK;
-        float sval = 0.f, gval = 0.f;  // padding columns add Kg = 0
-        if (c < cw) {
-          const int64_t o = (d.xoff + (int64_t)row * W + c0) * VN_NK + q;
-          sval = a.s[o];
-          gval = a.kg[o];
-        }
-        sv[ii * VWS + c] = sval;
-        gv[ii * VWS + c] = gval;
+        const int64_t o = (d.xoff + (int64_t)row * W + c0) * VN_NK + q;
+        sv[ii * VWS + c] = a.s[o];
+        gv[ii * VWS + c] = a.kg[o];
       }
       __syncthreads();
-      if (t < VN_NK * VN_NW) {
-        const float4* s4 = (const float4*)&sv[i * VWS];
-        const float4* g4 = (const float4*)&gv[i * VWS];
-        for (int c = 0; c < cw4 / 4; ++c) {
-          const float4 sq = s4[c], gq = g4[c];
-          const float ss[4] = {sq.x, sq.y, sq.z, sq.w}, gg[4] = {gq.x, gq.y, gq.z, gq.w};
+      for (int c = pl; c < cw; c += VW_LANES) {
+        const float u = fminf(fmaxf(sv[i * VWS + c] - m, -VN_UC), VN_UC);
+        const float F = __builtin_amdgcn_exp2f((u * KF) * (u + SPAN));
+        const float Q = __builtin_amdgcn_exp2f(u * KQ);
+        float tt = gv[i * VWS + c] * F;
+        acc[0] += tt;
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const float dd = ss[m] - mu;
-            acc = fmaf(gg[m], __builtin_amdgcn_exp2f(-(dd * C2) * dd), acc);
-          }
+        for (int k = 1; k < VN_GK; ++k) {
+          tt *= Q;
+          acc[k] += tt;
         }
       }
     }
   }
-  if (t < VN_NK * VN_NW) part[t] = -acc;
+  __syncthreads();
+  float* red = sv;  // [lane][pair][8]
+#pragma unroll
+  for (int k = 0; k < VN_GK; ++k) red[(pl * VW_PAIRS + ig) * VN_GK + k] = acc[k];
+  __syncthreads();
+  if (t < VN_NK * VN_NW) {
+    const int fi = t / VN_NW, j = t % VN_NW, gg = j / VN_GK, k = j % VN_GK;
+    float sum = 0.f;
+    for (int l = 0; l < VW_LANES; ++l) sum += red[(l * VW_PAIRS + fi * VN_NG + gg) * VN_GK + k];
+    const double dk = (double)k - 0.5 * (VN_GK - 1);
+    const float Dk = (float)exp(-(double)VN_INV2S2 * (double)VN_SIG * (double)VN_SIG * dk * dk);
+    part[t] = -Dk * sum;
+  }
 }
 
 // out[i] (+)= sum_s part[s][i] in a fixed order: a block takes 64 entries;
