@@ -182,6 +182,8 @@ hipError_t for_groups(mrx_plan_s* p, hipStream_t s, F fn) {
 
 mrx_status sense_adj_impl(mrx_plan_s* p, const float2* y, const float2* S, const float* mask, float2* x,
                           hipStream_t s);
+hipError_t normal_group(mrx_plan_s* p, mrx::Group& g, const float2* x, const float2* S, const float* mask,
+                        const float* lam, float2* out, hipStream_t s);
 mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
                        float2* out, hipStream_t s);
 mrx_status cg_impl(mrx_plan_s* p, const float2* aHy, const float2* z, const float2* S, const float* mask,

@@ -38,17 +38,12 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
         if (use_cg)
           return cg_impl(p, (const float2*)a, nullptr, (const float2*)S, mask, nullptr, 4, (float2*)b, nullptr, s) ==
                  MRX_OK;
-        NormalArgs na{};
-        na.desc = p->d_desc;
-        na.slices = g.d_slices;
-        na.nslices = (int)g.slices.size();
-        na.S = (const float2*)S;
-        na.mask = mask;
-        na.pin = (const float2*)a;
-        na.qout = (float2*)b;
-        na.tw = p->tw.at(g.H);
+        // the operator application as normal_impl runs it (with the
+        // schedule's coil split where the scratch allows)
         bool ok = true;
-        for (int it = 0; it < 5; ++it) ok = ok && v->normal(na, g.W, s) == hipSuccess;
+        for (int it = 0; it < 5; ++it)
+          ok = ok && normal_group(p, g, (const float2*)a, (const float2*)S, mask, nullptr, (float2*)b, s) ==
+                         hipSuccess;
         return ok;
       };
       if (!run()) continue;  // warm-up

@@ -1,4 +1,5 @@
 // Host-side sequencing of the SENSE and CG operators on the device.
+#include <algorithm>
 #include <chrono>
 #include <mutex>
 
@@ -111,23 +112,59 @@ static mrx_status toep_normal_impl(mrx_plan_s* p, const float2* x, const float2*
   return e == hipSuccess ? MRX_OK : hip_fail(e, "toeplitz normal operator");
 }
 
+// out = sum_{k < nparts} part[k qstride + .] over the slices of one launch,
+// in plane order (the order k_cg_update adds the planes of a CG step).
+__global__ void k_add_planes(const SliceDesc* desc, const int* slices, const float2* part, int nparts,
+                             int64_t qstride, float2* out) {
+  const SliceDesc d = desc[slices[blockIdx.y]];
+  const int64_t n = (int64_t)d.H * d.W;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = d.xoff + i;
+    float2 v = part[o];
+    for (int k = 1; k < nparts; ++k) v = cadd(v, part[k * qstride + o]);
+    out[o] = v;
+  }
+}
+
+// One size group's operator application.  When the group's schedule splits
+// a column tile's coils over several workgroups (the CG-step split) and the
+// plan's coil-sized scratch holds that many image planes, the application
+// uses the split too -- a batch with few column tiles then fills the chip --
+// and a fixed-order sum adds the partial planes into out.
+hipError_t normal_group(mrx_plan_s* p, Group& g, const float2* x, const float2* S, const float* mask,
+                        const float* lam, float2* out, hipStream_t s) {
+  NormalArgs na{};
+  na.desc = p->d_desc;
+  na.slices = g.d_slices;
+  na.nslices = (int)g.slices.size();
+  na.S = S;
+  na.mask = mask;
+  na.lam = lam;
+  na.pin = x;
+  na.qout = out;
+  na.tw = p->tw.at(g.H);
+  na.mode = 0;
+  const int ks = g.col->kspl;
+  if (ks <= 1 || !p->ws || (int64_t)ks * p->n_image > p->n_coil) return g.col->normal(na, g.W, s);
+  float2* part = (float2*)(p->ws + p->ws_tmp);
+  na.qout = part;
+  na.qstride = p->n_image;
+  na.split_plain = 1;
+  hipError_t e = g.col->normal(na, g.W, s);
+  if (e != hipSuccess) return e;
+  const int64_t hw = (int64_t)g.H * g.W;
+  const unsigned blocks = (unsigned)std::min<int64_t>((hw + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_add_planes, dim3(blocks, (unsigned)g.slices.size()), dim3(256), 0, s, p->d_desc,
+                     g.d_slices, (const float2*)part, ks, p->n_image, out);
+  return hipGetLastError();
+}
+
 mrx_status normal_impl(mrx_plan_s* p, const float2* x, const float2* S, const float* mask, const float* lam,
                        float2* out, hipStream_t s) {
   if (p->toep) return toep_normal_impl(p, x, S, mask, lam, out, s);
   KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
   hipError_t e = for_groups(p, s, [&](Group& g, hipStream_t sg) {
-    NormalArgs na{};
-    na.desc = p->d_desc;
-    na.slices = g.d_slices;
-    na.nslices = (int)g.slices.size();
-    na.S = S;
-    na.mask = mask;
-    na.lam = lam;
-    na.pin = x;
-    na.qout = out;
-    na.tw = p->tw.at(g.H);
-    na.mode = 0;
-    return g.col->normal(na, g.W, sg);
+    return normal_group(p, g, x, S, mask, lam, out, sg);
   });
   return e == hipSuccess ? MRX_OK : hip_fail(e, "sense_normal");
 }

@@ -702,15 +702,18 @@ k_adj_row(SenseRowArgs a) {
 }
 
 // ------------------------------------------------------------- launchers
-// Operator applications (mode 0) run unsplit; CG steps (mode 1) split each
-// column tile's coils over KSPL workgroups writing partial planes that the CG
-// update adds (a.qstride apart; pin and pout must then differ).
+// CG steps (mode 1) split each column tile's coils over KSPL workgroups
+// writing partial planes that the CG update adds (a.qstride apart; pin and
+// pout must then differ); operator applications (mode 0) do the same when the
+// caller asks for it (split_plain, partial planes then added by the caller)
+// and otherwise run unsplit.
 template <class Sd, int WT, int G, bool KS, int KSPL>
 hipError_t launch_normal(const NormalArgs& a0, int maxW, hipStream_t s) {
   NormalArgs a = a0;
   a.tiles = (maxW + WT - 1) / WT;
-  if (a.mode == 1 && KSPL > 1) {
-    if (a.tiles * KSPL > a.npq || (a.iter > 0 && a.pin == a.pout)) return hipErrorInvalidValue;
+  if ((a.mode == 1 || a.split_plain) && KSPL > 1) {
+    if (a.mode == 1 && (a.tiles * KSPL > a.npq || (a.iter > 0 && a.pin == a.pout))) return hipErrorInvalidValue;
+    if (a.qstride <= 0) return hipErrorInvalidValue;
     const int total = a.tiles * a.nslices * KSPL;
     dim3 grid((unsigned)(((total + 15) / 16) * 16));
     hipLaunchKernelGGL((k_normal<Sd, WT, G, KS, KSPL>), grid, dim3(Sd::T * WT * G), 0, s, a);

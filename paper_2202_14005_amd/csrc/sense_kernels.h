@@ -37,7 +37,11 @@ struct NormalArgs {
   int npq;
   const int* stopped;      // [B] per-slice stop flag (CG breakdown)
   int tiles;               // column tiles per slice (set by the launcher)
-  int64_t qstride;         // CG mode: distance between the partial output planes
+  int64_t qstride;         // distance between the partial output planes (CG mode, or split_plain)
+  // Operator application (mode 0) split like a CG step: a column tile's
+  // coils over the schedule's KSPL workgroups, each writing its partial
+  // plane at qout + k qstride (the first adds lambda p); the caller adds them.
+  int split_plain;
 };
 
 struct SenseColArgs {

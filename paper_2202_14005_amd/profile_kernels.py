@@ -106,6 +106,7 @@ def main():
         vp = ops.Plan(vH, vW, C, B=vB, device=dev, network=True, vn=True)
         vx, vS, vm = t(vd["x"]), t(vd["S"]), t(vd["mask"])
         vy = vp.sense_fwd(vx, vS, vm, noise=t(vd["noise"]))
+        vp.autotune(vS, vm)  # as the benchmark's leg does
         vnet = ops.VarNet.init(vp, seed=1, T=10)
         for _ in range(a.reps):
             vaHy = vp.sense_adj(vy, vS, vm)
@@ -113,6 +114,7 @@ def main():
             _, vg = vp.mse_grad(vxT, vx)
             vnet.backward(vg, vst, vaHy, vS, vm)
         torch.cuda.synchronize()
+        print("vn schedule:", vp.schedule(0), flush=True)
         del vd, vp, vnet, vst
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
     dst = torch.empty_like(src)
