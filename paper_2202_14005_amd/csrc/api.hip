@@ -250,12 +250,12 @@ mrx_status mrx_plan_create(mrx_plan* out, int32_t B, const int32_t* H, const int
   off += align256(sizeof(SliceDesc) * B);
   {
     // the CG element kernels' view of a slice: sets x H x W entries at
-    // sets x xoff, no partial planes
+    // sets x xoff, and the soft normal operator's partial planes
     std::vector<SliceDesc> dv(p->desc);
     for (auto& d : dv) {
       d.H *= p->sets;
       d.xoff *= p->sets;
-      d.nq = 1;
+      d.nq = SOFT_KSPL;
     }
     std::memcpy(host.data() + off, dv.data(), sizeof(SliceDesc) * B);
     p->d_desc_soft = (SliceDesc*)((char*)p->d_tables + off);

@@ -7,7 +7,7 @@
 
 namespace mrx {
 
-static_assert(KSPL_MAX <= CG_QPARTS_MAX, "k_cg_update must add every partial plane");
+static_assert(KSPL_MAX <= CG_QPARTS_MAX && SOFT_KSPL <= CG_QPARTS_MAX, "k_cg_update must add every partial plane");
 
 __global__ void k_fill_u32(uint32_t* d, uint32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -242,7 +242,9 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
   a.r = r;
   a.p = pv;
   a.q = q;
-  a.qstride = p->n_image;
+  // partial planes of a coil split hold every coil-map set
+  const int64_t qstride = p->n_image * (soft ? p->sets : 1);
+  a.qstride = qstride;
   a.pq = pq;
   a.hist = hist;
   a.rr_next = rr[0];
@@ -291,7 +293,7 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
         na.lam = lam;
         na.pin = pb[k == 0 ? 0 : ((k - 1) & 1)];
         na.qout = q;
-        na.qstride = p->n_image;
+        na.qstride = qstride;
         na.tw = p->tw.at(g.H);
         na.mode = 1;
         na.iter = k;

@@ -79,6 +79,7 @@ struct ColVariant {
   int kspl = 1;  // CG mode: workgroups per column tile (coil split), partial planes written
 };
 constexpr int KSPL_MAX = 4;
+constexpr int SOFT_KSPL = 3;  // soft-SENSE CG steps: workgroups per column tile (coil split)
 struct RowVariant {
   int N, N1, N2, N3, T, WT;
   RowFn fwd_row;

@@ -151,8 +151,12 @@ k_adj_col_soft(SenseColArgs a) {
 // fly from pin and r (beta = rho_k / rho_{k-1} from the rr partials) and
 // written to pout, and the tile's Re<p, q> partial written to pq_part.  The
 // operand is re-read for every coil (it is L2-resident) so that only the
-// two accumulators and the transform stay in registers.
-template <class Sd, int WT>
+// two accumulators and the transform stay in registers.  KSPL > 1 (CG
+// steps): a column tile's coils are split over KSPL workgroups, each writing
+// its partial planes (both sets) at qout + k qstride and its own Re<p, q>
+// partial; the first adds lambda p and writes pout; the CG update adds the
+// planes.
+template <class Sd, int WT, int KSPL>
 __global__ void __launch_bounds__(Sd::T * WT, 2)
 k_normal_soft(NormalArgs a) {
   constexpr int N = Sd::N, P = Sd::P, T = Sd::T, NT = T * WT;
@@ -166,8 +170,9 @@ k_normal_soft(NormalArgs a) {
   const int b = a.slices[blockIdx.y];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
-  const int W = d.W, tile = blockIdx.x;
+  const int W = d.W, tile = blockIdx.x / KSPL, ks = blockIdx.x % KSPL;
   if (tile * WT >= W) return;
+  const int c_begin = (ks * d.C) / KSPL, c_end = ((ks + 1) * d.C) / KSPL;
   const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
   const bool valid = col < W;
   const uint32_t voff = (uint32_t)(tc * W + (valid ? col : W - 1)) * 8u;
@@ -201,7 +206,7 @@ k_normal_soft(NormalArgs a) {
     const float2 rv = rr.ld(voff, s);
     return make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
   };
-  if (cg && valid) {
+  if (cg && valid && ks == 0) {
     const BufPlane pout0(a.pout + xo, pbytes), pout1(a.pout + xo + plane, pbytes);
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
@@ -215,7 +220,7 @@ k_normal_soft(NormalArgs a) {
 #pragma unroll
   for (int k = 0; k < P; ++k) acc0[k] = acc1[k] = make_float2(0.f, 0.f);
   const float2* Sb = a.S + 2 * d.soff;
-  for (int coil = 0; coil < d.C; ++coil) {
+  for (int coil = c_begin; coil < c_end; ++coil) {
     const BufPlane S0(Sb + coil * plane, pbytes), S1(Sb + (d.C + coil) * plane, pbytes);
     float2 v[P];
 #pragma unroll
@@ -237,8 +242,9 @@ k_normal_soft(NormalArgs a) {
         acc1[k] = cadd(acc1[k], cmulc(S1.ld_nt(voff, so(i, r)), v[k]));
       }
   }
-  const float lam = a.lam ? a.lam[b] : 0.f;
-  const BufPlane q0(a.qout + xo, pbytes), q1(a.qout + xo + plane, pbytes);
+  const float lam = (a.lam && ks == 0) ? a.lam[b] : 0.f;
+  float2* qo = a.qout + (int64_t)ks * a.qstride;
+  const BufPlane q0(qo + xo, pbytes), q1(qo + xo + plane, pbytes);
   float dot = 0.f;
 #pragma unroll
   for (int i = 0; i < Sd::G1; ++i)
@@ -258,16 +264,25 @@ k_normal_soft(NormalArgs a) {
   if (!valid) dot = 0.f;
   if (cg) {
     const float s = block_sum_fixed(dot, red);
-    if (lid == 0) a.pq_part[(int64_t)b * a.npq + tile] = s;
+    if (lid == 0) a.pq_part[(int64_t)b * a.npq + tile * KSPL + ks] = s;
   }
 }
 
+// CG steps split each column tile's coils over SOFT_KSPL workgroups (partial
+// planes a.qstride apart, pin and pout distinct); operator applications run
+// unsplit.
 template <class Sd, int WT>
 hipError_t launch_normal_soft(const NormalArgs& a0, int maxW, hipStream_t s) {
   NormalArgs a = a0;
   a.tiles = (maxW + WT - 1) / WT;
-  if (a.mode == 1 && a.tiles > a.npq) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_normal_soft<Sd, WT>), dim3(a.tiles, a.nslices), dim3(Sd::T * WT), 0, s, a);
+  if (a.mode == 1) {
+    if (a.tiles * SOFT_KSPL > a.npq || a.qstride <= 0 || (a.iter > 0 && a.pin == a.pout))
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_normal_soft<Sd, WT, SOFT_KSPL>), dim3(a.tiles * SOFT_KSPL, a.nslices),
+                       dim3(Sd::T * WT), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_normal_soft<Sd, WT, 1>), dim3(a.tiles, a.nslices), dim3(Sd::T * WT), 0, s, a);
+  }
   return hipGetLastError();
 }
 template <class Sd, int WT>
