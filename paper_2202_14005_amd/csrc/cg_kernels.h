@@ -37,6 +37,10 @@ struct CgElemArgs {
   float* hist;
 };
 
+// p_out = r + beta p_in with beta = rho_k / rho_{k-1} from the rr partials
+// (0 when rho_{k-1} = 0), for the slices of a.slices that have not stopped
+// (a.p: p_in, a.x: p_out, a.rr_cur: rho_k, a.rr_next: rho_{k-1}).
+hipError_t cg_form_p(const CgElemArgs& a, hipStream_t s);
 hipError_t cg_init(const CgElemArgs& a, hipStream_t s);
 hipError_t cg_update(const CgElemArgs& a, hipStream_t s);
 hipError_t cg_hist(const CgElemArgs& a, int k, int stride, hipStream_t s);

@@ -163,6 +163,26 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_update(CgElemArgs a) {
   if (threadIdx.x == 0) a.rr_next[(int64_t)b * a.nrr + blockIdx.x] = s;
 }
 
+// The search direction of a CG step, formed once for an operator that
+// then reads it as given (p_out = r + beta p_in; see cg_kernels.h).
+__global__ void __launch_bounds__(CG_THREADS) k_cg_form_p(CgElemArgs a) {
+  const int b = a.slices[blockIdx.y];
+  const SliceDesc d = a.desc[b];
+  const int64_t n = (int64_t)d.H * d.W;
+  const float rc = psum(a.rr_cur + (int64_t)b * a.nrr, a.nrr);
+  const float rp = psum(a.rr_next + (int64_t)b * a.nrr, a.nrr);
+  if (a.stopped[b]) return;
+  const float beta = rp > 0.f ? rc / rp : 0.f;
+  const int64_t base = (int64_t)blockIdx.x * CG_EPB;
+  for (int k = threadIdx.x; k < CG_EPB; k += CG_THREADS) {
+    const int64_t i = base + k;
+    if (i >= n) break;
+    const int64_t o = d.xoff + i;
+    const float2 rv = a.r[o], pv = a.p[o];
+    a.x[o] = make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
+  }
+}
+
 // hist[b][k] = rho_k (sum of the current partials).
 __global__ void __launch_bounds__(CG_THREADS) k_cg_hist(CgElemArgs a, int k, int stride) {
   const int b = a.slices[blockIdx.y];
@@ -206,6 +226,10 @@ __global__ void __launch_bounds__(CG_THREADS) k_slice_sum(CgElemArgs a, const fl
 
 hipError_t cg_init(const CgElemArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_init, dim3(a.nrr, a.nslices), dim3(CG_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t cg_form_p(const CgElemArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_form_p, dim3(a.nrr, a.nslices), dim3(CG_THREADS), 0, s, a);
   return hipGetLastError();
 }
 hipError_t cg_update(const CgElemArgs& a, hipStream_t s) {

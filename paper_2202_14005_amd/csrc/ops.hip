@@ -260,6 +260,18 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
       e = cg_hist(a, k, n_iter + 1, s);
       if (e != hipSuccess) return hip_fail(e, "cg: history");
     }
+    // soft-SENSE: p_k = r_k + beta p_{k-1} formed once, which the operator
+    // then reads as given (instead of forming it for every coil and set)
+    const bool soft_form = soft && k > 0;
+    if (soft_form) {
+      CgElemArgs fa = a;
+      fa.rr_cur = rr_cur;
+      fa.rr_next = rr_prev;
+      fa.p = pb[(k - 1) & 1];
+      fa.x = pb[k & 1];
+      e = cg_form_p(fa, s);
+      if (e != hipSuccess) return hip_fail(e, "cg: search direction");
+    }
     {
       KernelTimer kt(p, MRX_KERNEL_NORMAL, s);
       e = for_groups(p, s, [&](Group& g, hipStream_t sg) {
@@ -291,14 +303,14 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
         na.S = S;
         na.mask = mask;
         na.lam = lam;
-        na.pin = pb[k == 0 ? 0 : ((k - 1) & 1)];
+        na.pin = soft_form ? pb[k & 1] : pb[k == 0 ? 0 : ((k - 1) & 1)];
         na.qout = q;
         na.qstride = qstride;
         na.tw = p->tw.at(g.H);
         na.mode = 1;
-        na.iter = k;
+        na.iter = soft_form ? 0 : k;
         na.r = r;
-        na.pout = pb[k & 1];
+        na.pout = soft_form ? nullptr : pb[k & 1];
         na.rr_cur = rr_cur;
         na.rr_prev = rr_prev;
         na.nrr = p->nrr;

@@ -149,7 +149,8 @@ k_adj_col_soft(SenseColArgs a) {
 // workgroup = WT columns of one slice (2-D grid: column tiles x slices of
 // the launch).  Mode 1 (CG step, as k_normal): p = r + beta p formed on the
 // fly from pin and r (beta = rho_k / rho_{k-1} from the rr partials) and
-// written to pout, and the tile's Re<p, q> partial written to pq_part.  The
+// written to pout (pout null: p given as pin, nothing written), and the
+// tile's Re<p, q> partial written to pq_part.  The
 // operand is re-read for every coil (it is L2-resident) so that only the
 // two accumulators and the transform stay in registers.  KSPL > 1 (CG
 // steps): a column tile's coils are split over KSPL workgroups, each writing
@@ -206,7 +207,7 @@ k_normal_soft(NormalArgs a) {
     const float2 rv = rr.ld(voff, s);
     return make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
   };
-  if (cg && valid && ks == 0) {
+  if (cg && valid && ks == 0 && a.pout) {
     const BufPlane pout0(a.pout + xo, pbytes), pout1(a.pout + xo + plane, pbytes);
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
