@@ -169,6 +169,36 @@ def test_uneven_batch_matches_oracle_per_slice():
         so += nc
 
 
+def test_uneven_batch_split_operator_matches_oracle():
+    """The operator applications of an uneven batch under coil-split
+    schedules: every size group with a split schedule writes its partial
+    planes (one group has fewer coils than splits), the 128^2 group has no
+    split schedule and runs unsplit, and a fixed-order sum adds the planes;
+    the normal operator and the CG solve per slice against the oracle."""
+    from paper_2202_14005_amd import ops
+    shapes = [(192, 192, 10), (320, 320, 15), (384, 320, 12), (128, 128, 3), (256, 256, 2)]
+    sl, pk = uneven(shapes, seed0=5100)
+    plan = Plan([s[0] for s in shapes], [s[1] for s in shapes], [s[2] for s in shapes])
+    for H in (192, 256, 320, 384):
+        name = [n for n in ops.schedules(H) if n.endswith("_w16_k3")][0]
+        plan.set_schedule(H, name)
+    lam = np.array([0.05] * len(shapes), dtype=np.float32)
+    x, S, m = dev(pk["x"]), dev(pk["S"]), dev(pk["mask"])
+    q = host(plan.sense_normal(x, S, m, torch.tensor(lam)))
+    a = host(plan.sense_adj(plan.sense_fwd(x, S, m, noise=dev(pk["noise"])), S, m))
+    xs = host(plan.cg_dc(dev(a), S, m, torch.tensor(lam), 10))
+    xo = 0
+    for (H, W, C), s in zip(shapes, sl):
+        ni = H * W
+        args = (s["x"][None], s["S"][None], s["mask"][None])
+        e_q = rel(q[xo:xo + ni], osense.sense_normal(*args, [0.05]))
+        xref, _ = ocg.cg_dc(a[xo:xo + ni].reshape(1, H, W), None, s["S"][None], s["mask"][None], [0.05], 10)
+        e_x = rel(xs[xo:xo + ni], xref)
+        print(f"{H}x{W}x{C} ({plan.schedule(shapes.index((H, W, C)))}): normal {e_q:.1e} cg {e_x:.1e}")
+        assert e_q < OP_TOL and e_x < CG_TOL
+        xo += ni
+
+
 def test_bitwise_reproducible():
     H, W, C = 320, 320, 15
     d = case_inputs(H, W, C, "vd")

@@ -33,8 +33,11 @@ def case(B, H, W, C, seed):
     return d
 
 
-@pytest.mark.parametrize("B,H,W,C", [(2, 48, 40, 4), (1, 96, 80, 6), (8, 320, 320, 15), (1, 240, 288, 5)])
+@pytest.mark.parametrize("B,H,W,C", [(2, 48, 40, 4), (1, 96, 80, 6), (8, 320, 320, 15), (1, 240, 288, 5),
+                                     (2, 48, 40, 1), (1, 48, 40, 2)])
 def test_soft_operators_and_cg(B, H, W, C):
+    """The CG steps split each column tile's coils over three workgroups:
+    with one or two coils some of them get none."""
     d = case(B, H, W, C, 11000)
     x, S, m = d["x"], d["S"], d["mask"]
     plan = ops.Plan(H, W, C, B=B, soft=True)
