@@ -217,6 +217,12 @@ def _jobs():
     for s in srcs:
         jobs.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".hip", ".o")), []))
     soft_done = set()
+    # the soft normal operator takes 16-column tiles (whole 128-byte rows of
+    # the coil maps and images) where the length has a 16-column schedule on
+    # the same decomposition; the soft column passes keep the first
+    # schedule's tile
+    wide = {(e[1], e[2], e[3], e[4]) for e in SCHEDULES
+            if e[5] == 16 and not (e[9] if len(e) > 9 else 0)}
     for entry in SCHEDULES:
         name, n1, n2, n3, t, wtc, wtr, g, ks = entry[:9]
         wl = entry[9] if len(entry) > 9 else 0
@@ -230,6 +236,8 @@ def _jobs():
         defs = [f"-DMRX_N1={n1}", f"-DMRX_N2={n2}", f"-DMRX_N3={n3}", f"-DMRX_T={t}",
                 f"-DMRX_WTC={wtc}", f"-DMRX_WTR={wtr}", f"-DMRX_G={g}", f"-DMRX_KS={ks}",
                 f"-DMRX_WL={wl}", f"-DMRX_KSPL={kspl}", f"-DMRX_SOFT={soft}", f'-DMRX_NAME="{name}"']
+        if soft and wtc < 16 and (n1, n2, n3, t) in wide:
+            defs.append("-DMRX_SOFT_WTN=16")
         jobs.append((os.path.join(CSRC, "sense_inst.hip"), os.path.join(BUILD, f"sched_{name}.o"), defs))
     for name, n2, n3, t, twr, twc in TOEP_SCHEDULES:
         defs = [f"-DMRX_N2={n2}", f"-DMRX_N3={n3}", f"-DMRX_T={t}", f"-DMRX_TWR={twr}", f"-DMRX_TWC={twc}",

@@ -212,7 +212,22 @@ mrx_status soft_normal_impl(mrx_plan_s* p, const float2* x, const float2* S, con
     na.qout = out;
     na.tw = p->tw.at(g.H);
     na.mode = 0;
-    return g.soft->normal(na, g.W, sg);
+    // split like a CG step when the coil-sized scratch holds the partial
+    // planes of both sets (the few column tiles of a batch then fill the
+    // chip); a fixed-order sum adds them into out
+    const int64_t simg = p->n_image * p->sets;
+    if (!p->ws || SOFT_KSPL * simg > p->n_coil) return g.soft->normal(na, g.W, sg);
+    float2* part = (float2*)(p->ws + p->ws_tmp);
+    na.qout = part;
+    na.qstride = simg;
+    na.split_plain = 1;
+    hipError_t e2 = g.soft->normal(na, g.W, sg);
+    if (e2 != hipSuccess) return e2;
+    const int64_t n = (int64_t)p->sets * g.H * g.W;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_add_planes, dim3(blocks, (unsigned)g.slices.size()), dim3(256), 0, sg, p->d_desc_soft,
+                       g.d_slices, (const float2*)part, SOFT_KSPL, simg, out);
+    return hipGetLastError();
   });
   return e == hipSuccess ? MRX_OK : hip_fail(e, "soft_sense_normal");
 }
@@ -303,14 +318,15 @@ mrx_status cg_impl(mrx_plan_s* p, const CgBufs& bb, const float2* aHy, const flo
         na.S = S;
         na.mask = mask;
         na.lam = lam;
-        na.pin = soft_form ? pb[k & 1] : pb[k == 0 ? 0 : ((k - 1) & 1)];
+        // (soft: p_0 = r_0 from the initialisation, later p_k formed above)
+        na.pin = soft ? pb[k & 1] : pb[k == 0 ? 0 : ((k - 1) & 1)];
         na.qout = q;
         na.qstride = qstride;
         na.tw = p->tw.at(g.H);
         na.mode = 1;
-        na.iter = soft_form ? 0 : k;
+        na.iter = soft ? 0 : k;
         na.r = r;
-        na.pout = soft_form ? nullptr : pb[k & 1];
+        na.pout = soft ? nullptr : pb[k & 1];
         na.rr_cur = rr_cur;
         na.rr_prev = rr_prev;
         na.nrr = p->nrr;

@@ -147,16 +147,14 @@ k_adj_col_soft(SenseColArgs a) {
 // maps: per coil v = S_{0,c} p_0 + S_{1,c} p_1, transform along H, mask,
 // inverse transform, q_m += conj(S_{m,c}) v; q_m += lambda p_m.  One
 // workgroup = WT columns of one slice (2-D grid: column tiles x slices of
-// the launch).  Mode 1 (CG step, as k_normal): p = r + beta p formed on the
-// fly from pin and r (beta = rho_k / rho_{k-1} from the rr partials) and
-// written to pout (pout null: p given as pin, nothing written), and the
-// tile's Re<p, q> partial written to pq_part.  The
-// operand is re-read for every coil (it is L2-resident) so that only the
-// two accumulators and the transform stay in registers.  KSPL > 1 (CG
-// steps): a column tile's coils are split over KSPL workgroups, each writing
-// its partial planes (both sets) at qout + k qstride and its own Re<p, q>
-// partial; the first adds lambda p and writes pout; the CG update adds the
-// planes.
+// the launch).  Mode 1 (CG step): p is given as pin (the CG step forms
+// p = r + beta p beforehand, once for both sets) and the tile's Re<p, q>
+// partial goes to pq_part.  The operand is re-read for every coil (it is
+// L2-resident) so that only the two accumulators and the transform stay in
+// registers.  KSPL > 1 (CG steps): a column tile's coils are split over
+// KSPL workgroups, each writing its partial planes (both sets) at
+// qout + k qstride and its own Re<p, q> partial; the first adds lambda p;
+// the CG update adds the planes.
 template <class Sd, int WT, int KSPL>
 __global__ void __launch_bounds__(Sd::T * WT, 2)
 k_normal_soft(NormalArgs a) {
@@ -167,7 +165,6 @@ k_normal_soft(NormalArgs a) {
   __shared__ float2 tw[N];
   __shared__ float mk[N];
   __shared__ float red[NT / 64];
-  __shared__ float sc[1];
   const int b = a.slices[blockIdx.y];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
@@ -185,38 +182,10 @@ k_normal_soft(NormalArgs a) {
     tw[i] = a.tw[i];
     mk[i] = a.mask[d.moff + (i + N / 2) % N] * (1.0f / N);
   }
-  if (lid < 64) {
-    float beta = 0.f;
-    if (cg && a.iter > 0) {
-      const float rc = wave_sum_fixed(a.rr_cur + (int64_t)b * a.nrr, a.nrr, lid);
-      const float rp = wave_sum_fixed(a.rr_prev + (int64_t)b * a.nrr, a.nrr, lid);
-      beta = rp > 0.f ? rc / rp : 0.f;
-    }
-    if (lid == 0) sc[0] = beta;
-  }
   __syncthreads();
   const int64_t plane = (int64_t)N * W;
   const int64_t xo = 2 * d.xoff;
-  const bool upd = cg && a.iter > 0;
-  const float beta = sc[0];
   const BufPlane pin0(a.pin + xo, pbytes), pin1(a.pin + xo + plane, pbytes);
-  const BufPlane rin0(upd ? a.r + xo : a.pin + xo, pbytes), rin1(upd ? a.r + xo + plane : a.pin + xo + plane, pbytes);
-  auto pval = [&](const BufPlane& pp, const BufPlane& rr, uint32_t s) {
-    const float2 pv = pp.ld(voff, s);
-    if (!upd) return pv;
-    const float2 rv = rr.ld(voff, s);
-    return make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
-  };
-  if (cg && valid && ks == 0 && a.pout) {
-    const BufPlane pout0(a.pout + xo, pbytes), pout1(a.pout + xo + plane, pbytes);
-#pragma unroll
-    for (int i = 0; i < Sd::G1; ++i)
-#pragma unroll
-      for (int r = 0; r < Sd::N1; ++r) {
-        pout0.st(pval(pin0, rin0, so(i, r)), voff, so(i, r));
-        pout1.st(pval(pin1, rin1, so(i, r)), voff, so(i, r));
-      }
-  }
   float2 acc0[P], acc1[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) acc0[k] = acc1[k] = make_float2(0.f, 0.f);
@@ -229,7 +198,7 @@ k_normal_soft(NormalArgs a) {
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
         const uint32_t s = so(i, r);
-        v[i * Sd::N1 + r] = cadd(cmul(S0.ld(voff, s), pval(pin0, rin0, s)), cmul(S1.ld(voff, s), pval(pin1, rin1, s)));
+        v[i * Sd::N1 + r] = cadd(cmul(S0.ld(voff, s), pin0.ld(voff, s)), cmul(S1.ld(voff, s), pin1.ld(voff, s)));
       }
     // the tile region sees only alternating forward and inverse transforms
     fft_forward<Sd, L, BlockSyncPost>(v, lds, tw, tc, c);
@@ -253,7 +222,7 @@ k_normal_soft(NormalArgs a) {
     for (int r = 0; r < Sd::N1; ++r) {
       const int k = i * Sd::N1 + r;
       const uint32_t s = so(i, r);
-      const float2 p0 = pval(pin0, rin0, s), p1 = pval(pin1, rin1, s);
+      const float2 p0 = pin0.ld(voff, s), p1 = pin1.ld(voff, s);
       const float2 u0 = make_float2(acc0[k].x + lam * p0.x, acc0[k].y + lam * p0.y);
       const float2 u1 = make_float2(acc1[k].x + lam * p1.x, acc1[k].y + lam * p1.y);
       dot += p0.x * u0.x + p0.y * u0.y + p1.x * u1.x + p1.y * u1.y;
@@ -270,15 +239,17 @@ k_normal_soft(NormalArgs a) {
 }
 
 // CG steps split each column tile's coils over SOFT_KSPL workgroups (partial
-// planes a.qstride apart, pin and pout distinct); operator applications run
-// unsplit.
+// planes a.qstride apart; p given, so iter 0 and no pout); operator
+// applications too when split_plain is set (the caller adds the planes),
+// else unsplit.
 template <class Sd, int WT>
 hipError_t launch_normal_soft(const NormalArgs& a0, int maxW, hipStream_t s) {
   NormalArgs a = a0;
   a.tiles = (maxW + WT - 1) / WT;
-  if (a.mode == 1) {
-    if (a.tiles * SOFT_KSPL > a.npq || a.qstride <= 0 || (a.iter > 0 && a.pin == a.pout))
-      return hipErrorInvalidValue;
+  if (a.mode == 1 || a.split_plain) {
+    if (a.qstride <= 0) return hipErrorInvalidValue;
+    // p is given (pin): the kernel neither forms nor writes it
+    if (a.mode == 1 && (a.tiles * SOFT_KSPL > a.npq || a.iter != 0 || a.pout)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_normal_soft<Sd, WT, SOFT_KSPL>), dim3(a.tiles * SOFT_KSPL, a.nslices),
                        dim3(Sd::T * WT), 0, s, a);
   } else {
@@ -297,12 +268,13 @@ hipError_t launch_adj_col_soft(const SenseColArgs& a, int maxW, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Registers the soft-SENSE kernels of one length (built for each length's
-// default schedule).
-template <class Sd, int WT>
+// Registers the soft-SENSE kernels of one length (built on the length's
+// default decomposition): the normal operator on WTN-column tiles, the
+// column passes on WTC-column tiles.
+template <class Sd, int WTN, int WTC>
 struct RegistrarSoft {
   RegistrarSoft(const char* name) {
-    SoftVariant v{Sd::N, &launch_normal_soft<Sd, WT>, &launch_fwd_col_soft<Sd, WT>, &launch_adj_col_soft<Sd, WT>,
+    SoftVariant v{Sd::N, &launch_normal_soft<Sd, WTN>, &launch_fwd_col_soft<Sd, WTC>, &launch_adj_col_soft<Sd, WTC>,
                   name};
     register_soft_variant(v);
   }

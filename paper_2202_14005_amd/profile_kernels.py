@@ -22,7 +22,10 @@ kernel traces, ``copy`` a device-to-device
 copy of 256 MiB (256 MiB read, 256 MiB written) whose counter readings
 calibrate FETCH_SIZE and WRITE_SIZE, ``vn`` ``reps`` forward and reverse
 passes of the variational network (10 stages, 4 slices of 384 x 320, 15
-coils).
+coils), ``soft`` one soft-SENSE CG solve of ``reps`` iterations (two coil-map
+sets, 8 slices of 320 x 320, 15 coils: one search-direction kernel, one
+CG-fused k_normal_soft launch with its coil split and one CG update per
+iteration).
 """
 from __future__ import annotations
 
@@ -116,6 +119,18 @@ def main():
         torch.cuda.synchronize()
         print("vn schedule:", vp.schedule(0), flush=True)
         del vd, vp, vnet, vst
+    if "soft" in what:
+        from synthetic import soft_batch_inputs
+        sd = soft_batch_inputs([2050 + i for i in range(B)], H, W, C, 4, 24, "vd")
+        sp = ops.Plan(H, W, C, B=B, device=dev, soft=True)
+        sS, sm = t(sd["S"]), t(sd["mask"])
+        sy = sp.soft_sense_fwd(t(sd["x"]), sS, sm, noise=t(sd["noise"]))
+        saHy = sp.soft_sense_adj(sy, sS, sm)
+        del sd
+        torch.cuda.synchronize()
+        sp.soft_cg_dc(saHy, sS, sm, sp.lam(0.05), a.reps)
+        torch.cuda.synchronize()
+        print("soft schedule:", sp.schedule(0), flush=True)
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
