@@ -146,8 +146,7 @@ k_adj_col_soft(SenseColArgs a) {
 // Normal operator (A^H A + lambda I) p on both sets, one pass over the coil
 // maps: per coil v = S_{0,c} p_0 + S_{1,c} p_1, transform along H, mask,
 // inverse transform, q_m += conj(S_{m,c}) v; q_m += lambda p_m.  One
-// workgroup = WT columns of one slice (2-D grid: column tiles x slices of
-// the launch).  Mode 1 (CG step): p is given as pin (the CG step forms
+// workgroup = WT columns of one slice.  Mode 1 (CG step): p is given as pin (the CG step forms
 // p = r + beta p beforehand, once for both sets) and the tile's Re<p, q>
 // partial goes to pq_part.  The operand is re-read for every coil (it is
 // L2-resident) so that only the two accumulators and the transform stay in
@@ -165,10 +164,17 @@ k_normal_soft(NormalArgs a) {
   __shared__ float2 tw[N];
   __shared__ float mk[N];
   __shared__ float red[NT / 64];
-  const int b = a.slices[blockIdx.y];
+  // workgroup -> (slice, column tile, coil split): consecutive workgroups
+  // go to the 8 XCDs in turn, so the KSPL splits of a (slice, tile) unit,
+  // 8 workgroups apart, run on one XCD and share the operand in its L2
+  const int Lb = blockIdx.x;
+  const int unit = (Lb / (8 * KSPL)) * 8 + (Lb & 7), ks = (Lb >> 3) % KSPL;
+  const int si = unit / a.tiles, tile = unit % a.tiles;
+  if (si >= a.nslices) return;
+  const int b = a.slices[si];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
-  const int W = d.W, tile = blockIdx.x / KSPL, ks = blockIdx.x % KSPL;
+  const int W = d.W;
   if (tile * WT >= W) return;
   const int c_begin = (ks * d.C) / KSPL, c_end = ((ks + 1) * d.C) / KSPL;
   const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
@@ -198,7 +204,9 @@ k_normal_soft(NormalArgs a) {
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
         const uint32_t s = so(i, r);
-        v[i * Sd::N1 + r] = cadd(cmul(S0.ld(voff, s), pin0.ld(voff, s)), cmul(S1.ld(voff, s), pin1.ld(voff, s)));
+        // the maps stream (non-temporal); the operand stays in L2 for the
+        // tile's other coils
+        v[i * Sd::N1 + r] = cadd(cmul(S0.ld_nt(voff, s), pin0.ld(voff, s)), cmul(S1.ld_nt(voff, s), pin1.ld(voff, s)));
       }
     // the tile region sees only alternating forward and inverse transforms
     fft_forward<Sd, L, BlockSyncPost>(v, lds, tw, tc, c);
@@ -250,10 +258,13 @@ hipError_t launch_normal_soft(const NormalArgs& a0, int maxW, hipStream_t s) {
     if (a.qstride <= 0) return hipErrorInvalidValue;
     // p is given (pin): the kernel neither forms nor writes it
     if (a.mode == 1 && (a.tiles * SOFT_KSPL > a.npq || a.iter != 0 || a.pout)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_normal_soft<Sd, WT, SOFT_KSPL>), dim3(a.tiles * SOFT_KSPL, a.nslices),
+    const int total = a.tiles * a.nslices * SOFT_KSPL, per = 8 * SOFT_KSPL;
+    hipLaunchKernelGGL((k_normal_soft<Sd, WT, SOFT_KSPL>), dim3((unsigned)(((total + per - 1) / per) * per)),
                        dim3(Sd::T * WT), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_normal_soft<Sd, WT, 1>), dim3(a.tiles, a.nslices), dim3(Sd::T * WT), 0, s, a);
+    const int total = a.tiles * a.nslices;
+    hipLaunchKernelGGL((k_normal_soft<Sd, WT, 1>), dim3((unsigned)(((total + 7) / 8) * 8)), dim3(Sd::T * WT), 0,
+                       s, a);
   }
   return hipGetLastError();
 }
