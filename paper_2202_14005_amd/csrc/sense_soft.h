@@ -13,14 +13,17 @@
 namespace mrx {
 
 // Forward column pass: v = S_{0,c} x_0 + S_{1,c} x_1, transform along H,
-// keep sampled rows (signs and centering as k_fwd_col).
+// keep sampled rows (signs and centering as k_fwd_col).  Loads address a
+// wave-uniform plane base plus one 32-bit lane offset (lanes past the last
+// column of a ragged tile read column W - 1 and store nothing).
 template <class Sd, int WT>
-__global__ void __launch_bounds__(Sd::T * WT)
+__global__ void __launch_bounds__(Sd::T * WT, 2)
 k_fwd_col_soft(SenseColArgs a) {
   constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
   using L = LdsInterleaved<N, WT>;
   __shared__ float2 lds[L::SIZE];
   __shared__ float2 tw[N];
+  __shared__ float mk[N];
   const int b = a.slices[blockIdx.y];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
@@ -28,38 +31,39 @@ k_fwd_col_soft(SenseColArgs a) {
   if (tile * WT >= W) return;
   const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
   const bool valid = col < W;
-  for (int i = lid; i < N; i += T * WT) tw[i] = a.tw[i];
+  for (int i = lid; i < N; i += T * WT) {
+    tw[i] = a.tw[i];
+    mk[i] = a.mask[d.moff + i];
+  }
   __syncthreads();
   const float scale = rsqrtf((float)N);
   const int64_t plane = (int64_t)N * W;
+  const uint32_t voff = (uint32_t)(tc * W + (valid ? col : W - 1)) * 8u;
+  auto so = [&](int i, int r) { return (uint32_t)((T * i + r * Sd::M1) * W) * 8u; };
+  const uint32_t pbytes = (uint32_t)N * (uint32_t)W * 8u;
   const float2* xin = a.in + 2 * d.xoff;
+  const BufPlane xp0(xin, pbytes), xp1(xin + plane, pbytes);
   float2 x0[P], x1[P];
 #pragma unroll
   for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
     for (int r = 0; r < Sd::N1; ++r) {
-      const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
-      x0[i * Sd::N1 + r] = valid ? xin[o] : make_float2(0.f, 0.f);
-      x1[i * Sd::N1 + r] = valid ? xin[plane + o] : make_float2(0.f, 0.f);
+      x0[i * Sd::N1 + r] = xp0.ld(voff, so(i, r));
+      x1[i * Sd::N1 + r] = xp1.ld(voff, so(i, r));
     }
-  const float* mrow = a.mask + d.moff;
   const float2* Sb = a.S + 2 * d.soff;
   for (int coil = 0; coil < d.C; ++coil) {
-    const float2* S0 = Sb + coil * plane;
-    const float2* S1 = Sb + (d.C + coil) * plane;
+    const BufPlane S0(Sb + coil * plane, pbytes), S1(Sb + (d.C + coil) * plane, pbytes);
     float2 v[P];
 #pragma unroll
     for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
       for (int r = 0; r < Sd::N1; ++r) {
         const int k = i * Sd::N1 + r;
-        const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
-        const float2 s0 = valid ? S0[o] : make_float2(0.f, 0.f);
-        const float2 s1 = valid ? S1[o] : make_float2(0.f, 0.f);
-        v[k] = cadd(cmul(s0, x0[k]), cmul(s1, x1[k]));
+        v[k] = cadd(cmul(S0.ld_nt(voff, so(i, r)), x0[k]), cmul(S1.ld_nt(voff, so(i, r)), x1[k]));
       }
     fft_forward<Sd, L>(v, lds, tw, tc, c);
-    float2* oc = a.out + d.soff + coil * plane;
+    const BufPlane oc(a.out + d.soff + coil * plane, pbytes);
 #pragma unroll
     for (int i = 0; i < Sd::GFIN; ++i)
 #pragma unroll
@@ -67,16 +71,16 @@ k_fwd_col_soft(SenseColArgs a) {
         const int j = Sd::freq(tc, i, r);
         const int k = (j + N / 2) % N;
         const float sg = (j & 1) ? -scale : scale;
-        if (valid && mrow[k] != 0.f) oc[(int64_t)k * W + col] = cscale(v[i * Sd::NFIN + r], sg);
+        if (valid && mk[k] != 0.f) oc.st(cscale(v[i * Sd::NFIN + r], sg), (uint32_t)(k * W + col) * 8u, 0);
       }
   }
 }
 
 // Adjoint column pass: per coil, the sampled rows of the row-pass output in
 // frequency order with the centering sign, inverse transform along H, then
-// x_m += conj(S_{m,c}) v for both sets.
+// x_m += conj(S_{m,c}) v for both sets (addressing as the forward pass).
 template <class Sd, int WT>
-__global__ void __launch_bounds__(Sd::T * WT)
+__global__ void __launch_bounds__(Sd::T * WT, 2)
 k_adj_col_soft(SenseColArgs a) {
   constexpr int N = Sd::N, P = Sd::P, T = Sd::T;
   using L = LdsInterleaved<N, WT>;
@@ -97,12 +101,16 @@ k_adj_col_soft(SenseColArgs a) {
   __syncthreads();
   const float scale = rsqrtf((float)N);
   const int64_t plane = (int64_t)N * W;
+  const int ccol = valid ? col : W - 1;
+  const uint32_t voff = (uint32_t)(tc * W + ccol) * 8u;
+  auto so = [&](int i, int r) { return (uint32_t)((T * i + r * Sd::M1) * W) * 8u; };
+  const uint32_t pbytes = (uint32_t)N * (uint32_t)W * 8u;
   const float2* Sb = a.S + 2 * d.soff;
   float2 acc0[P], acc1[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) acc0[k] = acc1[k] = make_float2(0.f, 0.f);
   for (int coil = 0; coil < d.C; ++coil) {
-    const float2* ic = a.in + d.soff + coil * plane;
+    const BufPlane ic(a.in + d.soff + coil * plane, pbytes);
     float2 v[P];
 #pragma unroll
     for (int i = 0; i < Sd::GFIN; ++i)
@@ -112,34 +120,30 @@ k_adj_col_soft(SenseColArgs a) {
         const int k = (j + N / 2) % N;
         const float sg = (j & 1) ? -scale : scale;
         float2 u = make_float2(0.f, 0.f);
-        if (valid && mk[k] != 0.f) u = cscale(ic[(int64_t)k * W + col], sg);
+        if (mk[k] != 0.f) u = cscale(ic.ld((uint32_t)(k * W + ccol) * 8u, 0), sg);
         v[i * Sd::NFIN + r] = u;
       }
     fft_inverse<Sd, L>(v, lds, tw, tc, c);
-    if (valid) {
-      const float2* S0 = Sb + coil * plane;
-      const float2* S1 = Sb + (d.C + coil) * plane;
+    const BufPlane S0(Sb + coil * plane, pbytes), S1(Sb + (d.C + coil) * plane, pbytes);
 #pragma unroll
-      for (int i = 0; i < Sd::G1; ++i)
+    for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
-        for (int r = 0; r < Sd::N1; ++r) {
-          const int k = i * Sd::N1 + r;
-          const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
-          acc0[k] = cadd(acc0[k], cmulc(S0[o], v[k]));
-          acc1[k] = cadd(acc1[k], cmulc(S1[o], v[k]));
-        }
-    }
+      for (int r = 0; r < Sd::N1; ++r) {
+        const int k = i * Sd::N1 + r;
+        acc0[k] = cadd(acc0[k], cmulc(S0.ld_nt(voff, so(i, r)), v[k]));
+        acc1[k] = cadd(acc1[k], cmulc(S1.ld_nt(voff, so(i, r)), v[k]));
+      }
   }
   if (!valid) return;
-  float2* xo = a.out + 2 * d.xoff;
+  const float2* xo = a.out + 2 * d.xoff;
+  const BufPlane q0(xo, pbytes), q1(xo + plane, pbytes);
 #pragma unroll
   for (int i = 0; i < Sd::G1; ++i)
 #pragma unroll
     for (int r = 0; r < Sd::N1; ++r) {
       const int k = i * Sd::N1 + r;
-      const int64_t o = (int64_t)Sd::a1(tc, i, r) * W + col;
-      xo[o] = acc0[k];
-      xo[plane + o] = acc1[k];
+      q0.st(acc0[k], voff, so(i, r));
+      q1.st(acc1[k], voff, so(i, r));
     }
 }
 
