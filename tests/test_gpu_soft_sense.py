@@ -62,6 +62,44 @@ def test_soft_operators_and_cg(B, H, W, C):
     assert errs["cg"] < CG_TOL and pix["cg"] < 2 * CG_TOL
 
 
+def test_soft_uneven_batch_matches_oracle_per_slice():
+    """Slices of several sizes and coil counts in one soft plan: per size
+    group one launch whose workgroups map to (slice, column tile, coil
+    split); narrower slices of a group leave tiles idle, and the 192^2
+    two-coil slice leaves coil-split workgroups without coils.  Every
+    operator and the CG solve, slice by slice, against the oracle."""
+    from synthetic import soft_slice_inputs
+    shapes = [(320, 320, 15), (192, 192, 10), (320, 256, 6), (48, 40, 3), (192, 192, 2)]
+    sl = [soft_slice_inputs(12000 + i, H, W, C, 4, max(2, min(24, H // 8)))
+          for i, (H, W, C) in enumerate(shapes)]
+    pk = {k: np.concatenate([d[k].ravel() for d in sl]) for k in ("x", "S", "mask")}
+    plan = ops.Plan([q[0] for q in shapes], [q[1] for q in shapes], [q[2] for q in shapes], soft=True)
+    xt, St, mt = dev(pk["x"]), dev(pk["S"]), dev(pk["mask"])
+    lam = np.full(len(shapes), 0.05, dtype=np.float32)
+    y = host(plan.soft_sense_fwd(xt, St, mt))
+    a = host(plan.soft_sense_adj(dev(y), St, mt))
+    q = host(plan.soft_sense_normal(xt, St, mt, torch.tensor(lam)))
+    xs = host(plan.soft_cg_dc(dev(a), St, mt, torch.tensor(lam), 10))
+    xo = so = 0
+    with oracle_threads():
+        for (H, W, C), d in zip(shapes, sl):
+            ni, nc = 2 * H * W, C * H * W
+            x1, S1, m1 = d["x"][None], d["S"][None], d["mask"][None]
+            yref = oss.soft_fwd(x1, S1, m1)
+            aref = oss.soft_adj(y[so:so + nc].reshape(1, C, H, W), S1, m1)
+            qref = oss.soft_normal(x1, S1, m1, 0.05)
+            a1 = a[xo:xo + ni].reshape(1, 2, H, W)
+            xref, _ = oss.soft_cg_dc(a1, None, S1, m1, lam[:1], 10)
+            errs = {"fwd": rel(y[so:so + nc], yref), "adj": rel(a[xo:xo + ni], aref),
+                    "normal": rel(q[xo:xo + ni], qref), "cg": rel(xs[xo:xo + ni], xref)}
+            print(f"soft uneven {H}x{W}x{C}:", {k: f"{v:.1e}" for k, v in errs.items()})
+            for k in ("fwd", "adj", "normal"):
+                assert errs[k] < OP_TOL, k
+            assert errs["cg"] < CG_TOL
+            xo += ni
+            so += nc
+
+
 def test_soft_with_empty_second_set_is_sense():
     """With the second set's maps zero the soft operators give the SENSE
     operators of the first set (different kernels, so to fp32 rounding)."""
