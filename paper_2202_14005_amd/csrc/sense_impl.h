@@ -88,8 +88,16 @@ k_normal(NormalArgs a) {
   __shared__ float sc[2];
 
   const int Lb = blockIdx.x;
-  const int ug = (((Lb >> 4) * 8 + (Lb & 7)) << 1) + ((Lb >> 3) & 1);
-  const int ks = ug % KSPL, tg = ug / KSPL;
+  int ks, tg;
+  if constexpr (KSPL > 1) {
+    // consecutive workgroups go to the 8 XCDs in turn: the KSPL splits of a
+    // tile, 8 workgroups apart, run on one XCD and share p and r in its L2
+    tg = (Lb / (8 * KSPL)) * 8 + (Lb & 7);
+    ks = (Lb >> 3) % KSPL;
+  } else {
+    tg = (((Lb >> 4) * 8 + (Lb & 7)) << 1) + ((Lb >> 3) & 1);
+    ks = 0;
+  }
   const int si = tg / a.tiles, tile = tg % a.tiles;
   if (si >= a.nslices) return;
   const int b = a.slices[si];
@@ -714,8 +722,8 @@ hipError_t launch_normal(const NormalArgs& a0, int maxW, hipStream_t s) {
   if ((a.mode == 1 || a.split_plain) && KSPL > 1) {
     if (a.mode == 1 && (a.tiles * KSPL > a.npq || (a.iter > 0 && a.pin == a.pout))) return hipErrorInvalidValue;
     if (a.qstride <= 0) return hipErrorInvalidValue;
-    const int total = a.tiles * a.nslices * KSPL;
-    dim3 grid((unsigned)(((total + 15) / 16) * 16));
+    const int total = a.tiles * a.nslices * KSPL, per = 8 * KSPL;
+    dim3 grid((unsigned)(((total + per - 1) / per) * per));
     hipLaunchKernelGGL((k_normal<Sd, WT, G, KS, KSPL>), grid, dim3(Sd::T * WT * G), 0, s, a);
   } else {
     const int total = a.tiles * a.nslices;
