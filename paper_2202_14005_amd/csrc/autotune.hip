@@ -28,10 +28,20 @@ extern "C" mrx_status mrx_plan_autotune(mrx_plan p, const float* S, const float*
     return fail(MRX_EHIP, "autotune: event create");
   // plans for the variational network use the plain operator, the others CG
   const bool use_cg = p->ws != nullptr && !(p->flags & MRX_PLAN_VN);
+  // With several size groups running concurrently, coil-split schedules on
+  // 8-column tiles (half a 128-byte row segment; the pairs of workgroups
+  // that share a segment are not guaranteed to run together) are left out
+  // where the length has a 16-column split: timed in four CG iterations they
+  // can come out ahead, yet the 64-slice batch's reconstruction graph ran
+  // 11% slower with one (384 x 320) than with the 16-column split.
+  const bool several = p->groups.size() > 1;
   for (auto& g : p->groups) {
     const ColVariant* best = g.col;
     float best_ms = 1e30f;
+    bool wide_split = false;
+    for (const ColVariant* v : col_variants(g.H)) wide_split = wide_split || (v->kspl > 1 && v->WT >= 16);
     for (const ColVariant* v : col_variants(g.H)) {
+      if (several && wide_split && v->kspl > 1 && v->WT < 16) continue;
       g.col = v;
       if (refresh_desc(p, true) != MRX_OK) continue;
       auto run = [&]() -> bool {

@@ -92,8 +92,12 @@ k_normal(NormalArgs a) {
   if constexpr (KSPL > 1) {
     // consecutive workgroups go to the 8 XCDs in turn: the KSPL splits of a
     // tile, 8 workgroups apart, run on one XCD and share p and r in its L2
-    tg = (Lb / (8 * KSPL)) * 8 + (Lb & 7);
-    ks = (Lb >> 3) % KSPL;
+    // -- with tiles narrower than a 128-byte row segment, the splits of the
+    // RUN adjacent tiles that share each segment
+    constexpr int RUN = WT * 8 >= 128 ? 1 : 128 / (WT * 8), PER = 8 * RUN * KSPL;
+    const int w = (Lb >> 3) % (RUN * KSPL);
+    tg = RUN * ((Lb / PER) * 8 + (Lb & 7)) + w / KSPL;
+    ks = w % KSPL;
   } else {
     tg = (((Lb >> 4) * 8 + (Lb & 7)) << 1) + ((Lb >> 3) & 1);
     ks = 0;
@@ -722,7 +726,7 @@ hipError_t launch_normal(const NormalArgs& a0, int maxW, hipStream_t s) {
   if ((a.mode == 1 || a.split_plain) && KSPL > 1) {
     if (a.mode == 1 && (a.tiles * KSPL > a.npq || (a.iter > 0 && a.pin == a.pout))) return hipErrorInvalidValue;
     if (a.qstride <= 0) return hipErrorInvalidValue;
-    const int total = a.tiles * a.nslices * KSPL, per = 8 * KSPL;
+    const int total = a.tiles * a.nslices * KSPL, per = 8 * (WT * 8 >= 128 ? 1 : 128 / (WT * 8)) * KSPL;
     dim3 grid((unsigned)(((total + per - 1) / per) * per));
     hipLaunchKernelGGL((k_normal<Sd, WT, G, KS, KSPL>), grid, dim3(Sd::T * WT * G), 0, s, a);
   } else {
