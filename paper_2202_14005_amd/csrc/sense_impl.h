@@ -36,6 +36,18 @@ struct BufPlane {
   }
 };
 
+// Column-pass workgroup -> (slice, column tile) unit of a 1-D grid padded
+// to 16 workgroups.  Tiles narrower than a 128-byte row segment pair up: the
+// two tiles of a segment are 8 workgroups apart, so they run on one XCD (the
+// chip deals consecutive workgroups to the 8 XCDs in turn) and read each
+// segment through one L2.
+template <int WT>
+__device__ __forceinline__ int col_pass_unit(int Lb) {
+  if constexpr (WT * 8 >= 128) return Lb;
+  else return (((Lb >> 4) * 8 + (Lb & 7)) << 1) + ((Lb >> 3) & 1);
+}
+inline dim3 col_pass_grid(int tiles, int nslices) { return dim3((unsigned)(((tiles * nslices + 15) / 16) * 16)); }
+
 // Deterministic fixed-order sum of n floats by one wavefront: lane l adds
 // elements l, l+64, ... in order, then a fixed butterfly over lanes.
 __device__ __forceinline__ float wave_sum_fixed(const float* a, int n, int lane) {
@@ -486,10 +498,12 @@ k_fwd_col(SenseColArgs a) {
   using L = LdsInterleaved<N, WT>;
   __shared__ float2 lds[L::SIZE];
   __shared__ float2 tw[N];
-  const int b = a.slices[blockIdx.y];
+  const int unit = col_pass_unit<WT>(blockIdx.x), si = unit / a.tiles, tile = unit % a.tiles;
+  if (si >= a.nslices) return;
+  const int b = a.slices[si];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
-  const int W = d.W, tile = blockIdx.x;
+  const int W = d.W;
   if (tile * WT >= W) return;
   const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
   const bool valid = col < W;
@@ -543,10 +557,12 @@ k_adj_col(SenseColArgs a) {
   __shared__ float2 lds[G * L::SIZE];
   __shared__ float2 tw[N];
   __shared__ float mk[N];
-  const int b = a.slices[blockIdx.y];
+  const int unit = col_pass_unit<WT>(blockIdx.x), si = unit / a.tiles, tile = unit % a.tiles;
+  if (si >= a.nslices) return;
+  const int b = a.slices[si];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
-  const int W = d.W, tile = blockIdx.x;
+  const int W = d.W;
   if (tile * WT >= W) return;
   const int lid = threadIdx.x, grp = lid / NT, l2 = lid % NT;
   const int c = l2 % WT, tc = l2 / WT, col = tile * WT + c;
@@ -748,8 +764,9 @@ hipError_t launch_normal_wl(const NormalArgs& a0, int maxW, hipStream_t s) {
 }
 template <class Sd, int WT>
 hipError_t launch_fwd_col(const SenseColArgs& a, int maxW, hipStream_t s) {
-  dim3 grid((maxW + WT - 1) / WT, a.nslices);
-  hipLaunchKernelGGL((k_fwd_col<Sd, WT>), grid, dim3(Sd::T * WT), 0, s, a);
+  SenseColArgs c = a;
+  c.tiles = (maxW + WT - 1) / WT;
+  hipLaunchKernelGGL((k_fwd_col<Sd, WT>), col_pass_grid(c.tiles, c.nslices), dim3(Sd::T * WT), 0, s, c);
   return hipGetLastError();
 }
 // The adjoint column pass uses its own tile: 8 columns, two coil groups.
@@ -757,8 +774,10 @@ constexpr int ADJ_WT = 8, ADJ_G = 2;
 template <class Sd, int WT>
 hipError_t launch_adj_col(const SenseColArgs& a, int maxW, hipStream_t s) {
   (void)WT;
-  dim3 grid((maxW + ADJ_WT - 1) / ADJ_WT, a.nslices);
-  hipLaunchKernelGGL((k_adj_col<Sd, ADJ_WT, ADJ_G>), grid, dim3(Sd::T * ADJ_WT * ADJ_G), 0, s, a);
+  SenseColArgs c = a;
+  c.tiles = (maxW + ADJ_WT - 1) / ADJ_WT;
+  hipLaunchKernelGGL((k_adj_col<Sd, ADJ_WT, ADJ_G>), col_pass_grid(c.tiles, c.nslices), dim3(Sd::T * ADJ_WT * ADJ_G), 0,
+                     s, c);
   return hipGetLastError();
 }
 template <class Sd, int WT>

@@ -53,6 +53,7 @@ struct SenseColArgs {
   const float2* in;        // fwd: image x; adj: row-pass output (coil sized)
   float2* out;             // fwd: coil-sized k-space rows; adj: image
   const float2* tw;
+  int tiles;               // column tiles per slice (set by the launcher)
 };
 
 struct SenseRowArgs {

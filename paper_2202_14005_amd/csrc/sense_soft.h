@@ -24,10 +24,12 @@ k_fwd_col_soft(SenseColArgs a) {
   __shared__ float2 lds[L::SIZE];
   __shared__ float2 tw[N];
   __shared__ float mk[N];
-  const int b = a.slices[blockIdx.y];
+  const int unit = col_pass_unit<WT>(blockIdx.x), si = unit / a.tiles, tile = unit % a.tiles;
+  if (si >= a.nslices) return;
+  const int b = a.slices[si];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
-  const int W = d.W, tile = blockIdx.x;
+  const int W = d.W;
   if (tile * WT >= W) return;
   const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
   const bool valid = col < W;
@@ -87,10 +89,12 @@ k_adj_col_soft(SenseColArgs a) {
   __shared__ float2 lds[L::SIZE];
   __shared__ float2 tw[N];
   __shared__ float mk[N];
-  const int b = a.slices[blockIdx.y];
+  const int unit = col_pass_unit<WT>(blockIdx.x), si = unit / a.tiles, tile = unit % a.tiles;
+  if (si >= a.nslices) return;
+  const int b = a.slices[si];
   const SliceDesc d = a.desc[b];
   if (d.H != N) return;
-  const int W = d.W, tile = blockIdx.x;
+  const int W = d.W;
   if (tile * WT >= W) return;
   const int lid = threadIdx.x, c = lid % WT, tc = lid / WT, col = tile * WT + c;
   const bool valid = col < W;
@@ -274,12 +278,16 @@ hipError_t launch_normal_soft(const NormalArgs& a0, int maxW, hipStream_t s) {
 }
 template <class Sd, int WT>
 hipError_t launch_fwd_col_soft(const SenseColArgs& a, int maxW, hipStream_t s) {
-  hipLaunchKernelGGL((k_fwd_col_soft<Sd, WT>), dim3((maxW + WT - 1) / WT, a.nslices), dim3(Sd::T * WT), 0, s, a);
+  SenseColArgs c = a;
+  c.tiles = (maxW + WT - 1) / WT;
+  hipLaunchKernelGGL((k_fwd_col_soft<Sd, WT>), col_pass_grid(c.tiles, c.nslices), dim3(Sd::T * WT), 0, s, c);
   return hipGetLastError();
 }
 template <class Sd, int WT>
 hipError_t launch_adj_col_soft(const SenseColArgs& a, int maxW, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_col_soft<Sd, WT>), dim3((maxW + WT - 1) / WT, a.nslices), dim3(Sd::T * WT), 0, s, a);
+  SenseColArgs c = a;
+  c.tiles = (maxW + WT - 1) / WT;
+  hipLaunchKernelGGL((k_adj_col_soft<Sd, WT>), col_pass_grid(c.tiles, c.nslices), dim3(Sd::T * WT), 0, s, c);
   return hipGetLastError();
 }
 
