@@ -169,17 +169,25 @@ __global__ void __launch_bounds__(CG_THREADS) k_cg_form_p(CgElemArgs a) {
   const int b = a.slices[blockIdx.y];
   const SliceDesc d = a.desc[b];
   const int64_t n = (int64_t)d.H * d.W;
-  const float rc = psum(a.rr_cur + (int64_t)b * a.nrr, a.nrr);
-  const float rp = psum(a.rr_next + (int64_t)b * a.nrr, a.nrr);
-  if (a.stopped[b]) return;
-  const float beta = rp > 0.f ? rc / rp : 0.f;
   const int64_t base = (int64_t)blockIdx.x * CG_EPB;
-  for (int k = threadIdx.x; k < CG_EPB; k += CG_THREADS) {
-    const int64_t i = base + k;
-    if (i >= n) break;
-    const int64_t o = d.xoff + i;
-    const float2 rv = a.r[o], pv = a.p[o];
-    a.x[o] = make_float2(rv.x + beta * pv.x, rv.y + beta * pv.y);
+  // the thread's loads first, then both rho sums in one pass (their memory
+  // latency overlaps the reductions, as in k_cg_update)
+  constexpr int PER = CG_EPB / CG_THREADS;
+  float2 rv[PER], pv[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = base + threadIdx.x + j * CG_THREADS;
+    const int64_t o = d.xoff + (i < n ? i : 0);
+    rv[j] = a.r[o];
+    pv[j] = a.p[o];
+  }
+  const float2 rr = psum2(a.rr_cur + (int64_t)b * a.nrr, a.nrr, a.rr_next + (int64_t)b * a.nrr, a.nrr);
+  if (a.stopped[b]) return;
+  const float beta = rr.y > 0.f ? rr.x / rr.y : 0.f;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = base + threadIdx.x + j * CG_THREADS;
+    if (i < n) a.x[d.xoff + i] = make_float2(rv[j].x + beta * pv[j].x, rv[j].y + beta * pv[j].y);
   }
 }
 
